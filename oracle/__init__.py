@@ -1,0 +1,209 @@
+"""FP64 CPU oracle of the Nyx comoving gas step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It is a ctypes wrapper around
+``oracle/nyx_oracle.c`` (plain C, built with ``-O2 -ffp-contract=off``) and
+shares no code with the HIP library in ``paper_1301_4498_amd``.
+
+What it computes is stated in ``nyx_oracle.c``: the unsplit PPM Godunov step
+of Sec. 3.2 (Gas Dynamics) with the Step 2 predictor and Step 6 corrector and
+dual-energy sync of Sec. 3.6, and the hydro CFL of Sec. 3.5.
+
+Array convention: a field of ``ncomp`` components on a box of valid extent
+(nx, ny, nz) with ``ng`` ghost cells is a C-contiguous float64 array of shape
+``(ncomp, nz + 2 ng, ny + 2 ng, nx + 2 ng)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libnyxoracle.so")
+_SRC = os.path.join(_HERE, "nyx_oracle.c")
+_MLP_SRC = os.path.join(_HERE, "mlp_oracle.c")
+
+# Compiler line: plain IEEE FP64, no contraction, no fast-math.
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc; returns its path."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    srcs = [_SRC] + ([_MLP_SRC] if os.path.exists(_MLP_SRC) else [])
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc"] + CFLAGS + ["-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("small_dens", ctypes.c_double),
+        ("small_pres", ctypes.c_double),
+        ("riemann_tol", ctypes.c_double),
+        ("riemann_maxiter", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "nonfinite", "neg_dens", "neg_eint", "floor_hits", "trans_reverts",
+        "sync_E_from_e", "riemann_iters", "riemann_calls")]
+
+
+STATS_FIELDS = [f[0] for f in _Stats._fields_]
+
+
+@dataclass
+class Params:
+    """Method parameters (Sec. 2.2: gamma = 5/3; Sec. 3.6 Step 6: eta = 1e-4)."""
+    gamma: float = 5.0 / 3.0
+    eta: float = 1e-4
+    small_dens: float = 1e-20
+    small_pres: float = 1e-20
+    riemann_tol: float = 1e-14
+    riemann_maxiter: int = 20
+
+    def c(self) -> _Params:
+        return _Params(self.gamma, self.eta, self.small_dens, self.small_pres,
+                       self.riemann_tol, int(self.riemann_maxiter), 0)
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER(_Params)
+        i = ctypes.c_int
+        d = ctypes.c_double
+        L.nyxo_estimate_dt.argtypes = [P, i, i, i, i, _D, d, d, d, _D]
+        L.nyxo_estimate_dt.restype = i
+        L.nyxo_hydro_step.argtypes = [P, i, i, i, i, _D, _D, d, d, d, d, _D,
+                                      ctypes.POINTER(_Stats)]
+        L.nyxo_hydro_step.restype = i
+        L.nyxo_riemann.argtypes = [P, _D, _D, _D, _D, ctypes.POINTER(ctypes.c_int)]
+        L.nyxo_riemann.restype = None
+        L.nyxo_ppm_line.argtypes = [i, _D, _D, _D, _D]
+        L.nyxo_ppm_line.restype = None
+        L.nyxo_ppm_interface.argtypes = [_D]
+        L.nyxo_ppm_interface.restype = d
+        L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
+        L.nyxo_flatten_line.restype = None
+        L.nyxo_trace_cell.argtypes = [P, i, _D, d, _D, _D, _D, d, d, d, d, _D, _D]
+        L.nyxo_trace_cell.restype = i
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _dims(state: np.ndarray, ng: int):
+    _, pz, py, px = state.shape
+    return px - 2 * ng, py - 2 * ng, pz - 2 * ng
+
+
+def estimate_dt(state: np.ndarray, ng: int, a: float, dx: float, cfl: float,
+                params: Params | None = None) -> float:
+    """Hydro CFL time step of Sec. 3.5 over the valid cells of one box."""
+    params = params or Params()
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    nx, ny, nz = _dims(state, ng)
+    out = ctypes.c_double(0.0)
+    rc = lib().nyxo_estimate_dt(ctypes.byref(params.c()), nx, ny, nz, ng,
+                                _ptr(state), a, dx, cfl, ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("nyxo_estimate_dt: bad arguments")
+    return out.value
+
+
+def hydro_step(state: np.ndarray, grav: np.ndarray, ng: int, dt: float,
+               dx: float, a_old: float, a_new: float,
+               params: Params | None = None):
+    """One gas step.  Returns (new_state, stats dict).  Ghost cells of the
+    returned array are copies of the input's (stale); refill before reuse."""
+    params = params or Params()
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    grav = np.ascontiguousarray(grav, dtype=np.float64)
+    assert state.shape[0] == 6 and grav.shape == (3,) + state.shape[1:]
+    nx, ny, nz = _dims(state, ng)
+    out = state.copy()
+    st = _Stats()
+    rc = lib().nyxo_hydro_step(ctypes.byref(params.c()), nx, ny, nz, ng,
+                               _ptr(state), _ptr(grav), dt, dx, a_old, a_new,
+                               _ptr(out), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("nyxo_hydro_step: bad arguments")
+    return out, {k: int(getattr(st, k)) for k in STATS_FIELDS}
+
+
+def riemann(qL, qR, params: Params | None = None):
+    """Two-shock solve on rotated states (rho, u_n, u_t1, u_t2, p).
+    Returns (godunov_state[5], {p, u, rhoL, rhoR}, iterations)."""
+    params = params or Params()
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    qg = np.zeros(5)
+    star = np.zeros(4)
+    it = ctypes.c_int(0)
+    lib().nyxo_riemann(ctypes.byref(params.c()), _ptr(qL), _ptr(qR), _ptr(qg),
+                       _ptr(star), ctypes.byref(it))
+    return qg, dict(p=star[0], u=star[1], rhoL=star[2], rhoR=star[3]), it.value
+
+
+def ppm_interface(q4) -> float:
+    q4 = np.ascontiguousarray(q4, dtype=np.float64)
+    return lib().nyxo_ppm_interface(_ptr(q4))
+
+
+def ppm_line(q, chi=None):
+    """Edge values (qm, qp) for cells 2..m-3 of a line; NaN elsewhere."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    m = q.shape[0]
+    chi = np.ones(m) if chi is None else np.ascontiguousarray(chi, dtype=np.float64)
+    qm = np.full(m, np.nan)
+    qp = np.full(m, np.nan)
+    lib().nyxo_ppm_line(m, _ptr(q), _ptr(chi), _ptr(qm), _ptr(qp))
+    return qm, qp
+
+
+def flatten_line(p, u, params: Params | None = None):
+    """Directional flattening coefficient for cells 3..m-4; NaN elsewhere."""
+    params = params or Params()
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    chi = np.full(p.shape[0], np.nan)
+    lib().nyxo_flatten_line(ctypes.byref(params.c()), p.shape[0], _ptr(p), _ptr(u),
+                            _ptr(chi))
+    return chi
+
+
+def trace_cell(d, qc, cc, qm, qp, g, kh, hdt_a=0.0, hda_a=0.0, pexp=0.0,
+               params: Params | None = None):
+    """Traced (left-face, right-face) lab-frame states of one cell."""
+    params = params or Params()
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (qc, qm, qp, g)]
+    lo = np.zeros(5)
+    hi = np.zeros(5)
+    lib().nyxo_trace_cell(ctypes.byref(params.c()), d, _ptr(arr[0]), cc,
+                          _ptr(arr[1]), _ptr(arr[2]), _ptr(arr[3]), kh, hdt_a,
+                          hda_a, pexp, _ptr(lo), _ptr(hi))
+    return lo, hi

@@ -1,0 +1,102 @@
+/*
+ * nyx_oracle.h -- plain, slow FP64 CPU oracle of the comoving unsplit PPM
+ * Godunov gas step (Almgren et al., "Nyx", Sec. 3.2 Gas Dynamics, Sec. 3.5
+ * Computing the time step, Sec. 3.6 Single-Level Integration Algorithm,
+ * Steps 2 and 6).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can compare the HIP path
+ * against an obviously correct implementation.  It shares no code, header,
+ * table or constant with the HIP library and must never be linked into or
+ * called from the product path.
+ *
+ * Layout of every 3-D field: a box of n = (nx, ny, nz) valid cells surrounded
+ * by ng ghost cells on each side; component-major, x fastest:
+ *   idx(c, k, j, i) = ((c*(nz+2ng) + k+ng)*(ny+2ng) + j+ng)*(nx+2ng) + i+ng
+ * for i in [-ng, nx+ng), etc.  State components (Sec. 3.2):
+ *   0: rho, 1..3: a*rho*U_{x,y,z}, 4: a^2*rho*E, 5: a^2*rho*e.
+ * Gravity: 3 components g_{x,y,z} in the same padded layout.
+ * All arrays are host memory owned by the caller.
+ */
+#ifndef NYX_ORACLE_H
+#define NYX_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double gamma;        /* gamma-law EOS exponent (Sec. 2.2: 5/3) */
+  double eta;          /* dual-energy threshold (Sec. 3.6, Step 6: 1e-4) */
+  double small_dens;   /* density floor, primitives and edge states only */
+  double small_pres;   /* pressure floor, primitives, edge states, Riemann */
+  double riemann_tol;  /* relative stopping tolerance of the two-shock iteration */
+  int32_t riemann_maxiter;
+  int32_t pad_;
+} nyxo_params;
+
+typedef struct {
+  int64_t nonfinite;      /* valid output cells with a non-finite component */
+  int64_t neg_dens;       /* valid output cells with rho <= 0 */
+  int64_t neg_eint;       /* valid output cells with a^2 rho e <= 0 */
+  int64_t floor_hits;     /* individual floor applications (O1, O4) */
+  int64_t trans_reverts;  /* transverse corrections rejected (O7) */
+  int64_t sync_E_from_e;  /* cells where E was rebuilt from e (Step 6) */
+  int64_t riemann_iters;  /* total two-shock iterations */
+  int64_t riemann_calls;  /* total Riemann solves */
+} nyxo_stats;
+
+/* Hydro CFL (Sec. 3.5): dt = cfl * a * dx / max_{cells,d}(|U_d| + c).
+ * Returns 0, or -1 on bad arguments. */
+int nyxo_estimate_dt(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                     const double* state, double a, double dx, double cfl,
+                     double* dt_out);
+
+/* One gas step (Sec. 3.6, Step 2 predictor with S_g^n and S_e, then the Step 6
+ * gravity corrector with the same g and the dual-energy sync).  Input state is
+ * scaled with a_old, output with a_new.  Only valid cells of state_out are
+ * written.  Returns 0, or -1 on bad arguments / allocation failure. */
+int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                    const double* state_in, const double* grav, double dt,
+                    double dx, double a_old, double a_new, double* state_out,
+                    nyxo_stats* stats);
+
+/* ---- unit-level entry points used by the oracle's own pins ---- */
+
+/* Two-shock Riemann solve on rotated primitive states (rho, u_n, u_t1, u_t2, p).
+ * qg: Godunov state at xi = 0 in the same order.
+ * star: {p*, u*, rho*_L, rho*_R}.  *iters: iterations taken. */
+void nyxo_riemann(const nyxo_params* prm, const double* qL, const double* qR,
+                  double* qg, double* star, int* iters);
+
+/* PPM on a line of m cells: for j in [2, m-3], writes the flattened and
+ * monotonized edge values qm[j] (at j-1/2) and qp[j] (at j+1/2); chi[j] is the
+ * flattening coefficient of cell j.  Other entries are left untouched. */
+void nyxo_ppm_line(int m, const double* q, const double* chi, double* qm,
+                   double* qp);
+
+/* Unflattened fourth-order interface value between cells j and j+1 from
+ * q[j-1..j+2] with van Leer-limited slopes (q points at q[j-1]). */
+double nyxo_ppm_interface(const double* q4);
+
+/* Directional flattening coefficient chi_d on a line of m cells for
+ * j in [3, m-4]; others untouched. */
+void nyxo_flatten_line(const nyxo_params* prm, int m, const double* p,
+                       const double* u, double* chi);
+
+/* Characteristic tracing of one cell in direction d (0, 1, 2).
+ * qc: cell primitives (rho, ux, uy, uz, p); cc: sound speed;
+ * qmv, qpv: PPM edge values (5 each, already flattened/monotonized);
+ * g: cell gravity (3); kh = dt/(a_h dx); hdt_a = (dt/2)/a_h;
+ * hda_a = (da/2)/a_h; pexp = 1.5(gamma-1) da/a_h.
+ * Outputs lab-frame edge states: lo = left-face state (R input of face j-1/2),
+ * hi = right-face state (L input of face j+1/2).  Returns floors applied. */
+int nyxo_trace_cell(const nyxo_params* prm, int d, const double* qc, double cc,
+                    const double* qmv, const double* qpv, const double* g,
+                    double kh, double hdt_a, double hda_a, double pexp,
+                    double* lo, double* hi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
