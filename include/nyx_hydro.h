@@ -1,0 +1,191 @@
+/*
+ * nyx_hydro.h -- C ABI of the MI355X (gfx950) comoving gas step.
+ *
+ * The library advances the gas state of Nyx (Almgren et al.) by one time step
+ * on ghost-filled boxes: the unsplit PPM Godunov method with characteristic
+ * tracing and full corner coupling, the iterative two-shock Riemann solver,
+ * the conservative update with the expansion-factor and gravity sources, the
+ * gravity corrector and the dual-energy sync (Sec. 3.2 Gas Dynamics, Sec. 3.6
+ * Single-Level Integration Algorithm, Steps 2 and 6), and the hydro CFL time
+ * step (Sec. 3.5).
+ *
+ * Conventions shared by every entry point
+ *  - State U (Sec. 3.2): 6 components (rho, a rho U_x, a rho U_y, a rho U_z,
+ *    a^2 rho E, a^2 rho e), FP64.  Gravity g: 3 components, FP64 in
+ *    NYX_FP64 mode, FP32 in NYX_MIXED mode.
+ *  - Box layout: n = (nx, ny, nz) valid cells (each even and >= 2; Sec. 4.1
+ *    asks for an even number of cells per direction), ng >= 4 ghost cells on
+ *    every side, component-major with x fastest:
+ *      element (c, k, j, i) at off + c*comp_stride
+ *                            + ((k+ng)*(ny+2ng) + (j+ng))*(nx+2ng) + (i+ng)
+ *    for i in [-ng, nx+ng) and likewise j, k; comp_stride >= the padded cell
+ *    count.  dx is the comoving cell size, the same on every axis (Sec. 4.1).
+ *  - Memory: every pointer marked (device) is device memory owned by the
+ *    caller; the library never allocates or frees device memory.  Workspace
+ *    sizes are queried first and passed in.  Host pointers are read during
+ *    the call only.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *    only enqueue work; nothing synchronises the host.
+ *  - Errors: argument errors return a negative nyx_status before anything is
+ *    enqueued.  Conditions met on the device (non-finite values, rho <= 0,
+ *    floors, rejected transverse corrections, learned-flux fallbacks) are only
+ *    counted in an optional device nyx_stats block; values are never clamped
+ *    silently.  No C++ exception crosses this interface.
+ *  - The input state is U^n scaled with a_old, the output U^{n+1} scaled with
+ *    a_new (Sec. 3.2); only valid cells of the output are written, so the
+ *    caller refills its ghost cells before the next step.  Input and output
+ *    must not overlap.
+ */
+#ifndef NYX_HYDRO_H
+#define NYX_HYDRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NYX_OK = 0,
+  NYX_E_NULL = -1,        /* a required pointer is NULL */
+  NYX_E_SHAPE = -2,       /* box extents, ghost width or strides invalid */
+  NYX_E_PARAM = -3,       /* dt, a, dx, cfl, gamma or an enum out of range */
+  NYX_E_ALIAS = -4,       /* input and output state overlap */
+  NYX_E_HIP = -5,         /* a HIP launch or runtime call failed */
+  NYX_E_UNSUPPORTED = -6, /* combination not built into this library */
+  NYX_E_WORKSPACE = -7    /* workspace too small or misaligned */
+} nyx_status;
+
+typedef enum { NYX_FP64 = 0, NYX_MIXED = 1 } nyx_precision;
+typedef enum { NYX_RIEMANN_TWOSHOCK = 0, NYX_RIEMANN_LEARNED = 1 } nyx_riemann;
+
+typedef struct {
+  double gamma;          /* gamma-law exponent, > 1 (Sec. 2.2: 5/3) */
+  double eta_dual;       /* dual-energy threshold (Sec. 3.6 Step 6: 1e-4) */
+  double small_dens;     /* density floor of primitives and edge states */
+  double small_pres;     /* pressure floor of primitives, edge states, Riemann */
+  double riemann_tol;    /* relative stopping tolerance of the two-shock iteration */
+  double mlp_resid_tol;  /* learned flux: accepted two-shock residual (tau_r) */
+  double cfl;            /* hydro CFL factor used for dt_next (Sec. 3.5) */
+  int32_t riemann_maxiter;     /* 1..64 */
+  int32_t precision;           /* nyx_precision */
+  int32_t riemann;             /* nyx_riemann */
+  int32_t learned_stages_mask; /* bit s set: stage s (0, 1, 2) uses the MLP */
+  const void* mlp_weights;     /* (device) packed learned-flux weights, or NULL */
+} nyx_params;
+
+typedef struct {
+  int32_t n[3];          /* valid cells per axis */
+  int32_t ng;            /* ghost cells per side, >= 4 */
+  int64_t state_off;     /* element offset of (c=0, k=-ng, j=-ng, i=-ng) */
+  int64_t grav_off;      /* same for the gravity buffer */
+  int64_t comp_stride;   /* elements between state components */
+  int64_t grav_stride;   /* elements between gravity components */
+  double dx;             /* comoving cell size */
+} nyx_box;
+
+/* Device counters, accumulated with atomics; zero them before a step. */
+typedef struct {
+  unsigned long long nonfinite, neg_dens, neg_eint, floor_hits, trans_reverts,
+      sync_E_from_e, riemann_iters, riemann_calls, mlp_used, mlp_fallback;
+} nyx_stats;
+
+/* Default parameters: gamma 5/3, eta 1e-4, floors 1e-20, tol 1e-14, 20
+ * iterations, cfl 0.5, FP64, two-shock solver. */
+void nyx_default_params(nyx_params* p);
+
+/* Human-readable text of a status code (static storage). */
+const char* nyx_status_string(int status);
+
+/* Bytes of workspace nyx_hydro_step needs for this box and precision. */
+int nyx_workspace_bytes(const nyx_params* p, const nyx_box* box, size_t* bytes);
+
+/* Hydro CFL time step of one box (Sec. 3.5):
+ *   dt = cfl * a * dx / max over valid cells and axes of (|U_d| + c),
+ * with U_d = (a rho U_d)/(a rho) and c from the internal-energy slot.
+ * state (device, FP64); dt_out (device, one double).  The maximum is exact,
+ * so the result does not depend on the reduction order.  Uses `workspace`
+ * (>= 16 bytes, device) for the running maximum. */
+int nyx_estimate_dt(const nyx_params* p, const nyx_box* box, const double* state,
+                    double a, double cfl, double* dt_out, void* workspace,
+                    size_t ws_bytes, void* stream);
+
+/* One gas step of one box (Sec. 3.6 Steps 2 and 6).
+ * state_in, state_out (device, FP64, same layout, not overlapping); grav
+ * (device, FP64 or FP32 per p->precision); dt > 0 and a_old, a_new > 0 are
+ * host values.  dt_next (device, one double, or NULL): CFL time step of the
+ * new state at a_new with p->cfl.  stats (device or NULL).  workspace
+ * (device, 256-byte aligned) of at least nyx_workspace_bytes. */
+int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_in,
+                   const void* grav, double dt, double a_old, double a_new,
+                   double* state_out, double* dt_next, nyx_stats* stats,
+                   void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------- batched boxes (one AMR level) ----------------
+ * A plan describes a list of boxes living in shared state / gravity buffers
+ * (each box at its own offsets).  The plan is host memory created once per
+ * box layout; its device tables live in the caller's workspace.  Boxes are
+ * advanced together: every stage runs as one launch over all boxes of a
+ * group, groups being sized to fit the workspace.  dt is read per box from
+ * device memory, so a captured HIP graph can be replayed step after step. */
+typedef struct nyx_batch nyx_batch;
+
+/* Minimum workspace (all boxes in groups of one) and the size that holds all
+ * boxes in a single group. */
+int nyx_batch_workspace_bytes(const nyx_params* p, int nbox, const nyx_box* boxes,
+                              size_t* min_bytes, size_t* single_group_bytes);
+
+/* Build a plan; uploads its tables into `workspace` on `stream` (the host
+ * array is copied before return).  *out is freed with nyx_batch_destroy. */
+int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes,
+                     void* workspace, size_t ws_bytes, void* stream, nyx_batch** out);
+int nyx_batch_destroy(nyx_batch* plan);
+int nyx_batch_num_groups(const nyx_batch* plan);
+
+/* Per-box CFL time steps into dt (device, nbox doubles). */
+int nyx_batch_estimate_dt(nyx_batch* plan, const double* state, double a, double cfl,
+                          double* dt, void* stream);
+
+/* Replace every entry of dt (device, nbox doubles) by their minimum: one level
+ * time step for all boxes. */
+int nyx_batch_min_dt(nyx_batch* plan, double* dt, void* stream);
+
+/* One step of every box: dt (device, nbox doubles); dt_next (device, nbox
+ * doubles, or NULL) receives each box's CFL step of the new state. */
+int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* grav,
+                           const double* dt, double a_old, double a_new,
+                           double* state_out, double* dt_next, nyx_stats* stats,
+                           void* stream);
+
+/* ---------------- ghost fills (outside the step) ---------------- */
+/* Periodic ghost cells of one box from its own valid cells (the box is its
+ * own periodic domain).  state (device), ncomp components at box->state_off
+ * with box->comp_stride. */
+int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void* stream);
+
+/* Ghost fill of every box of a plan (6 state components):
+ *   mode 0: each box is its own periodic domain;
+ *   mode 1: the boxes tile a periodic domain as a gx*gy*gz grid of equal
+ *           boxes, box b = (bz*gy + by)*gx + bx, and ghosts are copied from
+ *           the neighbouring boxes' valid cells (the same-level ghost fill of
+ *           Sec. 4.1 for one uniform level). */
+int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
+                          void* stream);
+
+/* ---------------- stage timing (profiling aid, off by default) ----------------
+ * When enabled, every step records HIP events around each of its
+ * NYX_NSTAGES stage launches on the step's own stream, in this order:
+ * primitives, flattening, PPM + tracing, stage-0 Riemann, stage-1 transverse
+ * Riemann, stage-2 final Riemann, update.  nyx_profile_read waits for the
+ * recorded events and returns the milliseconds accumulated per stage (ms[7])
+ * and the number of timed stage sequences since the last reset.  Do not enable
+ * it while a stream is being captured into a HIP graph. */
+#define NYX_NSTAGES 7
+int nyx_profile_enable(int on);
+int nyx_profile_read(double* ms, long long* sequences, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,150 @@
+"""MI355X-native comoving PPM gas step of Nyx (Almgren et al.).
+
+Python binding of the C ABI in include/nyx_hydro.h.  Functions carry the C
+names without the ``nyx_`` prefix and only marshal arguments: tensors are
+passed by device pointer and the stream defaults to torch's current stream.
+PyTorch is used only for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (NYX_FP64, NYX_MIXED, NYX_RIEMANN_LEARNED, NYX_RIEMANN_TWOSHOCK, STATS_FIELDS,
+                   Box, NyxError, Params, Stats, check, lib)
+
+__all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
+           "NYX_RIEMANN_LEARNED", "default_params", "make_box", "workspace_bytes", "estimate_dt",
+           "hydro_step", "fill_ghosts_periodic", "Batch", "stats_dict"]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().nyx_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def make_box(n, ng: int = 4, dx: float = 1.0, state_off: int = 0, grav_off: int = 0,
+             comp_stride: int | None = None, grav_stride: int | None = None) -> Box:
+    nx, ny, nz = (int(x) for x in n)
+    P = (nx + 2 * ng) * (ny + 2 * ng) * (nz + 2 * ng)
+    b = Box()
+    b.n[0], b.n[1], b.n[2] = nx, ny, nz
+    b.ng = ng
+    b.state_off = state_off
+    b.grav_off = grav_off
+    b.comp_stride = P if comp_stride is None else comp_stride
+    b.grav_stride = P if grav_stride is None else grav_stride
+    b.dx = dx
+    return b
+
+
+def workspace_bytes(params: Params, box: Box) -> int:
+    out = ctypes.c_size_t(0)
+    check("nyx_workspace_bytes", lib().nyx_workspace_bytes(ctypes.byref(params), ctypes.byref(box),
+                                                           ctypes.byref(out)))
+    return out.value
+
+
+def estimate_dt(params, box, state, a, cfl, dt_out, workspace, stream=None) -> None:
+    ws_bytes = workspace.numel() * workspace.element_size()
+    check("nyx_estimate_dt", lib().nyx_estimate_dt(
+        ctypes.byref(params), ctypes.byref(box), _ptr(state), a, cfl, _ptr(dt_out),
+        _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def hydro_step(params, box, state_in, grav, dt, a_old, a_new, state_out, dt_next=None,
+               stats=None, workspace=None, stream=None) -> None:
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    check("nyx_hydro_step", lib().nyx_hydro_step(
+        ctypes.byref(params), ctypes.byref(box), _ptr(state_in), _ptr(grav), float(dt),
+        float(a_old), float(a_new), _ptr(state_out), _ptr(dt_next), _ptr(stats), _ptr(workspace),
+        ws_bytes, _stream(stream)))
+
+
+def fill_ghosts_periodic(box, state, ncomp=6, stream=None) -> None:
+    check("nyx_fill_ghosts_periodic", lib().nyx_fill_ghosts_periodic(
+        ctypes.byref(box), _ptr(state), ncomp, _stream(stream)))
+
+
+def stats_dict(t) -> dict:
+    """Device nyx_stats block (a uint8/int64 tensor of 80 bytes) -> dict."""
+    vals = t.view(dtype=__import__("torch").int64).cpu().tolist()
+    return dict(zip(STATS_FIELDS, vals))
+
+
+class Batch:
+    """A batched plan (nyx_batch_*) over boxes in shared state/gravity buffers."""
+
+    def __init__(self, params: Params, boxes, workspace, stream=None):
+        self.params = params
+        self.nbox = len(boxes)
+        self._boxes = (Box * self.nbox)(*boxes)
+        self.workspace = workspace
+        h = ctypes.c_void_p(0)
+        ws_bytes = workspace.numel() * workspace.element_size()
+        check("nyx_batch_create", lib().nyx_batch_create(
+            ctypes.byref(params), self.nbox, self._boxes, _ptr(workspace), ws_bytes,
+            _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def workspace_bytes(params: Params, boxes):
+        arr = (Box * len(boxes))(*boxes)
+        mn, one = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check("nyx_batch_workspace_bytes", lib().nyx_batch_workspace_bytes(
+            ctypes.byref(params), len(boxes), arr, ctypes.byref(mn), ctypes.byref(one)))
+        return mn.value, one.value
+
+    @property
+    def num_groups(self) -> int:
+        return lib().nyx_batch_num_groups(self.handle)
+
+    def estimate_dt(self, state, a, cfl, dt, stream=None):
+        check("nyx_batch_estimate_dt", lib().nyx_batch_estimate_dt(
+            self.handle, _ptr(state), a, cfl, _ptr(dt), _stream(stream)))
+
+    def min_dt(self, dt, stream=None):
+        check("nyx_batch_min_dt", lib().nyx_batch_min_dt(self.handle, _ptr(dt), _stream(stream)))
+
+    def step(self, state_in, grav, dt, a_old, a_new, state_out, dt_next=None, stats=None,
+             stream=None):
+        check("nyx_hydro_step_batched", lib().nyx_hydro_step_batched(
+            self.handle, _ptr(state_in), _ptr(grav), _ptr(dt), float(a_old), float(a_new),
+            _ptr(state_out), _ptr(dt_next), _ptr(stats), _stream(stream)))
+
+    def fill_ghosts(self, state, mode=0, grid=(1, 1, 1), stream=None):
+        check("nyx_batch_fill_ghosts", lib().nyx_batch_fill_ghosts(
+            self.handle, mode, grid[0], grid[1], grid[2], _ptr(state), _stream(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().nyx_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

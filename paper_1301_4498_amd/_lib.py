@@ -1,0 +1,129 @@
+"""ctypes binding of libnyxhydro.so (include/nyx_hydro.h): argument marshalling
+only.  Every step of the path runs in the HIP library; if the library is not
+built this module raises instead of falling back to anything."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnyxhydro.so")
+
+NYX_OK = 0
+NYX_FP64 = 0
+NYX_MIXED = 1
+NYX_RIEMANN_TWOSHOCK = 0
+NYX_RIEMANN_LEARNED = 1
+
+STATUS = {0: "NYX_OK", -1: "NYX_E_NULL", -2: "NYX_E_SHAPE", -3: "NYX_E_PARAM",
+          -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("eta_dual", ctypes.c_double),
+        ("small_dens", ctypes.c_double),
+        ("small_pres", ctypes.c_double),
+        ("riemann_tol", ctypes.c_double),
+        ("mlp_resid_tol", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("riemann_maxiter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("riemann", ctypes.c_int32),
+        ("learned_stages_mask", ctypes.c_int32),
+        ("mlp_weights", ctypes.c_void_p),
+    ]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("ng", ctypes.c_int32),
+        ("state_off", ctypes.c_int64),
+        ("grav_off", ctypes.c_int64),
+        ("comp_stride", ctypes.c_int64),
+        ("grav_stride", ctypes.c_int64),
+        ("dx", ctypes.c_double),
+    ]
+
+
+STATS_FIELDS = ("nonfinite", "neg_dens", "neg_eint", "floor_hits", "trans_reverts",
+                "sync_E_from_e", "riemann_iters", "riemann_calls", "mlp_used", "mlp_fallback")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_ulonglong) for n in STATS_FIELDS]
+
+
+class NyxError(RuntimeError):
+    def __init__(self, fn, rc):
+        super().__init__("%s failed: %s (%d)" % (fn, STATUS.get(rc, "?"), rc))
+        self.rc = rc
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnyxhydro.so is not built (run __graft_entry__.build() or "
+                               "python paper_1301_4498_amd/build.py); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        P, B = ctypes.POINTER(Params), ctypes.POINTER(Box)
+        d, i = ctypes.c_double, ctypes.c_int
+        sig = {
+            "nyx_default_params": (None, [P]),
+            "nyx_status_string": (ctypes.c_char_p, [i]),
+            "nyx_workspace_bytes": (i, [P, B, ctypes.POINTER(sz)]),
+            "nyx_estimate_dt": (i, [P, B, vp, d, d, vp, vp, sz, vp]),
+            "nyx_hydro_step": (i, [P, B, vp, vp, d, d, d, vp, vp, vp, vp, sz, vp]),
+            "nyx_batch_workspace_bytes": (i, [P, i, B, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
+            "nyx_batch_create": (i, [P, i, B, vp, sz, vp, ctypes.POINTER(vp)]),
+            "nyx_batch_destroy": (i, [vp]),
+            "nyx_batch_num_groups": (i, [vp]),
+            "nyx_batch_estimate_dt": (i, [vp, vp, d, d, vp, vp]),
+            "nyx_batch_min_dt": (i, [vp, vp, vp]),
+            "nyx_hydro_step_batched": (i, [vp, vp, vp, vp, d, d, vp, vp, vp, vp]),
+            "nyx_fill_ghosts_periodic": (i, [B, vp, i, vp]),
+            "nyx_batch_fill_ghosts": (i, [vp, i, i, i, i, vp, vp]),
+            "nyx_profile_enable": (i, [i]),
+            "nyx_profile_read": (i, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), i]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(fn: str, rc: int) -> None:
+    if rc != NYX_OK:
+        raise NyxError(fn, rc)
+
+
+def exported_symbols():
+    return ["nyx_default_params", "nyx_status_string", "nyx_workspace_bytes", "nyx_estimate_dt",
+            "nyx_hydro_step", "nyx_batch_workspace_bytes", "nyx_batch_create",
+            "nyx_batch_destroy", "nyx_batch_num_groups", "nyx_batch_estimate_dt",
+            "nyx_batch_min_dt", "nyx_hydro_step_batched", "nyx_fill_ghosts_periodic",
+            "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read"]
+
+
+STAGE_NAMES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")
+
+
+def profile_enable(on: bool) -> None:
+    check("nyx_profile_enable", lib().nyx_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True):
+    """Milliseconds accumulated per stage and the number of timed sequences."""
+    ms = (ctypes.c_double * len(STAGE_NAMES))()
+    n = ctypes.c_longlong(0)
+    check("nyx_profile_read", lib().nyx_profile_read(ms, ctypes.byref(n), 1 if reset else 0))
+    return dict(zip(STAGE_NAMES, list(ms))), n.value

@@ -1,0 +1,59 @@
+"""Build the HIP library libnyxhydro.so for gfx950 in-tree with hipcc.
+
+Translation units:
+  nyx_step.hip  twice: FP64 stages (no contraction) and FP32-mixed stages;
+  nyx_util.hip  CFL reduction, dt finalisation, ghost fills (no contraction);
+  nyx_abi.cpp   the C ABI (validation, plans, dispatch).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libnyxhydro.so")
+ARCH = os.environ.get("NYX_OFFLOAD_ARCH", "gfx950")
+
+COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-command-line-argument"]
+
+UNITS = [
+    ("nyx_step.hip", "nyx_step_fp64.o", ["-DNYX_PREC_FP64", "-ffp-contract=off"]),
+    ("nyx_step.hip", "nyx_step_mixed.o", ["-DNYX_PREC_MIXED", "-ffp-contract=fast",
+                                          "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
+    ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
+    ("nyx_abi.cpp", "nyx_abi.o", ["-ffp-contract=off", "-x", "hip"]),
+]
+
+
+def _compile(unit):
+    src, obj, flags = unit
+    cmd = ["hipcc"] + COMMON + flags + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return obj
+
+
+def build() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        objs = list(ex.map(_compile, UNITS))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
+        [os.path.join(BUILD, o) for o in objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())
+    sys.exit(0)

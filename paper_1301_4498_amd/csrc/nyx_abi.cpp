@@ -1,0 +1,504 @@
+// nyx_abi.cpp -- the C ABI of include/nyx_hydro.h: argument validation,
+// workspace layout, batched plans and dispatch to the stage kernels.
+// Validation runs on the host before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "nyx_internal.h"
+
+using namespace nyx;
+
+namespace {
+
+constexpr size_t kHeaderBytes = 256;  // per-box running maximum of the CFL reduction
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_params(const nyx_params* p) {
+  if (!p) return NYX_E_NULL;
+  if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) return NYX_E_PARAM;
+  if (!(std::isfinite(p->eta_dual) && p->eta_dual >= 0.0)) return NYX_E_PARAM;
+  if (!finite_pos(p->small_dens) || !finite_pos(p->small_pres)) return NYX_E_PARAM;
+  if (!finite_pos(p->riemann_tol)) return NYX_E_PARAM;
+  if (!finite_pos(p->cfl)) return NYX_E_PARAM;
+  if (p->riemann_maxiter < 1 || p->riemann_maxiter > 64) return NYX_E_PARAM;
+  if (p->precision != NYX_FP64 && p->precision != NYX_MIXED) return NYX_E_PARAM;
+  if (p->riemann != NYX_RIEMANN_TWOSHOCK && p->riemann != NYX_RIEMANN_LEARNED) return NYX_E_PARAM;
+  if (p->riemann == NYX_RIEMANN_LEARNED) return NYX_E_UNSUPPORTED;
+  return NYX_OK;
+}
+
+int check_box(const nyx_box* b) {
+  if (!b) return NYX_E_NULL;
+  for (int d = 0; d < 3; ++d)
+    if (b->n[d] < 2 || (b->n[d] & 1) || b->n[d] > (1 << 20)) return NYX_E_SHAPE;
+  if (b->ng < 4 || b->ng > 64) return NYX_E_SHAPE;
+  long long P = 1;
+  for (int d = 0; d < 3; ++d) P *= (long long)(b->n[d] + 2 * b->ng);
+  if (P > (1ll << 40)) return NYX_E_SHAPE;
+  if (b->comp_stride < P || b->grav_stride < P) return NYX_E_SHAPE;
+  if (b->state_off < 0 || b->grav_off < 0) return NYX_E_SHAPE;
+  if (!finite_pos(b->dx)) return NYX_E_PARAM;
+  return NYX_OK;
+}
+
+size_t real_bytes(const nyx_params* p) { return p->precision == NYX_MIXED ? 4 : 8; }
+
+long long blocks_for(long long n) { return (n + kBlock - 1) / kBlock; }
+
+void set_blocks(const BoxDev& b, int* nb) {
+  nb[kSpaceP] = (int)blocks_for(b.P);
+  nb[kSpaceE] = (int)blocks_for(b.E);
+  nb[kSpaceV] = (int)blocks_for(b.V);
+}
+
+// [a0, a0 + alen) and [b0, b0 + blen) in bytes
+bool overlaps(const void* a, size_t alen, const void* b, size_t blen) {
+  uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + blen && y < x + alen;
+}
+
+size_t state_span_bytes(const nyx_box& b) {
+  long long P = (long long)(b.n[0] + 2 * b.ng) * (b.n[1] + 2 * b.ng) * (b.n[2] + 2 * b.ng);
+  return (size_t)(b.state_off + 5 * b.comp_stride + P) * sizeof(double);
+}
+
+void fill_physics(StepArgs& a, const nyx_params* p) {
+  a.gamma = p->gamma;
+  a.eta = p->eta_dual;
+  a.small_dens = p->small_dens;
+  a.small_pres = p->small_pres;
+  a.riemann_tol = p->riemann_tol;
+  a.cfl = p->cfl;
+  a.maxiter = p->riemann_maxiter;
+}
+
+// ---- stage timing ----
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t*> pending, free_;
+  double ms[kStages] = {0};
+  long long seq = 0;
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+
+hipEvent_t* take_events() {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (!P.on) return nullptr;
+  hipEvent_t* ev;
+  if (!P.free_.empty()) {
+    ev = P.free_.back();
+    P.free_.pop_back();
+  } else {
+    ev = new (std::nothrow) hipEvent_t[kStages + 1];
+    if (!ev) return nullptr;
+    for (int i = 0; i <= kStages; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) return nullptr;
+  }
+  P.pending.push_back(ev);
+  return ev;
+}
+
+hipError_t run_stages(const nyx_params* p, StepArgs a, hipStream_t s) {
+  a.ev = take_events();
+  return p->precision == NYX_MIXED ? mixed::launch_step(a, s) : fp64::launch_step(a, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void nyx_default_params(nyx_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->gamma = 5.0 / 3.0;
+  p->eta_dual = 1e-4;
+  p->small_dens = 1e-20;
+  p->small_pres = 1e-20;
+  p->riemann_tol = 1e-14;
+  p->mlp_resid_tol = 1e-3;
+  p->cfl = 0.5;
+  p->riemann_maxiter = 20;
+  p->precision = NYX_FP64;
+  p->riemann = NYX_RIEMANN_TWOSHOCK;
+  p->learned_stages_mask = 0;
+  p->mlp_weights = nullptr;
+}
+
+const char* nyx_status_string(int s) {
+  switch (s) {
+    case NYX_OK: return "ok";
+    case NYX_E_NULL: return "a required pointer is NULL";
+    case NYX_E_SHAPE: return "invalid box extents, ghost width or strides";
+    case NYX_E_PARAM: return "parameter out of range";
+    case NYX_E_ALIAS: return "input and output state overlap";
+    case NYX_E_HIP: return "HIP runtime or launch error";
+    case NYX_E_UNSUPPORTED: return "combination not supported by this library";
+    case NYX_E_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+int nyx_workspace_bytes(const nyx_params* p, const nyx_box* box, size_t* bytes) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_box(box))) return rc;
+  if (!bytes) return NYX_E_NULL;
+  long long elems = box_layout(*box, 0, 0, nullptr);
+  *bytes = kHeaderBytes + (size_t)elems * real_bytes(p);
+  return NYX_OK;
+}
+
+int nyx_estimate_dt(const nyx_params* p, const nyx_box* box, const double* state, double a,
+                    double cfl, double* dt_out, void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_box(box))) return rc;
+  if (!state || !dt_out || !workspace) return NYX_E_NULL;
+  if (!finite_pos(a) || !finite_pos(cfl)) return NYX_E_PARAM;
+  if (ws_bytes < 16 || ((uintptr_t)workspace & 255)) return NYX_E_WORKSPACE;
+  StepArgs A{};
+  box_layout(*box, 0, 0, &A.single);
+  set_blocks(A.single, A.nblocks);
+  fill_physics(A, p);
+  A.Uin = state;
+  A.smax = (unsigned long long*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
+  if (launch_dtmax(A, a, s) != hipSuccess) return NYX_E_HIP;
+  if (launch_dt_finalize(A, a, cfl, dt_out, s) != hipSuccess) return NYX_E_HIP;
+  return NYX_OK;
+}
+
+int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_in,
+                   const void* grav, double dt, double a_old, double a_new, double* state_out,
+                   double* dt_next, nyx_stats* stats, void* workspace, size_t ws_bytes,
+                   void* stream) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_box(box))) return rc;
+  if (!state_in || !grav || !state_out || !workspace) return NYX_E_NULL;
+  if (!finite_pos(dt) || !finite_pos(a_old) || !finite_pos(a_new)) return NYX_E_PARAM;
+  size_t span = state_span_bytes(*box);
+  if (overlaps(state_in, span, state_out, span)) return NYX_E_ALIAS;
+  size_t need = 0;
+  nyx_workspace_bytes(p, box, &need);
+  if (ws_bytes < need || ((uintptr_t)workspace & 255)) return NYX_E_WORKSPACE;
+  StepArgs A{};
+  box_layout(*box, 0, 0, &A.single);
+  set_blocks(A.single, A.nblocks);
+  fill_physics(A, p);
+  A.Uin = state_in;
+  A.Uout = state_out;
+  A.grav = grav;
+  A.work = (char*)workspace + kHeaderBytes;
+  A.smax = (unsigned long long*)workspace;
+  A.dt_host = dt;
+  A.a_old = a_old;
+  A.a_new = a_new;
+  A.stats = stats;
+  A.dt_next = dt_next;
+  hipStream_t s = (hipStream_t)stream;
+  if (dt_next && launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
+  if (run_stages(p, A, s) != hipSuccess) return NYX_E_HIP;
+  if (dt_next && launch_dt_finalize(A, a_new, p->cfl, dt_next, s) != hipSuccess) return NYX_E_HIP;
+  return NYX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched plans
+// ---------------------------------------------------------------------------
+struct nyx_batch {
+  nyx_params prm;
+  int nbox;
+  std::vector<nyx_box> boxes;
+  struct Group {
+    int b0, b1;
+    int nblocks[3];
+    const int* prefix[3];  // device
+  };
+  std::vector<Group> groups;
+  BoxDev* table;                 // device, nbox entries in box order
+  unsigned long long* smax;      // device, nbox entries
+  void* stage;                   // device stage region
+  size_t state_span;             // bytes spanned by the state of all boxes
+};
+
+namespace {
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+// bytes of the table region for a plan with `ngroups` groups
+size_t table_bytes(int nbox, int ngroups) {
+  return round256(sizeof(BoxDev) * (size_t)nbox) + round256(sizeof(int) * 3 * (size_t)(nbox + ngroups)) +
+         round256(sizeof(unsigned long long) * (size_t)nbox);
+}
+
+int check_boxes(const nyx_params* p, int nbox, const nyx_box* boxes) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (nbox < 1 || nbox > (1 << 24)) return NYX_E_SHAPE;
+  if (!boxes) return NYX_E_NULL;
+  for (int i = 0; i < nbox; ++i)
+    if ((rc = check_box(&boxes[i]))) return rc;
+  return NYX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nyx_batch_workspace_bytes(const nyx_params* p, int nbox, const nyx_box* boxes,
+                              size_t* min_bytes, size_t* single_group_bytes) {
+  int rc = check_boxes(p, nbox, boxes);
+  if (rc) return rc;
+  if (!min_bytes || !single_group_bytes) return NYX_E_NULL;
+  long long maxe = 0, tot = 0;
+  for (int i = 0; i < nbox; ++i) {
+    long long e = box_layout(boxes[i], i, 0, nullptr);
+    maxe = e > maxe ? e : maxe;
+    tot += e;
+  }
+  *min_bytes = table_bytes(nbox, nbox) + (size_t)maxe * real_bytes(p);
+  *single_group_bytes = table_bytes(nbox, nbox) + (size_t)tot * real_bytes(p);
+  return NYX_OK;
+}
+
+int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* workspace,
+                     size_t ws_bytes, void* stream, nyx_batch** out) {
+  int rc = check_boxes(p, nbox, boxes);
+  if (rc) return rc;
+  if (!workspace || !out) return NYX_E_NULL;
+  if ((uintptr_t)workspace & 255) return NYX_E_WORKSPACE;
+  const size_t rb = real_bytes(p);
+  // Pack boxes greedily into groups.  The group count is not known before
+  // packing, so the table region is sized for the worst case (one group per
+  // box) -- a few bytes per box.
+  const size_t tbytes = table_bytes(nbox, nbox);
+  if (ws_bytes <= tbytes) return NYX_E_WORKSPACE;
+  const long long cap = (long long)((ws_bytes - tbytes) / rb);
+  nyx_batch* plan = new (std::nothrow) nyx_batch();
+  if (!plan) return NYX_E_WORKSPACE;
+  plan->prm = *p;
+  plan->nbox = nbox;
+  plan->boxes.assign(boxes, boxes + nbox);
+  std::vector<BoxDev> host(nbox);
+  std::vector<int> prefix;
+  long long used = 0;
+  int g0 = 0;
+  size_t span = 0;
+  for (int i = 0; i <= nbox; ++i) {
+    long long need = 0;
+    if (i < nbox) {
+      need = box_layout(boxes[i], i, 0, nullptr);
+      if (need > cap) { delete plan; return NYX_E_WORKSPACE; }
+      size_t sp = state_span_bytes(boxes[i]);
+      span = sp > span ? sp : span;
+    }
+    if (i == nbox || used + need > cap) {
+      // close group [g0, i)
+      nyx_batch::Group g{};
+      g.b0 = g0;
+      g.b1 = i;
+      for (int s = 0; s < 3; ++s) {
+        g.prefix[s] = (const int*)(size_t)prefix.size();  // host offset for now
+        int acc = 0;
+        for (int b = g0; b < i; ++b) {
+          prefix.push_back(acc);
+          long long cnt = s == kSpaceP ? host[b].P : (s == kSpaceE ? host[b].E : host[b].V);
+          acc += (int)blocks_for(cnt);
+        }
+        prefix.push_back(acc);
+        g.nblocks[s] = acc;
+      }
+      if (i > g0) plan->groups.push_back(g);
+      g0 = i;
+      used = 0;
+      if (i == nbox) break;
+    }
+    used = box_layout(boxes[i], i, used, &host[i]);
+  }
+  char* w = (char*)workspace;
+  plan->table = (BoxDev*)w;
+  int* pre_dev = (int*)(w + round256(sizeof(BoxDev) * (size_t)nbox));
+  plan->smax = (unsigned long long*)((char*)pre_dev + round256(sizeof(int) * 3 * (size_t)(nbox + nbox)));
+  plan->stage = w + tbytes;
+  plan->state_span = span;
+  for (auto& g : plan->groups)
+    for (int s = 0; s < 3; ++s) g.prefix[s] = pre_dev + (size_t)g.prefix[s];
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(plan->table, host.data(), sizeof(BoxDev) * (size_t)nbox, hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(pre_dev, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete plan;
+    return NYX_E_HIP;
+  }
+  *out = plan;
+  return NYX_OK;
+}
+
+int nyx_batch_destroy(nyx_batch* plan) {
+  delete plan;
+  return NYX_OK;
+}
+
+int nyx_batch_num_groups(const nyx_batch* plan) { return plan ? (int)plan->groups.size() : 0; }
+
+}  // extern "C"
+
+namespace {
+
+StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
+  StepArgs A{};
+  A.table = plan->table + g.b0;
+  for (int s = 0; s < 3; ++s) {
+    A.prefix[s] = g.prefix[s];
+    A.nblocks[s] = g.nblocks[s];
+  }
+  A.nb = g.b1 - g.b0;
+  A.work = plan->stage;
+  A.smax = plan->smax;
+  fill_physics(A, &plan->prm);
+  return A;
+}
+
+StepArgs all_boxes_args(const nyx_batch* plan) {
+  StepArgs A{};
+  A.table = plan->table;
+  A.nb = plan->nbox;
+  A.smax = plan->smax;
+  fill_physics(A, &plan->prm);
+  return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nyx_batch_estimate_dt(nyx_batch* plan, const double* state, double a, double cfl, double* dt,
+                          void* stream) {
+  if (!plan || !state || !dt) return NYX_E_NULL;
+  if (!finite_pos(a) || !finite_pos(cfl)) return NYX_E_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
+  for (const auto& g : plan->groups) {
+    StepArgs A = group_args(plan, g);
+    A.Uin = state;
+    if (launch_dtmax(A, a, s) != hipSuccess) return NYX_E_HIP;
+  }
+  if (launch_dt_finalize(all_boxes_args(plan), a, cfl, dt, s) != hipSuccess) return NYX_E_HIP;
+  return NYX_OK;
+}
+
+int nyx_batch_min_dt(nyx_batch* plan, double* dt, void* stream) {
+  if (!plan || !dt) return NYX_E_NULL;
+  return launch_min_dt(dt, plan->nbox, (hipStream_t)stream) == hipSuccess ? NYX_OK : NYX_E_HIP;
+}
+
+int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* grav,
+                           const double* dt, double a_old, double a_new, double* state_out,
+                           double* dt_next, nyx_stats* stats, void* stream) {
+  if (!plan || !state_in || !grav || !dt || !state_out) return NYX_E_NULL;
+  if (!finite_pos(a_old) || !finite_pos(a_new)) return NYX_E_PARAM;
+  if (overlaps(state_in, plan->state_span, state_out, plan->state_span)) return NYX_E_ALIAS;
+  hipStream_t s = (hipStream_t)stream;
+  if (dt_next && launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
+  for (const auto& g : plan->groups) {
+    StepArgs A = group_args(plan, g);
+    A.Uin = state_in;
+    A.Uout = state_out;
+    A.grav = grav;
+    A.dt_dev = dt;
+    A.a_old = a_old;
+    A.a_new = a_new;
+    A.stats = stats;
+    A.dt_next = dt_next;
+    if (run_stages(&plan->prm, A, s) != hipSuccess) return NYX_E_HIP;
+  }
+  if (dt_next &&
+      launch_dt_finalize(all_boxes_args(plan), a_new, plan->prm.cfl, dt_next, s) != hipSuccess)
+    return NYX_E_HIP;
+  return NYX_OK;
+}
+
+int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void* stream) {
+  int rc = check_box(box);
+  if (rc) return rc;
+  if (!state) return NYX_E_NULL;
+  if (ncomp < 1 || ncomp > 16) return NYX_E_PARAM;
+  StepArgs A{};
+  box_layout(*box, 0, 0, &A.single);
+  set_blocks(A.single, A.nblocks);
+  return launch_fill_periodic(A, nullptr, state, ncomp, 0, 1, 1, 1, (hipStream_t)stream) == hipSuccess
+             ? NYX_OK
+             : NYX_E_HIP;
+}
+
+int nyx_profile_enable(int on) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.on = on != 0;
+  return NYX_OK;
+}
+
+int nyx_profile_read(double* ms, long long* sequences, int reset) {
+  Profiler& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (hipEvent_t* ev : P.pending) {
+    if (hipEventSynchronize(ev[kStages]) != hipSuccess) return NYX_E_HIP;
+    for (int i = 0; i < kStages; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) return NYX_E_HIP;
+      P.ms[i] += t;
+    }
+    P.seq += 1;
+    P.free_.push_back(ev);
+  }
+  P.pending.clear();
+  if (ms)
+    for (int i = 0; i < kStages; ++i) ms[i] = P.ms[i];
+  if (sequences) *sequences = P.seq;
+  if (reset) {
+    for (int i = 0; i < kStages; ++i) P.ms[i] = 0.0;
+    P.seq = 0;
+  }
+  return NYX_OK;
+}
+
+int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
+                          void* stream) {
+  if (!plan || !state) return NYX_E_NULL;
+  if (mode != 0 && mode != 1) return NYX_E_PARAM;
+  if (mode == 1) {
+    if (gx < 1 || gy < 1 || gz < 1 || (long long)gx * gy * gz != plan->nbox) return NYX_E_SHAPE;
+    const nyx_box& b0 = plan->boxes[0];
+    for (const auto& b : plan->boxes)
+      if (b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.n[2] != b0.n[2] || b.ng != b0.ng ||
+          b.ng > b.n[0] || b.ng > b.n[1] || b.ng > b.n[2])
+        return NYX_E_SHAPE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (const auto& g : plan->groups) {
+    StepArgs A = group_args(plan, g);
+    if (launch_fill_periodic(A, plan->table, state, 6, mode, gx, gy, gz, s) != hipSuccess)
+      return NYX_E_HIP;
+  }
+  return NYX_OK;
+}
+
+}  // extern "C"

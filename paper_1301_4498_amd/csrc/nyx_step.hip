@@ -1,0 +1,778 @@
+// nyx_step.hip -- stage kernels of the comoving unsplit PPM Godunov gas step
+// for gfx950 (Almgren et al., Nyx: Sec. 3.2 Gas Dynamics; Sec. 3.6 Steps 2
+// and 6).  This file is compiled twice:
+//   NYX_PREC_FP64  : every stage in FP64, no contraction (parity build);
+//   NYX_PREC_MIXED : primitives, flattening, PPM, tracing and the flux
+//                    formulas in FP32; the two-shock iteration, the transverse
+//                    corrections with their internal-energy recovery, the
+//                    conservative accumulation, the gravity corrector and the
+//                    dual-energy sync in FP64.
+//
+// Pipeline (one launch per stage, each over every box of a group):
+//   prim    padded cells       primitives rho, u, v, w, p, c
+//   flat    cells [-1,n]^3     flattening coefficient chi = min_d chi_d
+//   trace   cells [-1,n]^3 x 3 PPM + characteristic tracing -> edge states
+//   riem0   faces x 3          Riemann on stage-0 states -> F^d
+//   riem1   faces x 6          states corrected by F^t (k/3) -> F^{d|t}
+//   riem2   valid faces x 3    states corrected by F^{t1|t2}, F^{t2|t1} (k/2)
+//                              -> final comoving fluxes
+//   update  valid cells        flux differences, S_e, S_g^n, corrector, sync,
+//                              optional CFL maximum of the new state
+// Stage arrays are component-major over the [-1,n]^3 cell range (x fastest),
+// so every load and store of a wavefront is contiguous.
+#include <hip/hip_runtime.h>
+
+#include "nyx_internal.h"
+
+#if defined(NYX_PREC_FP64)
+#define NYX_NS fp64
+typedef double real;
+#elif defined(NYX_PREC_MIXED)
+#define NYX_NS mixed
+typedef float real;
+#else
+#error "define NYX_PREC_FP64 or NYX_PREC_MIXED"
+#endif
+
+namespace nyx {
+namespace NYX_NS {
+
+// CW84 flattening constants (the PPM reference cited in Sec. 3.2)
+#define FLAT_EPS 0.33
+#define FLAT_OMEGA1 0.75
+#define FLAT_OMEGA2 10.0
+
+template <class T>
+__device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+template <class T>
+__device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// block -> (box, local block) mapping
+// ---------------------------------------------------------------------------
+struct Loc {
+  const BoxDev* bd;
+  long long idx;  // cell index within the box's space
+};
+
+__device__ __forceinline__ Loc locate(const StepArgs& A, int space) {
+  Loc L;
+  long long lb;
+  if (A.table == nullptr) {
+    L.bd = &A.single;
+    lb = blockIdx.x;
+  } else {
+    const int* pre = A.prefix[space];
+    int lo = 0, hi = A.nb;  // find b with pre[b] <= blockIdx.x < pre[b+1]
+    int x = (int)blockIdx.x;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (pre[mid] <= x) lo = mid;
+      else hi = mid;
+    }
+    L.bd = A.table + lo;
+    lb = x - pre[lo];
+  }
+  L.idx = lb * kBlock + threadIdx.x;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// per-box constants of the step (same expressions as the host reference)
+// ---------------------------------------------------------------------------
+struct StepC {
+  double dt, a_h, da, kh, hdt_a, hda_a, pexp, kap1, kap2, k, gm1;
+};
+
+__device__ __forceinline__ StepC step_consts(const StepArgs& A, const BoxDev& b) {
+  StepC c;
+  c.dt = A.dt_dev ? A.dt_dev[b.gidx] : A.dt_host;
+  c.gm1 = A.gamma - 1.0;
+  c.a_h = 0.5 * (A.a_old + A.a_new);
+  c.da = A.a_new - A.a_old;
+  c.kh = c.dt / (c.a_h * b.dx);
+  c.hdt_a = (0.5 * c.dt) / c.a_h;
+  c.hda_a = (0.5 * c.da) / c.a_h;
+  c.pexp = (1.5 * c.gm1) * (c.da / c.a_h);
+  c.kap1 = c.kh / 3.0;
+  c.kap2 = c.kh / 2.0;
+  c.k = c.dt / b.dx;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// counters: one atomic per wavefront
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ void count(unsigned long long* dst, unsigned v) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: primitives on every padded cell
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
+  Loc L = locate(A, kSpaceP);
+  const BoxDev& b = *L.bd;
+  unsigned floors = 0;
+  if (L.idx < b.P) {
+    const long long id = L.idx;
+    const double* U = A.Uin + b.soff + id;
+    const double ao = A.a_old;
+    double rho = U[0];
+    if (rho < A.small_dens) { rho = A.small_dens; floors++; }
+    double u = U[b.sstride] / (ao * rho);
+    double v = U[2 * b.sstride] / (ao * rho);
+    double w = U[3 * b.sstride] / (ao * rho);
+    double re = U[5 * b.sstride] / (ao * ao);
+    double p = (A.gamma - 1.0) * re;
+    if (p < A.small_pres) { p = A.small_pres; floors++; }
+    double c = sqrt((A.gamma * p) / rho);
+    real* q = (real*)A.work + b.w_prim + id;
+    q[0] = (real)rho;
+    q[b.P] = (real)u;
+    q[2 * b.P] = (real)v;
+    q[3 * b.P] = (real)w;
+    q[4 * b.P] = (real)p;
+    q[5 * b.P] = (real)c;
+  }
+  if (A.stats) count(&A.stats->floor_hits, floors);
+}
+
+// padded index of the cell at E-array coordinates (ie, je, ke) (cell ie - 1)
+__device__ __forceinline__ long long pidx_e(const BoxDev& b, int ie, int je, int ke) {
+  return ((long long)(ke - 1 + b.ng) * b.py + (je - 1 + b.ng)) * b.px + (ie - 1 + b.ng);
+}
+
+// ---------------------------------------------------------------------------
+// stage 2: flattening (O2)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ real flat_tilde(real sp, real pm2, real pm1, real pp1, real pp2,
+                                           real um1, real up1) {
+  real dp1 = pp1 - pm1;
+  real dp2 = pp2 - pm2;
+  real z = fabs(dp1) / vmax(fabs(dp2), sp);
+  bool w = (fabs(dp1) > (real)FLAT_EPS * vmin(pp1, pm1)) && ((up1 - um1) < (real)0);
+  return w ? vmax((real)0, vmin((real)1, (real)FLAT_OMEGA2 * (z - (real)FLAT_OMEGA1))) : (real)0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
+  Loc L = locate(A, kSpaceE);
+  const BoxDev& b = *L.bd;
+  if (L.idx >= b.E) return;
+  const long long e = L.idx;
+  const int ie = (int)(e % b.ex);
+  const int je = (int)((e / b.ex) % b.ey);
+  const int ke = (int)(e / ((long long)b.ex * b.ey));
+  const real* prim = (const real*)A.work + b.w_prim;
+  const real* P = prim + 4 * b.P;
+  const real sp = (real)A.small_pres;
+  const long long c0 = pidx_e(b, ie, je, ke);
+  const long long sd[3] = {1, b.px, (long long)b.px * b.py};
+  real cmin = (real)1;
+  for (int d = 0; d < 3; ++d) {
+    const long long s = sd[d];
+    const real* U = prim + (1 + d) * b.P;
+    real p[7], u[5];
+    for (int o = -3; o <= 3; ++o) p[o + 3] = P[c0 + o * s];
+    for (int o = -2; o <= 2; ++o) u[o + 2] = U[c0 + o * s];
+    real fm = flat_tilde(sp, p[0], p[1], p[3], p[4], u[0], u[2]);
+    real f0 = flat_tilde(sp, p[1], p[2], p[4], p[5], u[1], u[3]);
+    real fp = flat_tilde(sp, p[2], p[3], p[5], p[6], u[2], u[4]);
+    real dp1 = p[4] - p[2];
+    real f = f0;
+    if (dp1 > (real)0) f = vmax(f0, fm);
+    else if (dp1 < (real)0) f = vmax(f0, fp);
+    real cd = (real)1 - f;
+    cmin = (d == 0) ? cd : vmin(cmin, cd);
+  }
+  ((real*)A.work)[b.w_chi + e] = cmin;
+}
+
+// ---------------------------------------------------------------------------
+// stage 3: PPM (O3) and characteristic tracing (O4)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
+  real dc = (real)0.5 * (qp1 - qm1);
+  real dr = qp1 - q0;
+  real dl = q0 - qm1;
+  if (dr * dl > (real)0) {
+    real m = fabs(dc);
+    m = vmin(m, (real)2 * fabs(dl));
+    m = vmin(m, (real)2 * fabs(dr));
+    return dc > (real)0 ? m : -m;
+  }
+  return (real)0;
+}
+// interface value between the second and third of four consecutive cells
+__device__ __forceinline__ real ppm_face(real q0, real q1, real q2, real q3) {
+  real s0 = lim_slope(q0, q1, q2);
+  real s1 = lim_slope(q1, q2, q3);
+  return (q1 + (real)0.5 * (q2 - q1)) - (s1 - s0) / (real)6;
+}
+__device__ __forceinline__ void ppm_edges(const real* q5, real chi, real& qm_o, real& qp_o) {
+  real qj = q5[2];
+  real qp = ppm_face(q5[1], q5[2], q5[3], q5[4]);
+  real qm = ppm_face(q5[0], q5[1], q5[2], q5[3]);
+  qp = chi * qp + ((real)1 - chi) * qj;
+  qm = chi * qm + ((real)1 - chi) * qj;
+  if ((qp - qj) * (qj - qm) <= (real)0) {
+    qp = qj;
+    qm = qj;
+  } else {
+    real dq = qp - qm;
+    real t = dq * (qj - (real)0.5 * (qm + qp));
+    real s = dq * dq / (real)6;
+    if (t > s) qm = (real)3 * qj - (real)2 * qp;
+    else if (-s > t) qp = (real)3 * qj - (real)2 * qm;
+  }
+  qm_o = qm;
+  qp_o = qp;
+}
+__device__ __forceinline__ real avg_hi(real qp, real dq, real q6, real sig) {
+  return qp - (real)0.5 * sig * (dq - ((real)1 - ((real)2 / (real)3) * sig) * q6);
+}
+__device__ __forceinline__ real avg_lo(real qm, real dq, real q6, real sig) {
+  return qm + (real)0.5 * sig * (dq + ((real)1 - ((real)2 / (real)3) * sig) * q6);
+}
+
+// One side of the tracing: side = +1 (right face, waves with lam > 0) or -1.
+// v[] indexes: 0 rho, nv normal velocity, t1/t2 transverse, 4 p.
+template <int SIDE>
+__device__ __forceinline__ void trace_side(const real* qc, real c, const real* qe,
+                                           const real* dq, const real* q6, const real* lam,
+                                           const real* sig, int nv, int t1, int t2,
+                                           real* out) {
+  const real rho = qc[0];
+  const real csq = c * c;
+  // averages over each wave's domain of dependence for rho, u_n, p
+  real I[3][3];
+  const int vid[3] = {0, nv, 4};
+  for (int w = 0; w < 3; ++w)
+    for (int k = 0; k < 3; ++k) {
+      int v = vid[k];
+      I[w][k] = SIDE > 0 ? avg_hi(qe[v], dq[v], q6[v], sig[w]) : avg_lo(qe[v], dq[v], q6[v], sig[w]);
+    }
+  const int fast = SIDE > 0 ? 2 : 0;  // fastest wave toward the face
+  const bool fast_in = SIDE > 0 ? (lam[2] > (real)0) : (lam[0] < (real)0);
+  real ref[3];
+  for (int k = 0; k < 3; ++k) ref[k] = fast_in ? I[fast][k] : qe[vid[k]];
+  real D[3][3];
+  for (int w = 0; w < 3; ++w) {
+    bool in = SIDE > 0 ? (lam[w] > (real)0) : (lam[w] < (real)0);
+    for (int k = 0; k < 3; ++k) D[w][k] = in ? ref[k] - I[w][k] : (real)0;
+  }
+  real am = (real)0.5 * (D[0][2] / csq - (rho * D[0][1]) / c);
+  real ap = (real)0.5 * (D[2][2] / csq + (rho * D[2][1]) / c);
+  real a0 = D[1][0] - D[1][2] / csq;
+  out[0] = ref[0] - ((am + a0) + ap);
+  out[nv] = ref[1] - (c / rho) * (ap - am);
+  out[4] = ref[2] - csq * (am + ap);
+  const bool c_in = SIDE > 0 ? (lam[1] > (real)0) : (lam[1] < (real)0);
+  out[t1] = c_in ? (SIDE > 0 ? avg_hi(qe[t1], dq[t1], q6[t1], sig[1])
+                             : avg_lo(qe[t1], dq[t1], q6[t1], sig[1]))
+                 : qe[t1];
+  out[t2] = c_in ? (SIDE > 0 ? avg_hi(qe[t2], dq[t2], q6[t2], sig[1])
+                             : avg_lo(qe[t2], dq[t2], q6[t2], sig[1]))
+                 : qe[t2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
+  Loc L = locate(A, kSpaceE);
+  const BoxDev& b = *L.bd;
+  const int d = blockIdx.y;
+  unsigned floors = 0;
+  if (L.idx < b.E) {
+    const long long e = L.idx;
+    const int ie = (int)(e % b.ex);
+    const int je = (int)((e / b.ex) % b.ey);
+    const int ke = (int)(e / ((long long)b.ex * b.ey));
+    const StepC C = step_consts(A, b);
+    const real* prim = (const real*)A.work + b.w_prim;
+    const long long c0 = pidx_e(b, ie, je, ke);
+    const long long s = d == 0 ? 1 : (d == 1 ? (long long)b.px : (long long)b.px * b.py);
+    const real chi = ((const real*)A.work)[b.w_chi + e];
+    real qc[5], qm[5], qp[5], dq[5], q6[5];
+    for (int v = 0; v < 5; ++v) {
+      const real* Q = prim + v * b.P;
+      real q5[5];
+      for (int o = -2; o <= 2; ++o) q5[o + 2] = Q[c0 + o * s];
+      qc[v] = q5[2];
+      ppm_edges(q5, chi, qm[v], qp[v]);
+      dq[v] = qp[v] - qm[v];
+      q6[v] = (real)6 * qc[v] - (real)3 * (qm[v] + qp[v]);
+    }
+    const real c = prim[5 * b.P + c0];
+    const int nv = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+    const real u = qc[nv];
+    real lam[3] = {u - c, u, u + c};
+    const real kh = (real)C.kh;
+    real sig[3];
+    for (int w = 0; w < 3; ++w) sig[w] = fabs(lam[w]) * kh;
+    real lo[5], hi[5];
+    trace_side<+1>(qc, c, qp, dq, q6, lam, sig, nv, t1, t2, hi);
+    trace_side<-1>(qc, c, qm, dq, q6, lam, sig, nv, t1, t2, lo);
+    // half-step gravity and expansion sources, then floors
+    const real* G = (const real*)A.grav + b.goff + c0;
+    real g[3] = {G[0], G[b.gstride], G[2 * b.gstride]};
+    const real hdt_a = (real)C.hdt_a, hda_a = (real)C.hda_a, pexp = (real)C.pexp;
+    const real sd_ = (real)A.small_dens, sp_ = (real)A.small_pres;
+    real* out[2] = {lo, hi};
+    for (int sd = 0; sd < 2; ++sd) {
+      real* q = out[sd];
+      for (int dd = 0; dd < 3; ++dd) q[1 + dd] = q[1 + dd] + (hdt_a * g[dd] - hda_a * qc[1 + dd]);
+      q[4] = q[4] - pexp * qc[4];
+      if (q[0] < sd_) { q[0] = sd_; floors++; }
+      if (q[4] < sp_) { q[4] = sp_; floors++; }
+    }
+    real* W = (real*)A.work + b.w_edge + e;
+    for (int v = 0; v < 5; ++v) {
+      W[((d * 2 + 0) * 5 + v) * b.E] = lo[v];
+      W[((d * 2 + 1) * 5 + v) * b.E] = hi[v];
+    }
+  }
+  if (A.stats) count(&A.stats->floor_hits, floors);
+}
+
+// ---------------------------------------------------------------------------
+// two-shock Riemann solver (O5), always FP64
+// ---------------------------------------------------------------------------
+struct RiemannOut {
+  double r, u, v, w, p;
+  int iters;
+};
+
+__device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
+                                                const double* qR) {
+  const double gam = A.gamma;
+  const double g2 = 0.5 * (gam + 1.0);
+  const double sp = A.small_pres;
+  const double rl = qL[0], ul = qL[1], pl = qL[4];
+  const double rr = qR[0], ur = qR[1], pr = qR[4];
+  const double CL = (gam * pl) * rl;
+  const double CR = (gam * pr) * rr;
+  const double W0L = sqrt(CL), W0R = sqrt(CR);
+  double p = ((W0R * pl + W0L * pr) + (W0L * W0R) * (ul - ur)) / (W0L + W0R);
+  p = vmax(p, sp);
+  int it = 0;
+  double WL, WR, usL, usR, ZL, ZR;
+  while (it < A.maxiter) {
+    WL = sqrt(CL + (g2 * rl) * (p - pl));
+    WR = sqrt(CR + (g2 * rr) * (p - pr));
+    usL = ul - (p - pl) / WL;
+    usR = ur + (p - pr) / WR;
+    ZL = ((2.0 * WL) * WL) * WL / (WL * WL + CL);
+    ZR = ((2.0 * WR) * WR) * WR / (WR * WR + CR);
+    double pn = p - ((ZL * ZR) * (usR - usL)) / (ZL + ZR);
+    pn = vmax(pn, sp);
+    ++it;
+    bool conv = fabs(pn - p) <= A.riemann_tol * pn;
+    p = pn;
+    if (conv) break;
+  }
+  WL = sqrt(CL + (g2 * rl) * (p - pl));
+  WR = sqrt(CR + (g2 * rr) * (p - pr));
+  usL = ul - (p - pl) / WL;
+  usR = ur + (p - pr) / WR;
+  ZL = ((2.0 * WL) * WL) * WL / (WL * WL + CL);
+  ZR = ((2.0 * WR) * WR) * WR / (WR * WR + CR);
+  const double ustar = (ZL * usL + ZR * usR) / (ZL + ZR);
+  const double pstar = p;
+  const double rsL = 1.0 / (1.0 / rl - (pstar - pl) / (WL * WL));
+  const double rsR = 1.0 / (1.0 / rr - (pstar - pr) / (WR * WR));
+  const double cL = sqrt((gam * pl) / rl), cR = sqrt((gam * pr) / rr);
+  const double csL = sqrt((gam * pstar) / rsL), csR = sqrt((gam * pstar) / rsR);
+  double shdL, stlL, shdR, stlR;
+  if (pstar >= pl) { shdL = ul - WL / rl; stlL = shdL; }
+  else { shdL = ul - cL; stlL = ustar - csL; }
+  if (pstar >= pr) { shdR = ur + WR / rr; stlR = shdR; }
+  else { shdR = ur + cR; stlR = ustar + csR; }
+  double sL0, sL1, sL2, sR0, sR1, sR2;
+  if (shdL >= 0.0) { sL0 = rl; sL1 = ul; sL2 = pl; }
+  else if (stlL <= 0.0) { sL0 = rsL; sL1 = ustar; sL2 = pstar; }
+  else {
+    double f = (0.0 - shdL) / (stlL - shdL);
+    sL0 = rl + f * (rsL - rl);
+    sL1 = ul + f * (ustar - ul);
+    sL2 = pl + f * (pstar - pl);
+  }
+  if (shdR <= 0.0) { sR0 = rr; sR1 = ur; sR2 = pr; }
+  else if (stlR >= 0.0) { sR0 = rsR; sR1 = ustar; sR2 = pstar; }
+  else {
+    double f = (0.0 - shdR) / (stlR - shdR);
+    sR0 = rr + f * (rsR - rr);
+    sR1 = ur + f * (ustar - ur);
+    sR2 = pr + f * (pstar - pr);
+  }
+  RiemannOut o;
+  if (ustar > 0.0) {
+    o.r = sL0; o.u = sL1; o.p = sL2; o.v = qL[2]; o.w = qL[3];
+  } else if (ustar < 0.0) {
+    o.r = sR0; o.u = sR1; o.p = sR2; o.v = qR[2]; o.w = qR[3];
+  } else {
+    o.r = 0.5 * (sL0 + sR0);
+    o.u = 0.5 * (sL1 + sR1);
+    o.p = 0.5 * (sL2 + sR2);
+    o.v = 0.5 * (qL[2] + qR[2]);
+    o.w = 0.5 * (qL[3] + qR[3]);
+  }
+  o.iters = it;
+  return o;
+}
+
+// O6: lab-frame fluxes of a d-face from the Godunov state (flux arithmetic in real)
+__device__ __forceinline__ void face_flux(double gamma, int d, const RiemannOut& g, real* f) {
+  const real gm1 = (real)(gamma - 1.0);
+  const real r = (real)g.r, u = (real)g.u, v = (real)g.v, w = (real)g.w, p = (real)g.p;
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  const real ru = r * u;
+  f[0] = ru;
+  f[1 + d] = ru * u + p;
+  f[1 + t1] = ru * v;
+  f[1 + t2] = ru * w;
+  const real rE = p / gm1 + ((real)0.5 * r) * ((u * u + v * v) + w * w);
+  f[4] = u * (rE + p);
+  f[5] = (u * p) / gm1;
+  f[6] = p;
+  f[7] = u;
+}
+
+// solve at a d-face from lab-frame double states
+__device__ __forceinline__ RiemannOut solve_face(const StepArgs& A, int d, const double* L,
+                                                 const double* R) {
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  double qL[5] = {L[0], L[1 + d], L[1 + t1], L[1 + t2], L[4]};
+  double qR[5] = {R[0], R[1 + d], R[1 + t1], R[1 + t2], R[4]};
+  return two_shock(A, qL, qR);
+}
+
+__device__ __forceinline__ void e_coords(const BoxDev& b, long long e, int* c) {
+  c[0] = (int)(e % b.ex);
+  c[1] = (int)((e / b.ex) % b.ey);
+  c[2] = (int)(e / ((long long)b.ex * b.ey));
+}
+__device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
+  return d == 0 ? 1 : (d == 1 ? (long long)b.ex : (long long)b.ex * b.ey);
+}
+
+// ---------------------------------------------------------------------------
+// stage 4: Riemann on stage-0 states, faces between cells of [-1, n]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
+  Loc L = locate(A, kSpaceE);
+  const BoxDev& b = *L.bd;
+  const int d = blockIdx.y;
+  unsigned calls = 0, iters = 0;
+  if (L.idx < b.E) {
+    const long long e = L.idx;
+    int c[3];
+    e_coords(b, e, c);
+    if (c[d] >= 1) {  // face f = c[d] - 1 in [0, n_d]
+      const long long eL = e - e_stride(b, d);
+      const real* W = (const real*)A.work + b.w_edge;
+      double ql[5], qr[5];
+      for (int v = 0; v < 5; ++v) {
+        ql[v] = (double)W[((d * 2 + 1) * 5 + v) * b.E + eL];
+        qr[v] = (double)W[((d * 2 + 0) * 5 + v) * b.E + e];
+      }
+      RiemannOut g = solve_face(A, d, ql, qr);
+      calls = 1;
+      iters = g.iters;
+      real f[kFaceVals];
+      face_flux(A.gamma, d, g, f);
+      real* F = (real*)A.work + b.w_f0 + (long long)d * kFaceVals * b.E + e;
+      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+    }
+  }
+  if (A.stats) {
+    count(&A.stats->riemann_calls, calls);
+    count(&A.stats->riemann_iters, iters);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// O7: transverse correction of a lab-frame edge state (FP64 arithmetic)
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q,
+                                              const real* const* fm, const real* const* fp,
+                                              long long st, double kap, double* out) {
+  const double gm1 = A.gamma - 1.0;
+  const double rho = q[0], ux = q[1], uy = q[2], uz = q[3], p = q[4];
+  double U[5];
+  U[0] = rho;
+  U[1] = rho * ux;
+  U[2] = rho * uy;
+  U[3] = rho * uz;
+  U[4] = p / gm1 + (0.5 * rho) * ((ux * ux + uy * uy) + uz * uz);
+  const double Ue = p / gm1;
+  double Dc[5];
+  for (int c = 0; c < 5; ++c) {
+    Dc[c] = (double)fp[0][c * st] - (double)fm[0][c * st];
+    if (NT == 2) Dc[c] = Dc[c] + ((double)fp[1][c * st] - (double)fm[1][c * st]);
+  }
+  double De = ((double)fp[0][5 * st] - (double)fm[0][5 * st]) +
+              (0.5 * ((double)fp[0][6 * st] + (double)fm[0][6 * st])) *
+                  ((double)fp[0][7 * st] - (double)fm[0][7 * st]);
+  if (NT == 2)
+    De = De + (((double)fp[1][5 * st] - (double)fm[1][5 * st]) +
+               (0.5 * ((double)fp[1][6 * st] + (double)fm[1][6 * st])) *
+                   ((double)fp[1][7 * st] - (double)fm[1][7 * st]));
+  double Un[5];
+  for (int c = 0; c < 5; ++c) Un[c] = U[c] - kap * Dc[c];
+  const double Uen = Ue - kap * De;
+  const double ke = (0.5 * ((Un[1] * Un[1] + Un[2] * Un[2]) + Un[3] * Un[3])) / Un[0];
+  double pn;
+  if (Un[4] - ke > A.eta * Un[4]) pn = gm1 * (Un[4] - ke);
+  else pn = gm1 * Uen;
+  double r[5];
+  r[0] = Un[0];
+  r[1] = Un[1] / Un[0];
+  r[2] = Un[2] / Un[0];
+  r[3] = Un[3] / Un[0];
+  r[4] = pn;
+  bool ok = (r[0] > 0.0) && (r[4] > 0.0);
+  for (int c = 0; c < 5; ++c) ok = ok && isfinite(r[c]);
+  if (!ok) {
+    for (int c = 0; c < 5; ++c) out[c] = q[c];
+    return true;
+  }
+  for (int c = 0; c < 5; ++c) out[c] = r[c];
+  return false;
+}
+
+__device__ __forceinline__ int pair_index(int d, int t) { return d * 2 + (t == (d + 1) % 3 ? 0 : 1); }
+
+// ---------------------------------------------------------------------------
+// stage 5: d-states corrected by stage-0 t-fluxes, Riemann -> F^{d|t}
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
+  Loc L = locate(A, kSpaceE);
+  const BoxDev& b = *L.bd;
+  const int pq = blockIdx.y;
+  const int d = pq >> 1;
+  const int t = (d + 1 + (pq & 1)) % 3;
+  unsigned calls = 0, iters = 0, reverts = 0;
+  if (L.idx < b.E) {
+    const long long e = L.idx;
+    int c[3];
+    e_coords(b, e, c);
+    if (c[d] >= 1 && c[t] >= 1 && c[t] <= b.n[t]) {
+      const StepC C = step_consts(A, b);
+      const long long sdd = e_stride(b, d), stt = e_stride(b, t);
+      const real* W = (const real*)A.work + b.w_edge;
+      const real* F0t = (const real*)A.work + b.w_f0 + (long long)t * kFaceVals * b.E;
+      double qs[2][5];
+      for (int s = 0; s < 2; ++s) {
+        const long long ec = s == 0 ? e - sdd : e;
+        const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
+        double q[5];
+        for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+        const real* fm[1] = {F0t + ec};
+        const real* fp[1] = {F0t + ec + stt};
+        reverts += trans_correct<1>(A, q, fm, fp, b.E, C.kap1, qs[s]) ? 1u : 0u;
+      }
+      RiemannOut g = solve_face(A, d, qs[0], qs[1]);
+      calls = 1;
+      iters = g.iters;
+      real f[kFaceVals];
+      face_flux(A.gamma, d, g, f);
+      real* F = (real*)A.work + b.w_f1 + (long long)pq * kFaceVals * b.E + e;
+      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+    }
+  }
+  if (A.stats) {
+    count(&A.stats->riemann_calls, calls);
+    count(&A.stats->riemann_iters, iters);
+    count(&A.stats->trans_reverts, reverts);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 6: final d-states and comoving fluxes on valid faces
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+  Loc L = locate(A, kSpaceE);
+  const BoxDev& b = *L.bd;
+  const int d = blockIdx.y;
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  unsigned calls = 0, iters = 0, reverts = 0;
+  if (L.idx < b.E) {
+    const long long e = L.idx;
+    int c[3];
+    e_coords(b, e, c);
+    if (c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 && c[t2] <= b.n[t2]) {
+      const StepC C = step_consts(A, b);
+      const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
+      const real* W = (const real*)A.work + b.w_edge;
+      const real* F1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kFaceVals * b.E;
+      const real* F1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kFaceVals * b.E;
+      double qs[2][5];
+      for (int s = 0; s < 2; ++s) {
+        const long long ec = s == 0 ? e - sdd : e;
+        const int side = s == 0 ? 1 : 0;
+        double q[5];
+        for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+        const real* fm[2] = {F1a + ec, F1b + ec};
+        const real* fp[2] = {F1a + ec + s1, F1b + ec + s2};
+        reverts += trans_correct<2>(A, q, fm, fp, b.E, C.kap2, qs[s]) ? 1u : 0u;
+      }
+      RiemannOut g = solve_face(A, d, qs[0], qs[1]);
+      calls = 1;
+      iters = g.iters;
+      real f[kFaceVals];
+      face_flux(A.gamma, d, g, f);
+      // O9: comoving factors of the flux vector (Sec. 3.2)
+      const real ah = (real)C.a_h;
+      f[0] = f[0] / ah;
+      f[4] = ah * f[4];
+      f[5] = ah * f[5];
+      real* F = (real*)A.work + b.w_f2 + (long long)d * kFaceVals * b.E + e;
+      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+    }
+  }
+  if (A.stats) {
+    count(&A.stats->riemann_calls, calls);
+    count(&A.stats->riemann_iters, iters);
+    count(&A.stats->trans_reverts, reverts);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL maximum of one cell (Sec. 3.5), shared by update and estimate_dt
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cell_speed(const StepArgs& A, double U0, double m0, double m1,
+                                             double m2, double Ue, double a) {
+  const double gm1 = A.gamma - 1.0;
+  double rho = vmax(U0, A.small_dens);
+  double re = Ue / (a * a);
+  double p = vmax(gm1 * re, A.small_pres);
+  double c = sqrt((A.gamma * p) / rho);
+  double s = 0.0;
+  s = vmax(s, fabs(m0 / (a * rho)) + c);
+  s = vmax(s, fabs(m1 / (a * rho)) + c);
+  s = vmax(s, fabs(m2 / (a * rho)) + c);
+  return s;
+}
+
+__device__ __forceinline__ void block_max_atomic(double s, unsigned long long* dst) {
+  __shared__ double red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) s = vmax(s, __shfl_xor(s, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int i = 1; i < kBlock / 64; ++i) m = vmax(m, red[i]);
+    if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage 7: conservative update, gravity corrector, dual-energy sync
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
+  Loc L = locate(A, kSpaceV);
+  const BoxDev& b = *L.bd;
+  unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
+  double smax = 0.0;
+  if (L.idx < b.V) {
+    const long long v = L.idx;
+    const int i = (int)(v % b.n[0]);
+    const int j = (int)((v / b.n[0]) % b.n[1]);
+    const int k = (int)(v / ((long long)b.n[0] * b.n[1]));
+    const StepC C = step_consts(A, b);
+    const long long e = ((long long)(k + 1) * b.ey + (j + 1)) * b.ex + (i + 1);
+    const real* F2 = (const real*)A.work + b.w_f2;
+    double D[6];
+    double Pi = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const real* F = F2 + (long long)d * kFaceVals * b.E;
+      const long long eu = e + e_stride(b, d);
+      for (int c = 0; c < 6; ++c) {
+        double dF = (double)F[c * b.E + eu] - (double)F[c * b.E + e];
+        D[c] = (d == 0) ? dF : D[c] + dF;
+      }
+      double pd = (0.5 * ((double)F[6 * b.E + eu] + (double)F[6 * b.E + e])) *
+                  ((double)F[7 * b.E + eu] - (double)F[7 * b.E + e]);
+      Pi = (d == 0) ? pd : Pi + pd;
+    }
+    const long long id = ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
+    const double* U = A.Uin + b.soff + id;
+    const double U0 = U[0];
+    const double Um[3] = {U[b.sstride], U[2 * b.sstride], U[3 * b.sstride]};
+    const double UE = U[4 * b.sstride], Ue = U[5 * b.sstride];
+    const real* G = (const real*)A.grav + b.goff + id;
+    const double g[3] = {(double)G[0], (double)G[b.gstride], (double)G[2 * b.gstride]};
+    const double dt = C.dt, kk = C.k;
+    // predictor (Step 2)
+    const double s0 = U0 - kk * D[0];
+    double sm[3];
+    for (int d = 0; d < 3; ++d) sm[d] = (Um[d] - kk * D[1 + d]) + (dt * U0) * g[d];
+    const double sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+    const double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
+    // corrector (Step 6), same g
+    double nm[3];
+    for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
+    double nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
+                                   (sm[2] - Um[2]) * g[2]);
+    double ne = se;
+    // dual-energy sync (Step 6)
+    const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;
+    if (nE - ke > A.eta * nE) {
+      ne = nE - ke;
+    } else {
+      nE = ne + ke;
+      nsync = 1;
+    }
+    double* O = A.Uout + b.soff + id;
+    O[0] = s0;
+    O[b.sstride] = nm[0];
+    O[2 * b.sstride] = nm[1];
+    O[3 * b.sstride] = nm[2];
+    O[4 * b.sstride] = nE;
+    O[5 * b.sstride] = ne;
+    bool fin = isfinite(s0) && isfinite(nm[0]) && isfinite(nm[1]) && isfinite(nm[2]) &&
+               isfinite(nE) && isfinite(ne);
+    nnf = fin ? 0 : 1;
+    nnd = s0 <= 0.0 ? 1 : 0;
+    nne = ne <= 0.0 ? 1 : 0;
+    if (A.dt_next) smax = cell_speed(A, s0, nm[0], nm[1], nm[2], ne, A.a_new);
+  }
+  if (A.stats) {
+    count(&A.stats->sync_E_from_e, nsync);
+    count(&A.stats->nonfinite, nnf);
+    count(&A.stats->neg_dens, nnd);
+    count(&A.stats->neg_eint, nne);
+  }
+  if (A.dt_next) block_max_atomic(smax, A.smax + b.gidx);
+}
+
+hipError_t launch_step(const StepArgs& a, hipStream_t s) {
+  const dim3 blk(kBlock);
+  auto mark = [&](int i) {
+    if (a.ev) (void)hipEventRecord(a.ev[i], s);
+  };
+  mark(0);
+  hipLaunchKernelGGL(k_prim, dim3(a.nblocks[kSpaceP]), blk, 0, s, a);
+  mark(1);
+  hipLaunchKernelGGL(k_flat, dim3(a.nblocks[kSpaceE]), blk, 0, s, a);
+  mark(2);
+  hipLaunchKernelGGL(k_trace, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  mark(3);
+  hipLaunchKernelGGL(k_riem0, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  mark(4);
+  hipLaunchKernelGGL(k_riem1, dim3(a.nblocks[kSpaceE], 6), blk, 0, s, a);
+  mark(5);
+  hipLaunchKernelGGL(k_riem2, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  mark(6);
+  hipLaunchKernelGGL(k_update, dim3(a.nblocks[kSpaceV]), blk, 0, s, a);
+  mark(7);
+  return hipGetLastError();
+}
+
+}  // namespace NYX_NS
+}  // namespace nyx

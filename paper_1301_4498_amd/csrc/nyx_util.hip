@@ -1,0 +1,157 @@
+// nyx_util.hip -- precision-independent kernels: the hydro CFL reduction
+// (Sec. 3.5), the per-box dt finalisation, the level minimum and the ghost
+// fills that prepare a step's inputs (Sec. 4.1).  Built without contraction.
+#include <hip/hip_runtime.h>
+
+#include "nyx_internal.h"
+
+namespace nyx {
+
+__device__ __forceinline__ double dmaxd(double a, double b) { return a > b ? a : b; }
+__device__ __forceinline__ double dmind(double a, double b) { return a < b ? a : b; }
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ const BoxDev* locate_box(const StepArgs& A, int space, long long& idx) {
+  if (A.table == nullptr) {
+    idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    return &A.single;
+  }
+  const int* pre = A.prefix[space];
+  int lo = 0, hi = A.nb;
+  int x = (int)blockIdx.x;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pre[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  idx = (long long)(x - pre[lo]) * kBlock + threadIdx.x;
+  return A.table + lo;
+}
+
+// maximum over valid cells and axes of |U_d| + c (Sec. 3.5), per box
+__global__ __launch_bounds__(kBlock) void k_dtmax(StepArgs A, double a) {
+  long long v;
+  const BoxDev& b = *locate_box(A, kSpaceV, v);
+  double s = 0.0;
+  if (v < b.V) {
+    const int i = (int)(v % b.n[0]);
+    const int j = (int)((v / b.n[0]) % b.n[1]);
+    const int k = (int)(v / ((long long)b.n[0] * b.n[1]));
+    const long long id = ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
+    const double* U = A.Uin + b.soff + id;
+    const double gm1 = A.gamma - 1.0;
+    double rho = dmaxd(U[0], A.small_dens);
+    double re = U[5 * b.sstride] / (a * a);
+    double p = dmaxd(gm1 * re, A.small_pres);
+    double c = sqrt((A.gamma * p) / rho);
+    s = dmaxd(s, fabs(U[b.sstride] / (a * rho)) + c);
+    s = dmaxd(s, fabs(U[2 * b.sstride] / (a * rho)) + c);
+    s = dmaxd(s, fabs(U[3 * b.sstride] / (a * rho)) + c);
+  }
+  __shared__ double red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) s = dmaxd(s, __shfl_xor(s, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = dmaxd(m, red[w]);
+    if (m > 0.0) atomicMax(A.smax + b.gidx, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+hipError_t launch_dtmax(const StepArgs& a, double a_state, hipStream_t s) {
+  hipLaunchKernelGGL(k_dtmax, dim3(a.nblocks[kSpaceV]), dim3(kBlock), 0, s, a, a_state);
+  return hipGetLastError();
+}
+
+// dt = cfl a dx / s_max for each box (one thread per box)
+__global__ void k_dt_finalize(StepArgs A, double a, double cfl, double* dt, int nbox) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbox) return;
+  const BoxDev& b = A.table ? A.table[i] : A.single;
+  double smax = __longlong_as_double((long long)A.smax[b.gidx]);
+  dt[b.gidx] = ((cfl * a) * b.dx) / smax;
+}
+
+hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, double* dt_out,
+                              hipStream_t s) {
+  int n = a.table ? a.nb : 1;
+  hipLaunchKernelGGL(k_dt_finalize, dim3((n + 255) / 256), dim3(256), 0, s, a, a_state, cfl,
+                     dt_out, n);
+  return hipGetLastError();
+}
+
+// level time step: every entry becomes the minimum (one block)
+__global__ __launch_bounds__(1024) void k_min_dt(double* dt, int n) {
+  __shared__ double red[1024 / 64];
+  double m = 1.0 / 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = dmind(m, dt[i]);
+  for (int o = 32; o > 0; o >>= 1) m = dmind(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) r = dmind(r, red[w]);
+    red[0] = r;
+  }
+  __syncthreads();
+  double r = red[0];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dt[i] = r;
+}
+
+hipError_t launch_min_dt(double* dt, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_dt, dim3(1), dim3(1024), 0, s, dt, n);
+  return hipGetLastError();
+}
+
+// Ghost fill.  mode 0: periodic within the box.  mode 1: boxes tile a
+// periodic domain as a gx*gy*gz grid of equal boxes; `A.table` then points at
+// the group's boxes and `full` at the whole list in box order.
+__global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full, double* state,
+                                                 int ncomp, int mode, int gx, int gy, int gz) {
+  long long id;
+  const BoxDev& b = *locate_box(A, kSpaceP, id);
+  if (id >= b.P) return;
+  const int i = (int)(id % b.px) - b.ng;
+  const int j = (int)((id / b.px) % b.py) - b.ng;
+  const int k = (int)(id / ((long long)b.px * b.py)) - b.ng;
+  const bool valid = i >= 0 && i < b.n[0] && j >= 0 && j < b.n[1] && k >= 0 && k < b.n[2];
+  if (valid) return;
+  long long src;
+  if (mode == 0) {
+    const int si = ((i % b.n[0]) + b.n[0]) % b.n[0];
+    const int sj = ((j % b.n[1]) + b.n[1]) % b.n[1];
+    const int sk = ((k % b.n[2]) + b.n[2]) % b.n[2];
+    src = b.soff + ((long long)(sk + b.ng) * b.py + (sj + b.ng)) * b.px + (si + b.ng);
+  } else {
+    const int bx = b.gidx % gx, by = (b.gidx / gx) % gy, bz = b.gidx / (gx * gy);
+    const int NX = gx * b.n[0], NY = gy * b.n[1], NZ = gz * b.n[2];
+    const int X = ((bx * b.n[0] + i) % NX + NX) % NX;
+    const int Y = ((by * b.n[1] + j) % NY + NY) % NY;
+    const int Z = ((bz * b.n[2] + k) % NZ + NZ) % NZ;
+    const int sbx = X / b.n[0], sby = Y / b.n[1], sbz = Z / b.n[2];
+    const BoxDev& sb = full[(sbz * gy + sby) * gx + sbx];
+    const int si = X - sbx * b.n[0], sj = Y - sby * b.n[1], sk = Z - sbz * b.n[2];
+    src = sb.soff + ((long long)(sk + sb.ng) * sb.py + (sj + sb.ng)) * sb.px + (si + sb.ng);
+  }
+  const long long dst = b.soff + id;
+  for (int c = 0; c < ncomp; ++c) state[dst + c * b.sstride] = state[src + c * b.sstride];
+}
+
+hipError_t launch_fill_periodic(const StepArgs& a, const BoxDev* full, double* state, int ncomp,
+                                int mode, int gx, int gy, int gz, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(a.nblocks[kSpaceP]), dim3(kBlock), 0, s, a, full, state, ncomp,
+                     mode, gx, gy, gz);
+  return hipGetLastError();
+}
+
+}  // namespace nyx

@@ -1,0 +1,105 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point include/nyx_hydro.h declares, and rejects bad arguments on the host
+before anything is enqueued (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def nyx():
+    import paper_1301_4498_amd as nyx
+    if not os.path.exists(nyx._lib.LIB_PATH):
+        pytest.skip("HIP library not built")
+    return nyx
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nyx_hydro.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(nyx_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported(nyx):
+    L = nyx.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(nyx._lib.exported_symbols()) == names
+
+
+def test_defaults_and_status_strings(nyx):
+    p = nyx.default_params()
+    assert p.gamma == 5.0 / 3.0 and p.eta_dual == 1e-4 and p.riemann_maxiter == 20
+    assert p.cfl == 0.5 and p.precision == nyx.NYX_FP64
+    L = nyx.lib()
+    assert L.nyx_status_string(0) == b"ok"
+    assert b"overlap" in L.nyx_status_string(-4)
+
+
+def test_workspace_bytes(nyx):
+    p = nyx.default_params()
+    b = nyx.make_box((8, 6, 4), 4, 0.1)
+    P = 16 * 14 * 12
+    E = 10 * 8 * 6
+    al = lambda x: (x + 63) // 64 * 64
+    elems = al(6 * P) + al(E) + al(30 * E) + al(24 * E) + al(48 * E) + al(24 * E)
+    assert nyx.workspace_bytes(p, b) == 256 + 8 * elems
+    p.precision = nyx.NYX_MIXED
+    assert nyx.workspace_bytes(p, b) == 256 + 4 * elems
+
+
+def _step(nyx, p, b, sin=0x10000000, g=0x20000000, dt=1e-3, ao=0.5, an=0.51, sout=0x30000000,
+          ws=0x40000000, wsb=1 << 40):
+    L = nyx.lib()
+    return L.nyx_hydro_step(ctypes.byref(p) if p is not None else None,
+                            ctypes.byref(b) if b is not None else None, sin, g, dt, ao, an, sout,
+                            None, None, ws, wsb, None)
+
+
+def test_argument_errors(nyx):
+    p = nyx.default_params()
+    b = nyx.make_box((8, 8, 8), 4, 0.1)
+    assert _step(nyx, None, b) == -1
+    assert _step(nyx, p, None) == -1
+    assert _step(nyx, p, b, sin=None) == -1
+    assert _step(nyx, p, b, dt=0.0) == -3
+    assert _step(nyx, p, b, dt=float("nan")) == -3
+    assert _step(nyx, p, b, ao=-1.0) == -3
+    assert _step(nyx, p, b, an=0.0) == -3
+    # in/out overlap
+    assert _step(nyx, p, b, sout=0x10000008) == -4
+    # workspace too small / misaligned
+    assert _step(nyx, p, b, wsb=1024) == -7
+    assert _step(nyx, p, b, ws=0x40000010) == -7
+    for bad in ((7, 8, 8), (8, 0, 8), (8, 8, -2)):
+        assert _step(nyx, p, nyx.make_box(bad, 4, 0.1)) == -2
+    assert _step(nyx, p, nyx.make_box((8, 8, 8), 3, 0.1)) == -2
+    assert _step(nyx, p, nyx.make_box((8, 8, 8), 4, 0.0)) == -3
+    b2 = nyx.make_box((8, 8, 8), 4, 0.1)
+    b2.comp_stride = 10
+    assert _step(nyx, p, b2) == -2
+    for field, val in (("gamma", 1.0), ("riemann_maxiter", 0), ("precision", 7), ("cfl", 0.0),
+                       ("small_pres", 0.0), ("riemann", 5)):
+        q = nyx.default_params(**{field: val})
+        assert _step(nyx, q, b) == -3, field
+
+
+def test_batch_argument_errors(nyx):
+    L = nyx.lib()
+    p = nyx.default_params()
+    boxes = (nyx.Box * 2)(nyx.make_box((8, 8, 8), 4, 0.1), nyx.make_box((7, 8, 8), 4, 0.1))
+    mn, one = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.nyx_batch_workspace_bytes(ctypes.byref(p), 2, boxes, ctypes.byref(mn), ctypes.byref(one)) == -2
+    assert L.nyx_batch_workspace_bytes(ctypes.byref(p), 0, boxes, ctypes.byref(mn), ctypes.byref(one)) == -2
+    good = (nyx.Box * 2)(nyx.make_box((8, 8, 8), 4, 0.1), nyx.make_box((16, 8, 8), 4, 0.1))
+    assert L.nyx_batch_workspace_bytes(ctypes.byref(p), 2, good, ctypes.byref(mn), ctypes.byref(one)) == 0
+    assert 0 < mn.value < one.value
+    h = ctypes.c_void_p()
+    # a workspace smaller than the largest box is rejected before any upload
+    assert L.nyx_batch_create(ctypes.byref(p), 2, good, 0x40000000, 4096, None, ctypes.byref(h)) == -7
+    assert L.nyx_hydro_step_batched(None, 1, 1, 1, 0.5, 0.5, 2, None, None, None) == -1
