@@ -171,12 +171,30 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path would shard by boxes with a "
               "halo exchange; multi-GPU runs are not part of it)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "ms_per_copy": ms, "gbs_read_plus_write": 2 * nbytes / ms / 1e6}))
+        return
     import paper_1301_4498_amd as nyx
     from paper_1301_4498_amd import synth
     nyx.lib()

@@ -16,7 +16,10 @@ using namespace nyx;
 
 namespace {
 
-constexpr size_t kHeaderBytes = 256;  // per-box running maximum of the CFL reduction
+// Single-box workspace header: [0, 256) running maximum of the CFL reduction,
+// then kStatSlots x kStatFields partial counters; stage arrays follow.
+constexpr size_t kSlotBytes = sizeof(unsigned long long) * kStatSlots * kStatFields;
+constexpr size_t kHeaderBytes = 256 + (kSlotBytes + 255) / 256 * 256;
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -41,7 +44,7 @@ int check_box(const nyx_box* b) {
   if (b->ng < 4 || b->ng > 64) return NYX_E_SHAPE;
   long long P = 1;
   for (int d = 0; d < 3; ++d) P *= (long long)(b->n[d] + 2 * b->ng);
-  if (P > (1ll << 40)) return NYX_E_SHAPE;
+  if (P >= (1ll << 31)) return NYX_E_SHAPE;  // per-box indices are 32-bit
   if (b->comp_stride < P || b->grav_stride < P) return NYX_E_SHAPE;
   if (b->state_off < 0 || b->grav_off < 0) return NYX_E_SHAPE;
   if (!finite_pos(b->dx)) return NYX_E_PARAM;
@@ -208,10 +211,13 @@ int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_
   A.a_old = a_old;
   A.a_new = a_new;
   A.stats = stats;
+  A.slots = (unsigned long long*)((char*)workspace + 256);
   A.dt_next = dt_next;
   hipStream_t s = (hipStream_t)stream;
   if (dt_next && launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
+  if (stats && launch_zero_u64(A.slots, kStatSlots * kStatFields, s) != hipSuccess) return NYX_E_HIP;
   if (run_stages(p, A, s) != hipSuccess) return NYX_E_HIP;
+  if (stats && launch_stats_reduce(A.slots, stats, s) != hipSuccess) return NYX_E_HIP;
   if (dt_next && launch_dt_finalize(A, a_new, p->cfl, dt_next, s) != hipSuccess) return NYX_E_HIP;
   return NYX_OK;
 }
@@ -233,6 +239,7 @@ struct nyx_batch {
   std::vector<Group> groups;
   BoxDev* table;                 // device, nbox entries in box order
   unsigned long long* smax;      // device, nbox entries
+  unsigned long long* slots;     // device, partial counters
   void* stage;                   // device stage region
   size_t state_span;             // bytes spanned by the state of all boxes
 };
@@ -244,7 +251,7 @@ size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 // bytes of the table region for a plan with `ngroups` groups
 size_t table_bytes(int nbox, int ngroups) {
   return round256(sizeof(BoxDev) * (size_t)nbox) + round256(sizeof(int) * 3 * (size_t)(nbox + ngroups)) +
-         round256(sizeof(unsigned long long) * (size_t)nbox);
+         round256(sizeof(unsigned long long) * (size_t)nbox) + round256(kSlotBytes);
 }
 
 int check_boxes(const nyx_params* p, int nbox, const nyx_box* boxes) {
@@ -335,6 +342,7 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
   plan->table = (BoxDev*)w;
   int* pre_dev = (int*)(w + round256(sizeof(BoxDev) * (size_t)nbox));
   plan->smax = (unsigned long long*)((char*)pre_dev + round256(sizeof(int) * 3 * (size_t)(nbox + nbox)));
+  plan->slots = (unsigned long long*)((char*)plan->smax + round256(sizeof(unsigned long long) * (size_t)nbox));
   plan->stage = w + tbytes;
   plan->state_span = span;
   for (auto& g : plan->groups)
@@ -373,6 +381,7 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   A.nb = g.b1 - g.b0;
   A.work = plan->stage;
   A.smax = plan->smax;
+  A.slots = plan->slots;
   fill_physics(A, &plan->prm);
   return A;
 }
@@ -418,6 +427,8 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
   if (overlaps(state_in, plan->state_span, state_out, plan->state_span)) return NYX_E_ALIAS;
   hipStream_t s = (hipStream_t)stream;
   if (dt_next && launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
+  if (stats && launch_zero_u64(plan->slots, kStatSlots * kStatFields, s) != hipSuccess)
+    return NYX_E_HIP;
   for (const auto& g : plan->groups) {
     StepArgs A = group_args(plan, g);
     A.Uin = state_in;
@@ -430,6 +441,7 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
     A.dt_next = dt_next;
     if (run_stages(&plan->prm, A, s) != hipSuccess) return NYX_E_HIP;
   }
+  if (stats && launch_stats_reduce(plan->slots, stats, s) != hipSuccess) return NYX_E_HIP;
   if (dt_next &&
       launch_dt_finalize(all_boxes_args(plan), a_new, plan->prm.cfl, dt_next, s) != hipSuccess)
     return NYX_E_HIP;

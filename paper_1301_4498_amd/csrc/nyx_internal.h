@@ -10,7 +10,25 @@
 namespace nyx {
 
 constexpr int kBlock = 256;  // threads per block: 4 wavefronts of 64
-constexpr int kFaceVals = 8; // f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g
+// Stored per face: the Godunov state (rho_g, u_g normal, v_g, w_g transverse,
+// p_g) in the face's rotated frame; every flux is recomputed from it.
+constexpr int kGod = 5;
+// Device counters are accumulated per block into kStatSlots partial blocks
+// (block index modulo kStatSlots) and summed once per step.
+constexpr int kStatSlots = 64;
+constexpr int kStatFields = 10;
+
+// Division by a per-box invariant divisor d with a precomputed multiplier:
+// q = (umulhi(n, m) + n) >> l, exact for every n < 2^31.
+struct FastDiv {
+  unsigned d, m, l;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  unsigned l = 0;
+  while ((1ull << l) < d) ++l;
+  unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{d, (unsigned)m, l};
+}
 
 // One box as the kernels see it.  All offsets are element offsets.
 struct BoxDev {
@@ -25,6 +43,9 @@ struct BoxDev {
   int gidx;                // index of the box in the caller's list
   int pad_;
   double dx;
+  FastDiv dv[3][2];        // per Space: row length and plane size
+  unsigned sy[3];          // per Space: rows per plane
+  unsigned pad2_;
 };
 
 // Stage-array element count for a box (before alignment padding).
@@ -55,15 +76,52 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   d.w_prim = o; o += align_elems(6 * d.P);
   d.w_chi = o;  o += align_elems(d.E);
   d.w_edge = o; o += align_elems(30 * d.E);
-  d.w_f0 = o;   o += align_elems(3 * kFaceVals * d.E);
-  d.w_f1 = o;   o += align_elems(6 * kFaceVals * d.E);
-  d.w_f2 = o;   o += align_elems(3 * kFaceVals * d.E);
+  d.w_f0 = o;   o += align_elems(3 * kGod * d.E);
+  d.w_f1 = o;   o += align_elems(6 * kGod * d.E);
+  d.w_f2 = o;   o += align_elems(3 * kGod * d.E);
+  d.dv[0][0] = make_fastdiv((unsigned)d.px);
+  d.dv[0][1] = make_fastdiv((unsigned)d.px * (unsigned)d.py);
+  d.dv[1][0] = make_fastdiv((unsigned)d.ex);
+  d.dv[1][1] = make_fastdiv((unsigned)d.ex * (unsigned)d.ey);
+  d.dv[2][0] = make_fastdiv((unsigned)b.n[0]);
+  d.dv[2][1] = make_fastdiv((unsigned)b.n[0] * (unsigned)b.n[1]);
+  d.sy[0] = (unsigned)d.py;
+  d.sy[1] = (unsigned)d.ey;
+  d.sy[2] = (unsigned)b.n[1];
   if (out) *out = d;
   return o;
 }
 
 // Which cell range a launch walks.
 enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2 };
+
+#ifdef __HIPCC__
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Renumber them so that every XCD walks one contiguous
+// range of the (linearised) grid: neighbouring rows and planes of a stage
+// array are then read through the same L2.  A bijection for any grid size.
+__device__ __forceinline__ unsigned xcd_linear_block() {
+  const unsigned n = gridDim.x * gridDim.y;
+  const unsigned lin = blockIdx.x + blockIdx.y * gridDim.x;
+  const unsigned q = n >> 3, r = n & 7;
+  const unsigned xcd = lin & 7, pos = lin >> 3;
+  return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+}
+
+__device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
+  return (__umulhi(n, f.m) + n) >> f.l;
+}
+// (x, y, z) of flat index idx < 2^31 in the given Space of a box
+__device__ __forceinline__ void space_coords(const BoxDev& b, int space, unsigned idx, int* c) {
+  const FastDiv& r = b.dv[space][0];
+  const FastDiv& pl = b.dv[space][1];
+  unsigned q1 = fast_div(idx, r);
+  unsigned q2 = fast_div(idx, pl);
+  c[0] = (int)(idx - q1 * r.d);
+  c[1] = (int)(q1 - q2 * b.sy[space]);
+  c[2] = (int)q2;
+}
+#endif
 
 // Launch-wide arguments of a step.
 struct StepArgs {
@@ -85,6 +143,7 @@ struct StepArgs {
   double gamma, eta, small_dens, small_pres, riemann_tol, cfl;
   int maxiter;
   nyx_stats* stats;
+  unsigned long long* slots;  // kStatSlots x kStatFields partial counters (when stats)
   double* dt_next;
   hipEvent_t* ev;          // kStages + 1 events recorded around the stages, or nullptr
 };
@@ -105,6 +164,7 @@ hipError_t launch_dtmax(const StepArgs& a, double a_state, hipStream_t s);
 hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, double* dt_out,
                               hipStream_t s);
 hipError_t launch_min_dt(double* dt, int n, hipStream_t s);
+hipError_t launch_stats_reduce(const unsigned long long* slots, nyx_stats* stats, hipStream_t s);
 hipError_t launch_fill_periodic(const StepArgs& a, const BoxDev* full, double* state, int ncomp,
                                 int mode, int gx, int gy, int gz, hipStream_t s);
 

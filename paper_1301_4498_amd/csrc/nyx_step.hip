@@ -19,7 +19,10 @@
 //   update  valid cells        flux differences, S_e, S_g^n, corrector, sync,
 //                              optional CFL maximum of the new state
 // Stage arrays are component-major over the [-1,n]^3 cell range (x fastest),
-// so every load and store of a wavefront is contiguous.
+// so every load and store of a wavefront is contiguous.  A face stores only
+// its Godunov state (5 values); fluxes are recomputed from it where needed
+// with the same expressions, which keeps the HBM traffic of the Riemann
+// stages low without changing a single bit of the result.
 #include <hip/hip_runtime.h>
 
 #include "nyx_internal.h"
@@ -52,19 +55,24 @@ __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
 // ---------------------------------------------------------------------------
 struct Loc {
   const BoxDev* bd;
-  long long idx;  // cell index within the box's space
+  unsigned idx;  // cell index within the box's space (< 2^31)
 };
 
-__device__ __forceinline__ Loc locate(const StepArgs& A, int space) {
+// Returns the box and cell index of this thread; *ylane receives the
+// grid-y coordinate (direction or direction pair) after XCD renumbering.
+__device__ __forceinline__ Loc locate(const StepArgs& A, int space, int* ylane = nullptr) {
   Loc L;
-  long long lb;
+  unsigned lb;
+  const unsigned lin = xcd_linear_block();
+  const unsigned bx = lin % gridDim.x;
+  if (ylane) *ylane = (int)(lin / gridDim.x);
   if (A.table == nullptr) {
     L.bd = &A.single;
-    lb = blockIdx.x;
+    lb = bx;
   } else {
     const int* pre = A.prefix[space];
-    int lo = 0, hi = A.nb;  // find b with pre[b] <= blockIdx.x < pre[b+1]
-    int x = (int)blockIdx.x;
+    int lo = 0, hi = A.nb;  // find b with pre[b] <= bx < pre[b+1]
+    int x = (int)bx;
     while (hi - lo > 1) {
       int mid = (lo + hi) >> 1;
       if (pre[mid] <= x) lo = mid;
@@ -73,7 +81,7 @@ __device__ __forceinline__ Loc locate(const StepArgs& A, int space) {
     L.bd = A.table + lo;
     lb = x - pre[lo];
   }
-  L.idx = lb * kBlock + threadIdx.x;
+  L.idx = lb * (unsigned)kBlock + threadIdx.x;
   return L;
 }
 
@@ -103,13 +111,28 @@ __device__ __forceinline__ StepC step_consts(const StepArgs& A, const BoxDev& b)
 // ---------------------------------------------------------------------------
 // counters: one atomic per wavefront
 // ---------------------------------------------------------------------------
+enum StatField {
+  kNonfinite = 0, kNegDens, kNegEint, kFloorHits, kTransReverts, kSyncEfromE,
+  kRiemannIters, kRiemannCalls, kMlpUsed, kMlpFallback
+};
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ __forceinline__ void count(unsigned long long* dst, unsigned v) {
+// Block-wide sum added into one of kStatSlots partial counter blocks; every
+// thread of the block must call it (it synchronises the block).
+__device__ __forceinline__ void count(const StepArgs& A, int field, unsigned v) {
+  __shared__ unsigned red[kBlock / 64];
   v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = 0;
+    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+    const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % kStatSlots;
+    if (t) atomicAdd(A.slots + slot * kStatFields + field, (unsigned long long)t);
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -140,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
     q[4 * b.P] = (real)p;
     q[5 * b.P] = (real)c;
   }
-  if (A.stats) count(&A.stats->floor_hits, floors);
+  if (A.stats) count(A, kFloorHits, floors);
 }
 
 // padded index of the cell at E-array coordinates (ie, je, ke) (cell ie - 1)
@@ -165,9 +188,9 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
   const BoxDev& b = *L.bd;
   if (L.idx >= b.E) return;
   const long long e = L.idx;
-  const int ie = (int)(e % b.ex);
-  const int je = (int)((e / b.ex) % b.ey);
-  const int ke = (int)(e / ((long long)b.ex * b.ey));
+  int ec[3];
+  space_coords(b, kSpaceE, L.idx, ec);
+  const int ie = ec[0], je = ec[1], ke = ec[2];
   const real* prim = (const real*)A.work + b.w_prim;
   const real* P = prim + 4 * b.P;
   const real sp = (real)A.small_pres;
@@ -266,11 +289,21 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
     bool in = SIDE > 0 ? (lam[w] > (real)0) : (lam[w] < (real)0);
     for (int k = 0; k < 3; ++k) D[w][k] = in ? ref[k] - I[w][k] : (real)0;
   }
+#if defined(NYX_PREC_MIXED)
+  const real ic = (real)1 / c;
+  const real icsq = ic * ic;
+  real am = (real)0.5 * (D[0][2] * icsq - (rho * D[0][1]) * ic);
+  real ap = (real)0.5 * (D[2][2] * icsq + (rho * D[2][1]) * ic);
+  real a0 = D[1][0] - D[1][2] * icsq;
+  out[0] = ref[0] - ((am + a0) + ap);
+  out[nv] = ref[1] - (c * ((real)1 / rho)) * (ap - am);
+#else
   real am = (real)0.5 * (D[0][2] / csq - (rho * D[0][1]) / c);
   real ap = (real)0.5 * (D[2][2] / csq + (rho * D[2][1]) / c);
   real a0 = D[1][0] - D[1][2] / csq;
   out[0] = ref[0] - ((am + a0) + ap);
   out[nv] = ref[1] - (c / rho) * (ap - am);
+#endif
   out[4] = ref[2] - csq * (am + ap);
   const bool c_in = SIDE > 0 ? (lam[1] > (real)0) : (lam[1] < (real)0);
   out[t1] = c_in ? (SIDE > 0 ? avg_hi(qe[t1], dq[t1], q6[t1], sig[1])
@@ -282,15 +315,15 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
 }
 
 __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
-  Loc L = locate(A, kSpaceE);
+  int d;
+  Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
-  const int d = blockIdx.y;
   unsigned floors = 0;
   if (L.idx < b.E) {
     const long long e = L.idx;
-    const int ie = (int)(e % b.ex);
-    const int je = (int)((e / b.ex) % b.ey);
-    const int ke = (int)(e / ((long long)b.ex * b.ey));
+    int ec[3];
+    space_coords(b, kSpaceE, L.idx, ec);
+    const int ie = ec[0], je = ec[1], ke = ec[2];
     const StepC C = step_consts(A, b);
     const real* prim = (const real*)A.work + b.w_prim;
     const long long c0 = pidx_e(b, ie, je, ke);
@@ -335,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
       W[((d * 2 + 1) * 5 + v) * b.E] = hi[v];
     }
   }
-  if (A.stats) count(&A.stats->floor_hits, floors);
+  if (A.stats) count(A, kFloorHits, floors);
 }
 
 // ---------------------------------------------------------------------------
@@ -345,6 +378,127 @@ struct RiemannOut {
   double r, u, v, w, p;
   int iters;
 };
+
+#if defined(NYX_PREC_MIXED)
+// FP64 reciprocal and reciprocal square root from the hardware estimates
+// refined by two Newton-Raphson steps each (relative error near 1 ulp, not
+// correctly rounded).  Arguments are positive and finite where used.
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = x * y;
+  double r = fma(-h, y, 1.0);
+  y = fma(0.5 * y, r, y);
+  h = x * y;
+  r = fma(-h, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+
+// The same two-shock Newton iteration, rearranged so that each iteration
+// needs one reciprocal and two reciprocal square roots: with
+// X_K = W_K^2 = C_K + (gamma+1)/2 rho_K (p - p_K) and w_K = 1/W_K,
+//   u*_L = u_L - (p - p_L) w_L,  u*_R = u_R + (p - p_R) w_R,
+//   1/Z_K = (X_K + C_K) w_K^3 / 2,
+//   p' = p - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
+//   u* = (u*_L/Z_R' ...) = (u*_L (1/Z_R) + u*_R (1/Z_L)) / (1/Z_L + 1/Z_R),
+//   1/rho*_K = 1/rho_K - (p* - p_K) w_K^2.
+__device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
+                                                const double* qR) {
+  const double gam = A.gamma;
+  const double g2 = 0.5 * (gam + 1.0);
+  const double sp = A.small_pres;
+  const double rl = qL[0], ul = qL[1], pl = qL[4];
+  const double rr = qR[0], ur = qR[1], pr = qR[4];
+  const double CL = (gam * pl) * rl;
+  const double CR = (gam * pr) * rr;
+  const double W0L = CL * rsq64(CL), W0R = CR * rsq64(CR);
+  double p = ((W0R * pl + W0L * pr) + (W0L * W0R) * (ul - ur)) * rcp64(W0L + W0R);
+  p = vmax(p, sp);
+  const double gl = g2 * rl, gr = g2 * rr;
+  int it = 0;
+  double XL, XR, wL, wR, usL, usR, zL, zR;
+  while (it < A.maxiter) {
+    XL = CL + gl * (p - pl);
+    XR = CR + gr * (p - pr);
+    wL = rsq64(XL);
+    wR = rsq64(XR);
+    usL = ul - (p - pl) * wL;
+    usR = ur + (p - pr) * wR;
+    zL = 0.5 * (XL + CL) * (wL * wL * wL);
+    zR = 0.5 * (XR + CR) * (wR * wR * wR);
+    double pn = p - (usR - usL) * rcp64(zL + zR);
+    pn = vmax(pn, sp);
+    ++it;
+    bool conv = fabs(pn - p) <= A.riemann_tol * pn;
+    p = pn;
+    if (conv) break;
+  }
+  XL = CL + gl * (p - pl);
+  XR = CR + gr * (p - pr);
+  wL = rsq64(XL);
+  wR = rsq64(XR);
+  usL = ul - (p - pl) * wL;
+  usR = ur + (p - pr) * wR;
+  zL = 0.5 * (XL + CL) * (wL * wL * wL);
+  zR = 0.5 * (XR + CR) * (wR * wR * wR);
+  const double ustar = (usL * zR + usR * zL) * rcp64(zL + zR);
+  const double pstar = p;
+  const double irl = rcp64(rl), irr = rcp64(rr);
+  const double DL = irl - (pstar - pl) * (wL * wL);
+  const double DR = irr - (pstar - pr) * (wR * wR);
+  const double rsL = rcp64(DL), rsR = rcp64(DR);
+  double shdL, stlL, shdR, stlR;
+  if (pstar >= pl) { shdL = ul - (XL * wL) * irl; stlL = shdL; }
+  else {
+    const double x0 = (gam * pl) * irl, x1 = (gam * pstar) * DL;
+    shdL = ul - x0 * rsq64(x0);
+    stlL = ustar - x1 * rsq64(x1);
+  }
+  if (pstar >= pr) { shdR = ur + (XR * wR) * irr; stlR = shdR; }
+  else {
+    const double x0 = (gam * pr) * irr, x1 = (gam * pstar) * DR;
+    shdR = ur + x0 * rsq64(x0);
+    stlR = ustar + x1 * rsq64(x1);
+  }
+  double sL0, sL1, sL2, sR0, sR1, sR2;
+  if (shdL >= 0.0) { sL0 = rl; sL1 = ul; sL2 = pl; }
+  else if (stlL <= 0.0) { sL0 = rsL; sL1 = ustar; sL2 = pstar; }
+  else {
+    double f = (0.0 - shdL) * rcp64(stlL - shdL);
+    sL0 = rl + f * (rsL - rl);
+    sL1 = ul + f * (ustar - ul);
+    sL2 = pl + f * (pstar - pl);
+  }
+  if (shdR <= 0.0) { sR0 = rr; sR1 = ur; sR2 = pr; }
+  else if (stlR >= 0.0) { sR0 = rsR; sR1 = ustar; sR2 = pstar; }
+  else {
+    double f = (0.0 - shdR) * rcp64(stlR - shdR);
+    sR0 = rr + f * (rsR - rr);
+    sR1 = ur + f * (ustar - ur);
+    sR2 = pr + f * (pstar - pr);
+  }
+  RiemannOut o;
+  if (ustar > 0.0) {
+    o.r = sL0; o.u = sL1; o.p = sL2; o.v = qL[2]; o.w = qL[3];
+  } else if (ustar < 0.0) {
+    o.r = sR0; o.u = sR1; o.p = sR2; o.v = qR[2]; o.w = qR[3];
+  } else {
+    o.r = 0.5 * (sL0 + sR0);
+    o.u = 0.5 * (sL1 + sR1);
+    o.p = 0.5 * (sL2 + sR2);
+    o.v = 0.5 * (qL[2] + qR[2]);
+    o.w = 0.5 * (qL[3] + qR[3]);
+  }
+  o.iters = it;
+  return o;
+}
+#else
 
 __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
                                                 const double* qR) {
@@ -423,11 +577,23 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
   o.iters = it;
   return o;
 }
+#endif  // NYX_PREC_MIXED
 
-// O6: lab-frame fluxes of a d-face from the Godunov state (flux arithmetic in real)
-__device__ __forceinline__ void face_flux(double gamma, int d, const RiemannOut& g, real* f) {
+// Godunov state of a d-face as stored (rotated frame: rho, u_n, v_t1, w_t2, p)
+__device__ __forceinline__ void store_god(real* G, long long E, const RiemannOut& g) {
+  G[0] = (real)g.r;
+  G[E] = (real)g.u;
+  G[2 * E] = (real)g.v;
+  G[3 * E] = (real)g.w;
+  G[4 * E] = (real)g.p;
+}
+
+// O6: lab-frame fluxes of a d-face from its stored Godunov state (flux
+// arithmetic in real): f = (f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g).
+__device__ __forceinline__ void face_flux(double gamma, int d, const real* G, long long E,
+                                          real* f) {
   const real gm1 = (real)(gamma - 1.0);
-  const real r = (real)g.r, u = (real)g.u, v = (real)g.v, w = (real)g.w, p = (real)g.p;
+  const real r = G[0], u = G[E], v = G[2 * E], w = G[3 * E], p = G[4 * E];
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const real ru = r * u;
   f[0] = ru;
@@ -450,10 +616,8 @@ __device__ __forceinline__ RiemannOut solve_face(const StepArgs& A, int d, const
   return two_shock(A, qL, qR);
 }
 
-__device__ __forceinline__ void e_coords(const BoxDev& b, long long e, int* c) {
-  c[0] = (int)(e % b.ex);
-  c[1] = (int)((e / b.ex) % b.ey);
-  c[2] = (int)(e / ((long long)b.ex * b.ey));
+__device__ __forceinline__ void e_coords(const BoxDev& b, unsigned e, int* c) {
+  space_coords(b, kSpaceE, e, c);
 }
 __device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
   return d == 0 ? 1 : (d == 1 ? (long long)b.ex : (long long)b.ex * b.ey);
@@ -463,14 +627,14 @@ __device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
 // stage 4: Riemann on stage-0 states, faces between cells of [-1, n]
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
-  Loc L = locate(A, kSpaceE);
+  int d;
+  Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
-  const int d = blockIdx.y;
   unsigned calls = 0, iters = 0;
   if (L.idx < b.E) {
     const long long e = L.idx;
     int c[3];
-    e_coords(b, e, c);
+    e_coords(b, L.idx, c);
     if (c[d] >= 1) {  // face f = c[d] - 1 in [0, n_d]
       const long long eL = e - e_stride(b, d);
       const real* W = (const real*)A.work + b.w_edge;
@@ -482,25 +646,23 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
       RiemannOut g = solve_face(A, d, ql, qr);
       calls = 1;
       iters = g.iters;
-      real f[kFaceVals];
-      face_flux(A.gamma, d, g, f);
-      real* F = (real*)A.work + b.w_f0 + (long long)d * kFaceVals * b.E + e;
-      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+      store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E + e, b.E, g);
     }
   }
   if (A.stats) {
-    count(&A.stats->riemann_calls, calls);
-    count(&A.stats->riemann_iters, iters);
+    count(A, kRiemannCalls, calls);
+    count(A, kRiemannIters, iters);
   }
 }
 
 // ---------------------------------------------------------------------------
-// O7: transverse correction of a lab-frame edge state (FP64 arithmetic)
+// O7: transverse correction of a lab-frame edge state (FP64 arithmetic).
+// fm[k], fp[k]: lab-frame fluxes at the low and high t_k-faces of the cell.
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q,
-                                              const real* const* fm, const real* const* fp,
-                                              long long st, double kap, double* out) {
+                                              const real (*fm)[8], const real (*fp)[8],
+                                              double kap, double* out) {
   const double gm1 = A.gamma - 1.0;
   const double rho = q[0], ux = q[1], uy = q[2], uz = q[3], p = q[4];
   double U[5];
@@ -508,32 +670,45 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
   U[1] = rho * ux;
   U[2] = rho * uy;
   U[3] = rho * uz;
-  U[4] = p / gm1 + (0.5 * rho) * ((ux * ux + uy * uy) + uz * uz);
+#if defined(NYX_PREC_MIXED)
+  const double Ue = p * (1.0 / gm1);
+#else
   const double Ue = p / gm1;
+#endif
+  U[4] = Ue + (0.5 * rho) * ((ux * ux + uy * uy) + uz * uz);
   double Dc[5];
   for (int c = 0; c < 5; ++c) {
-    Dc[c] = (double)fp[0][c * st] - (double)fm[0][c * st];
-    if (NT == 2) Dc[c] = Dc[c] + ((double)fp[1][c * st] - (double)fm[1][c * st]);
+    Dc[c] = (double)fp[0][c] - (double)fm[0][c];
+    if (NT == 2) Dc[c] = Dc[c] + ((double)fp[1][c] - (double)fm[1][c]);
   }
-  double De = ((double)fp[0][5 * st] - (double)fm[0][5 * st]) +
-              (0.5 * ((double)fp[0][6 * st] + (double)fm[0][6 * st])) *
-                  ((double)fp[0][7 * st] - (double)fm[0][7 * st]);
+  double De = ((double)fp[0][5] - (double)fm[0][5]) +
+              (0.5 * ((double)fp[0][6] + (double)fm[0][6])) * ((double)fp[0][7] - (double)fm[0][7]);
   if (NT == 2)
-    De = De + (((double)fp[1][5 * st] - (double)fm[1][5 * st]) +
-               (0.5 * ((double)fp[1][6 * st] + (double)fm[1][6 * st])) *
-                   ((double)fp[1][7 * st] - (double)fm[1][7 * st]));
+    De = De + (((double)fp[1][5] - (double)fm[1][5]) +
+               (0.5 * ((double)fp[1][6] + (double)fm[1][6])) * ((double)fp[1][7] - (double)fm[1][7]));
   double Un[5];
   for (int c = 0; c < 5; ++c) Un[c] = U[c] - kap * Dc[c];
   const double Uen = Ue - kap * De;
+#if defined(NYX_PREC_MIXED)
+  const double iU0 = 1.0 / Un[0];
+  const double ke = (0.5 * ((Un[1] * Un[1] + Un[2] * Un[2]) + Un[3] * Un[3])) * iU0;
+#else
   const double ke = (0.5 * ((Un[1] * Un[1] + Un[2] * Un[2]) + Un[3] * Un[3])) / Un[0];
+#endif
   double pn;
   if (Un[4] - ke > A.eta * Un[4]) pn = gm1 * (Un[4] - ke);
   else pn = gm1 * Uen;
   double r[5];
   r[0] = Un[0];
+#if defined(NYX_PREC_MIXED)
+  r[1] = Un[1] * iU0;
+  r[2] = Un[2] * iU0;
+  r[3] = Un[3] * iU0;
+#else
   r[1] = Un[1] / Un[0];
   r[2] = Un[2] / Un[0];
   r[3] = Un[3] / Un[0];
+#endif
   r[4] = pn;
   bool ok = (r[0] > 0.0) && (r[4] > 0.0);
   for (int c = 0; c < 5; ++c) ok = ok && isfinite(r[c]);
@@ -548,47 +723,56 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
 __device__ __forceinline__ int pair_index(int d, int t) { return d * 2 + (t == (d + 1) % 3 ? 0 : 1); }
 
 // ---------------------------------------------------------------------------
-// stage 5: d-states corrected by stage-0 t-fluxes, Riemann -> F^{d|t}
+// stage 5: for one direction d, the d-states of a face's two cells corrected
+// by stage-0 t-fluxes (t = t1 and t = t2), Riemann -> F^{d|t1}, F^{d|t2}.
+// Both pairs share the loads of the d-states.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
-  Loc L = locate(A, kSpaceE);
+  int d;
+  Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
-  const int pq = blockIdx.y;
-  const int d = pq >> 1;
-  const int t = (d + 1 + (pq & 1)) % 3;
   unsigned calls = 0, iters = 0, reverts = 0;
   if (L.idx < b.E) {
     const long long e = L.idx;
     int c[3];
-    e_coords(b, e, c);
-    if (c[d] >= 1 && c[t] >= 1 && c[t] <= b.n[t]) {
+    e_coords(b, L.idx, c);
+    const int ts[2] = {(d + 1) % 3, (d + 2) % 3};
+    const bool want[2] = {c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
+                          c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
+    if (c[d] >= 1 && (want[0] || want[1])) {
       const StepC C = step_consts(A, b);
-      const long long sdd = e_stride(b, d), stt = e_stride(b, t);
+      const long long sdd = e_stride(b, d);
       const real* W = (const real*)A.work + b.w_edge;
-      const real* F0t = (const real*)A.work + b.w_f0 + (long long)t * kFaceVals * b.E;
-      double qs[2][5];
+      double q[2][5];
       for (int s = 0; s < 2; ++s) {
         const long long ec = s == 0 ? e - sdd : e;
         const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
-        double q[5];
-        for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
-        const real* fm[1] = {F0t + ec};
-        const real* fp[1] = {F0t + ec + stt};
-        reverts += trans_correct<1>(A, q, fm, fp, b.E, C.kap1, qs[s]) ? 1u : 0u;
+        for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
       }
-      RiemannOut g = solve_face(A, d, qs[0], qs[1]);
-      calls = 1;
-      iters = g.iters;
-      real f[kFaceVals];
-      face_flux(A.gamma, d, g, f);
-      real* F = (real*)A.work + b.w_f1 + (long long)pq * kFaceVals * b.E + e;
-      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+      for (int k = 0; k < 2; ++k) {
+        if (!want[k]) continue;
+        const int t = ts[k];
+        const long long stt = e_stride(b, t);
+        const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
+        double qs[2][5];
+        for (int s = 0; s < 2; ++s) {
+          const long long ec = s == 0 ? e - sdd : e;
+          real fm[1][8], fp[1][8];
+          face_flux(A.gamma, t, G0 + ec, b.E, fm[0]);
+          face_flux(A.gamma, t, G0 + ec + stt, b.E, fp[0]);
+          reverts += trans_correct<1>(A, q[s], fm, fp, C.kap1, qs[s]) ? 1u : 0u;
+        }
+        RiemannOut g = solve_face(A, d, qs[0], qs[1]);
+        calls += 1;
+        iters += g.iters;
+        store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, t) * kGod * b.E + e, b.E, g);
+      }
     }
   }
   if (A.stats) {
-    count(&A.stats->riemann_calls, calls);
-    count(&A.stats->riemann_iters, iters);
-    count(&A.stats->trans_reverts, reverts);
+    count(A, kRiemannCalls, calls);
+    count(A, kRiemannIters, iters);
+    count(A, kTransReverts, reverts);
   }
 }
 
@@ -596,50 +780,55 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
 // stage 6: final d-states and comoving fluxes on valid faces
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
-  Loc L = locate(A, kSpaceE);
+  int d;
+  Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
-  const int d = blockIdx.y;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   unsigned calls = 0, iters = 0, reverts = 0;
   if (L.idx < b.E) {
     const long long e = L.idx;
     int c[3];
-    e_coords(b, e, c);
+    e_coords(b, L.idx, c);
     if (c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 && c[t2] <= b.n[t2]) {
       const StepC C = step_consts(A, b);
       const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
       const real* W = (const real*)A.work + b.w_edge;
-      const real* F1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kFaceVals * b.E;
-      const real* F1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kFaceVals * b.E;
+      const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
+      const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
       double qs[2][5];
       for (int s = 0; s < 2; ++s) {
         const long long ec = s == 0 ? e - sdd : e;
         const int side = s == 0 ? 1 : 0;
         double q[5];
         for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
-        const real* fm[2] = {F1a + ec, F1b + ec};
-        const real* fp[2] = {F1a + ec + s1, F1b + ec + s2};
-        reverts += trans_correct<2>(A, q, fm, fp, b.E, C.kap2, qs[s]) ? 1u : 0u;
+        real fm[2][8], fp[2][8];
+        face_flux(A.gamma, t1, G1a + ec, b.E, fm[0]);       // t1-flux corrected by t2
+        face_flux(A.gamma, t1, G1a + ec + s1, b.E, fp[0]);
+        face_flux(A.gamma, t2, G1b + ec, b.E, fm[1]);       // t2-flux corrected by t1
+        face_flux(A.gamma, t2, G1b + ec + s2, b.E, fp[1]);
+        reverts += trans_correct<2>(A, q, fm, fp, C.kap2, qs[s]) ? 1u : 0u;
       }
       RiemannOut g = solve_face(A, d, qs[0], qs[1]);
       calls = 1;
       iters = g.iters;
-      real f[kFaceVals];
-      face_flux(A.gamma, d, g, f);
-      // O9: comoving factors of the flux vector (Sec. 3.2)
-      const real ah = (real)C.a_h;
-      f[0] = f[0] / ah;
-      f[4] = ah * f[4];
-      f[5] = ah * f[5];
-      real* F = (real*)A.work + b.w_f2 + (long long)d * kFaceVals * b.E + e;
-      for (int v = 0; v < kFaceVals; ++v) F[v * b.E] = f[v];
+      store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E + e, b.E, g);
     }
   }
   if (A.stats) {
-    count(&A.stats->riemann_calls, calls);
-    count(&A.stats->riemann_iters, iters);
-    count(&A.stats->trans_reverts, reverts);
+    count(A, kRiemannCalls, calls);
+    count(A, kRiemannIters, iters);
+    count(A, kTransReverts, reverts);
   }
+}
+
+// O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
+// F_m = f_m, F_E = a_h f_E, F_e = a_h f_e; p_g and u_g kept for S_e.
+__device__ __forceinline__ void final_flux(double gamma, int d, const real* G, long long E,
+                                           real ah, real* f) {
+  face_flux(gamma, d, G, E, f);
+  f[0] = f[0] / ah;
+  f[4] = ah * f[4];
+  f[5] = ah * f[5];
 }
 
 // ---------------------------------------------------------------------------
@@ -680,24 +869,26 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
   unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
   double smax = 0.0;
   if (L.idx < b.V) {
-    const long long v = L.idx;
-    const int i = (int)(v % b.n[0]);
-    const int j = (int)((v / b.n[0]) % b.n[1]);
-    const int k = (int)(v / ((long long)b.n[0] * b.n[1]));
+    int vc[3];
+    space_coords(b, kSpaceV, L.idx, vc);
+    const int i = vc[0], j = vc[1], k = vc[2];
     const StepC C = step_consts(A, b);
     const long long e = ((long long)(k + 1) * b.ey + (j + 1)) * b.ex + (i + 1);
-    const real* F2 = (const real*)A.work + b.w_f2;
+    const real* G2 = (const real*)A.work + b.w_f2;
+    const real ah = (real)C.a_h;
     double D[6];
     double Pi = 0.0;
     for (int d = 0; d < 3; ++d) {
-      const real* F = F2 + (long long)d * kFaceVals * b.E;
+      const real* G = G2 + (long long)d * kGod * b.E;
       const long long eu = e + e_stride(b, d);
+      real fl[8], fh[8];
+      final_flux(A.gamma, d, G + e, b.E, ah, fl);
+      final_flux(A.gamma, d, G + eu, b.E, ah, fh);
       for (int c = 0; c < 6; ++c) {
-        double dF = (double)F[c * b.E + eu] - (double)F[c * b.E + e];
+        double dF = (double)fh[c] - (double)fl[c];
         D[c] = (d == 0) ? dF : D[c] + dF;
       }
-      double pd = (0.5 * ((double)F[6 * b.E + eu] + (double)F[6 * b.E + e])) *
-                  ((double)F[7 * b.E + eu] - (double)F[7 * b.E + e]);
+      double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
       Pi = (d == 0) ? pd : Pi + pd;
     }
     const long long id = ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
@@ -743,10 +934,10 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     if (A.dt_next) smax = cell_speed(A, s0, nm[0], nm[1], nm[2], ne, A.a_new);
   }
   if (A.stats) {
-    count(&A.stats->sync_E_from_e, nsync);
-    count(&A.stats->nonfinite, nnf);
-    count(&A.stats->neg_dens, nnd);
-    count(&A.stats->neg_eint, nne);
+    count(A, kSyncEfromE, nsync);
+    count(A, kNonfinite, nnf);
+    count(A, kNegDens, nnd);
+    count(A, kNegEint, nne);
   }
   if (A.dt_next) block_max_atomic(smax, A.smax + b.gidx);
 }
@@ -765,7 +956,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   mark(3);
   hipLaunchKernelGGL(k_riem0, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(4);
-  hipLaunchKernelGGL(k_riem1, dim3(a.nblocks[kSpaceE], 6), blk, 0, s, a);
+  hipLaunchKernelGGL(k_riem1, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(5);
   hipLaunchKernelGGL(k_riem2, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(6);

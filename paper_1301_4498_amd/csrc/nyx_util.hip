@@ -21,13 +21,14 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
 }
 
 __device__ __forceinline__ const BoxDev* locate_box(const StepArgs& A, int space, long long& idx) {
+  const unsigned bx = xcd_linear_block();  // 1-D grids here
   if (A.table == nullptr) {
-    idx = (long long)blockIdx.x * kBlock + threadIdx.x;
+    idx = (long long)bx * kBlock + threadIdx.x;
     return &A.single;
   }
   const int* pre = A.prefix[space];
   int lo = 0, hi = A.nb;
-  int x = (int)blockIdx.x;
+  int x = (int)bx;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
     if (pre[mid] <= x) lo = mid;
@@ -43,9 +44,9 @@ __global__ __launch_bounds__(kBlock) void k_dtmax(StepArgs A, double a) {
   const BoxDev& b = *locate_box(A, kSpaceV, v);
   double s = 0.0;
   if (v < b.V) {
-    const int i = (int)(v % b.n[0]);
-    const int j = (int)((v / b.n[0]) % b.n[1]);
-    const int k = (int)(v / ((long long)b.n[0] * b.n[1]));
+    int vc[3];
+    space_coords(b, kSpaceV, (unsigned)v, vc);
+    const int i = vc[0], j = vc[1], k = vc[2];
     const long long id = ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
     const double* U = A.Uin + b.soff + id;
     const double gm1 = A.gamma - 1.0;
@@ -90,6 +91,20 @@ hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, dou
   return hipGetLastError();
 }
 
+// sum the per-slot partial counters into the caller's nyx_stats
+__global__ void k_stats_reduce(const unsigned long long* slots, unsigned long long* stats) {
+  const int f = threadIdx.x;
+  if (f >= kStatFields) return;
+  unsigned long long t = 0;
+  for (int i = 0; i < kStatSlots; ++i) t += slots[i * kStatFields + f];
+  if (t) atomicAdd(stats + f, t);
+}
+
+hipError_t launch_stats_reduce(const unsigned long long* slots, nyx_stats* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(64), 0, s, slots, (unsigned long long*)stats);
+  return hipGetLastError();
+}
+
 // level time step: every entry becomes the minimum (one block)
 __global__ __launch_bounds__(1024) void k_min_dt(double* dt, int n) {
   __shared__ double red[1024 / 64];
@@ -121,9 +136,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full,
   long long id;
   const BoxDev& b = *locate_box(A, kSpaceP, id);
   if (id >= b.P) return;
-  const int i = (int)(id % b.px) - b.ng;
-  const int j = (int)((id / b.px) % b.py) - b.ng;
-  const int k = (int)(id / ((long long)b.px * b.py)) - b.ng;
+  int pc[3];
+  space_coords(b, kSpaceP, (unsigned)id, pc);
+  const int i = pc[0] - b.ng, j = pc[1] - b.ng, k = pc[2] - b.ng;
   const bool valid = i >= 0 && i < b.n[0] && j >= 0 && j < b.n[1] && k >= 0 && k < b.n[2];
   if (valid) return;
   long long src;

@@ -47,10 +47,13 @@ def test_workspace_bytes(nyx):
     P = 16 * 14 * 12
     E = 10 * 8 * 6
     al = lambda x: (x + 63) // 64 * 64
-    elems = al(6 * P) + al(E) + al(30 * E) + al(24 * E) + al(48 * E) + al(24 * E)
-    assert nyx.workspace_bytes(p, b) == 256 + 8 * elems
+    # primitives, chi, edge states, then the Godunov states of the three
+    # Riemann stages (5 values per face)
+    elems = al(6 * P) + al(E) + al(30 * E) + al(15 * E) + al(30 * E) + al(15 * E)
+    header = 256 + 64 * 10 * 8  # CFL maximum, then partial counters
+    assert nyx.workspace_bytes(p, b) == header + 8 * elems
     p.precision = nyx.NYX_MIXED
-    assert nyx.workspace_bytes(p, b) == 256 + 4 * elems
+    assert nyx.workspace_bytes(p, b) == header + 4 * elems
 
 
 def _step(nyx, p, b, sin=0x10000000, g=0x20000000, dt=1e-3, ao=0.5, an=0.51, sout=0x30000000,
