@@ -173,6 +173,60 @@ int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void*
 int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
                           void* stream);
 
+/* ---------------- learned Riemann flux ----------------
+ * A small network 10 -> 64 -> 64 -> 64 -> 5 (ReLU) stands in for the
+ * iteration of the two-shock Riemann solver (Sec. 3.2 names the solver; the
+ * network is this library's addition).  Its inputs are the left and right
+ * face states (rho, u_n, u_t1, u_t2, p) normalised by the mean density, mean
+ * sound speed and mean normal velocity of the face; its first output is
+ * ln(p* / (rbar cbar^2)), the others are the normalised star velocity, star
+ * densities and Godunov density.  In a step with p->riemann ==
+ * NYX_RIEMANN_LEARNED (FP32-mixed precision only) the stages selected by
+ * p->learned_stages_mask evaluate the network with BF16 MFMA and FP32
+ * accumulation, correct its pressure by one FP64 Newton step of the
+ * two-shock relations and accept the face when the two-shock velocity
+ * residual divided by cbar is below p->mlp_resid_tol and the star state is
+ * positive and finite; every other face is solved by the plain iteration.
+ * Counters mlp_used / mlp_fallback record the split.
+ *
+ * Training records (float, 15 per face): left state, right state, p*, u*,
+ * rho*_L, rho*_R, Godunov density, as the plain solver computed them. */
+#define NYX_MLP_NPARAM 9349
+#define NYX_MLP_PACKED_BYTES 23552
+
+/* Harvest records of the final-stage faces of subsequent batched steps: a
+ * face is kept when a hash of (seed, box, face) falls below keep_fraction;
+ * records (device, capacity x 15 floats) are appended at *count (device,
+ * caller-zeroed); faces beyond the capacity are counted but not written.
+ * records == NULL disables harvesting. */
+int nyx_batch_set_harvest(nyx_batch* plan, float* records, unsigned long long* count,
+                          long long capacity, double keep_fraction, unsigned long long seed);
+
+/* FP32 master parameters (device, NYX_MLP_NPARAM floats, layout W1[64][10],
+ * b1, W2[64][64], b2, W3[64][64], b3, W4[5][64], b4): Glorot-uniform
+ * weights from a counter-based generator of `seed`, zero biases. */
+int nyx_mlp_init(float* params, unsigned long long seed, void* stream);
+
+/* Mean-squared loss over the normalised targets and its gradient for n
+ * records, both ADDED to loss (device, 1 float) and grad (device,
+ * NYX_MLP_NPARAM floats), each scaled by inv_batch (1 / samples in the whole
+ * batch, so several calls can form one batch).  FP32 arithmetic. */
+int nyx_mlp_loss_grad(const float* params, const float* records, long long n, double gamma,
+                      double inv_batch, float* grad, float* loss, void* stream);
+
+/* One Adam update (step t >= 1) of params with moments m, v (device). */
+int nyx_mlp_adam(float* params, float* m, float* v, const float* grad, int t, double lr,
+                 double beta1, double beta2, double eps, void* stream);
+
+/* Convert FP32 parameters into the packed BF16 inference weights (device,
+ * NYX_MLP_PACKED_BYTES, 16-byte aligned) read by learned steps. */
+int nyx_mlp_pack(const float* params, void* packed, void* stream);
+
+/* Network outputs (device, n x 5 floats) for n records with the inference
+ * path (BF16 MFMA). */
+int nyx_mlp_predict(const void* packed, const float* records, long long n, double gamma,
+                    float* out, void* stream);
+
 /* ---------------- stage timing (profiling aid, off by default) ----------------
  * When enabled, every step records HIP events around each of its
  * NYX_NSTAGES stage launches on the step's own stream, in this order:

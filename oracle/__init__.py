@@ -107,6 +107,17 @@ def lib():
         L.nyxo_flatten_line.restype = None
         L.nyxo_trace_cell.argtypes = [P, i, _D, d, _D, _D, _D, d, d, d, d, _D, _D]
         L.nyxo_trace_cell.restype = i
+        lg = ctypes.c_long
+        L.nyxo_mlp_nparam.argtypes = []
+        L.nyxo_mlp_nparam.restype = i
+        L.nyxo_mlp_normalize.argtypes = [d, _D, lg, _D, _D]
+        L.nyxo_mlp_normalize.restype = None
+        L.nyxo_mlp_forward.argtypes = [_D, _D, lg, _D]
+        L.nyxo_mlp_forward.restype = None
+        L.nyxo_mlp_relu_pattern.argtypes = [_D, _D, lg]
+        L.nyxo_mlp_relu_pattern.restype = ctypes.c_uint64
+        L.nyxo_mlp_loss_grad.argtypes = [_D, _D, _D, lg, _D]
+        L.nyxo_mlp_loss_grad.restype = d
         _lib = L
     return _lib
 
@@ -207,3 +218,42 @@ def trace_cell(d, qc, cc, qm, qp, g, kh, hdt_a=0.0, hda_a=0.0, pexp=0.0,
                           _ptr(arr[1]), _ptr(arr[2]), _ptr(arr[3]), kh, hdt_a,
                           hda_a, pexp, _ptr(lo), _ptr(hi))
     return lo, hi
+
+
+# ---------------- learned-flux network (FP64 gradient oracle) ----------------
+
+def mlp_nparam() -> int:
+    return lib().nyxo_mlp_nparam()
+
+
+def mlp_normalize(raw, gamma: float = 5.0 / 3.0):
+    """Harvested face records (n, 15) -> network inputs (n, 10), targets (n, 5)."""
+    raw = np.ascontiguousarray(raw, dtype=np.float64)
+    n = raw.shape[0]
+    x = np.zeros((n, 10))
+    y = np.zeros((n, 5))
+    lib().nyxo_mlp_normalize(gamma, _ptr(raw), n, _ptr(x), _ptr(y))
+    return x, y
+
+
+def mlp_forward(params, x):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros((x.shape[0], 5))
+    lib().nyxo_mlp_forward(_ptr(params), _ptr(x), x.shape[0], _ptr(out))
+    return out
+
+
+def mlp_relu_pattern(params, x) -> int:
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return int(lib().nyxo_mlp_relu_pattern(_ptr(params), _ptr(x), x.shape[0]))
+
+
+def mlp_loss_grad(params, x, y):
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.zeros(params.shape[0])
+    loss = lib().nyxo_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _ptr(g))
+    return loss, g

@@ -91,6 +91,12 @@ def lib():
             "nyx_fill_ghosts_periodic": (i, [B, vp, i, vp]),
             "nyx_batch_fill_ghosts": (i, [vp, i, i, i, i, vp, vp]),
             "nyx_profile_enable": (i, [i]),
+            "nyx_batch_set_harvest": (i, [vp, vp, vp, ctypes.c_longlong, d, ctypes.c_ulonglong]),
+            "nyx_mlp_init": (i, [vp, ctypes.c_ulonglong, vp]),
+            "nyx_mlp_loss_grad": (i, [vp, vp, ctypes.c_longlong, d, d, vp, vp, vp]),
+            "nyx_mlp_adam": (i, [vp, vp, vp, vp, i, d, d, d, d, vp]),
+            "nyx_mlp_pack": (i, [vp, vp, vp]),
+            "nyx_mlp_predict": (i, [vp, vp, ctypes.c_longlong, d, vp, vp]),
             "nyx_profile_read": (i, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), i]),
         }
         for name, (res, args) in sig.items():
@@ -111,7 +117,12 @@ def exported_symbols():
             "nyx_hydro_step", "nyx_batch_workspace_bytes", "nyx_batch_create",
             "nyx_batch_destroy", "nyx_batch_num_groups", "nyx_batch_estimate_dt",
             "nyx_batch_min_dt", "nyx_hydro_step_batched", "nyx_fill_ghosts_periodic",
-            "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read"]
+            "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read",
+            "nyx_batch_set_harvest", "nyx_mlp_init", "nyx_mlp_loss_grad", "nyx_mlp_adam",
+            "nyx_mlp_pack", "nyx_mlp_predict"]
+
+MLP_NPARAM = 9349
+MLP_PACKED_BYTES = 23552
 
 
 STAGE_NAMES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")

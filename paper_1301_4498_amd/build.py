@@ -24,8 +24,9 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
 
 UNITS = [
     ("nyx_step.hip", "nyx_step_fp64.o", ["-DNYX_PREC_FP64", "-ffp-contract=off"]),
-    ("nyx_step.hip", "nyx_step_mixed.o", ["-DNYX_PREC_MIXED", "-ffp-contract=fast",
+    ("nyx_step.hip", "nyx_step_mixed.o", ["-DNYX_PREC_MIXED", "-ffp-contract=on",
                                           "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
+    ("nyx_mlp.hip", "nyx_mlp.o", ["-ffp-contract=on"]),
     ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
     ("nyx_abi.cpp", "nyx_abi.o", ["-ffp-contract=off", "-x", "hip"]),
 ]

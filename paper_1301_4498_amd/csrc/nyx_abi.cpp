@@ -33,7 +33,13 @@ int check_params(const nyx_params* p) {
   if (p->riemann_maxiter < 1 || p->riemann_maxiter > 64) return NYX_E_PARAM;
   if (p->precision != NYX_FP64 && p->precision != NYX_MIXED) return NYX_E_PARAM;
   if (p->riemann != NYX_RIEMANN_TWOSHOCK && p->riemann != NYX_RIEMANN_LEARNED) return NYX_E_PARAM;
-  if (p->riemann == NYX_RIEMANN_LEARNED) return NYX_E_UNSUPPORTED;
+  if (p->riemann == NYX_RIEMANN_LEARNED) {
+    if (p->precision != NYX_MIXED) return NYX_E_UNSUPPORTED;
+    if (!p->mlp_weights) return NYX_E_NULL;
+    if ((uintptr_t)p->mlp_weights & 15) return NYX_E_PARAM;
+    if (p->learned_stages_mask < 1 || p->learned_stages_mask > 7) return NYX_E_PARAM;
+    if (!(std::isfinite(p->mlp_resid_tol) && p->mlp_resid_tol >= 0.0)) return NYX_E_PARAM;
+  }
   return NYX_OK;
 }
 
@@ -80,6 +86,10 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   a.riemann_tol = p->riemann_tol;
   a.cfl = p->cfl;
   a.maxiter = p->riemann_maxiter;
+  const bool learned = p->riemann == NYX_RIEMANN_LEARNED;
+  a.mlp = learned ? p->mlp_weights : nullptr;
+  a.learned_mask = learned ? p->learned_stages_mask : 0;
+  a.mlp_tol = p->mlp_resid_tol;
 }
 
 // ---- stage timing ----
@@ -242,6 +252,12 @@ struct nyx_batch {
   unsigned long long* slots;     // device, partial counters
   void* stage;                   // device stage region
   size_t state_span;             // bytes spanned by the state of all boxes
+  // training-record harvest (final-stage faces)
+  float* harvest = nullptr;
+  unsigned long long* harvest_count = nullptr;
+  long long harvest_cap = 0;
+  unsigned harvest_keep = 0;
+  unsigned long long harvest_seed = 0;
 };
 
 namespace {
@@ -383,6 +399,11 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   A.smax = plan->smax;
   A.slots = plan->slots;
   fill_physics(A, &plan->prm);
+  A.harvest = plan->harvest;
+  A.harvest_count = plan->harvest_count;
+  A.harvest_cap = plan->harvest_cap;
+  A.harvest_keep = plan->harvest_keep;
+  A.harvest_seed = plan->harvest_seed;
   return A;
 }
 
@@ -457,6 +478,67 @@ int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void*
   box_layout(*box, 0, 0, &A.single);
   set_blocks(A.single, A.nblocks);
   return launch_fill_periodic(A, nullptr, state, ncomp, 0, 1, 1, 1, (hipStream_t)stream) == hipSuccess
+             ? NYX_OK
+             : NYX_E_HIP;
+}
+
+int nyx_batch_set_harvest(nyx_batch* plan, float* records, unsigned long long* count,
+                          long long capacity, double keep_fraction, unsigned long long seed) {
+  if (!plan) return NYX_E_NULL;
+  if (!records) {
+    plan->harvest = nullptr;
+    return NYX_OK;
+  }
+  if (!count) return NYX_E_NULL;
+  if (capacity < 1 || !(keep_fraction > 0.0 && keep_fraction <= 1.0)) return NYX_E_PARAM;
+  plan->harvest = records;
+  plan->harvest_count = count;
+  plan->harvest_cap = capacity;
+  const double k = keep_fraction * 4294967296.0;
+  plan->harvest_keep = k >= 4294967295.0 ? 4294967295u : (unsigned)k;
+  plan->harvest_seed = seed;
+  return NYX_OK;
+}
+
+int nyx_mlp_init(float* params, unsigned long long seed, void* stream) {
+  if (!params) return NYX_E_NULL;
+  return launch_mlp_init(params, seed, (hipStream_t)stream) == hipSuccess ? NYX_OK : NYX_E_HIP;
+}
+
+int nyx_mlp_loss_grad(const float* params, const float* records, long long n, double gamma,
+                      double inv_batch, float* grad, float* loss, void* stream) {
+  if (!params || !records || !grad || !loss) return NYX_E_NULL;
+  if (n < 0 || n > (1ll << 40) || !(gamma > 1.0) || !finite_pos(inv_batch)) return NYX_E_PARAM;
+  return launch_mlp_loss_grad(params, records, n, gamma, (float)inv_batch, grad, loss,
+                              (hipStream_t)stream) == hipSuccess
+             ? NYX_OK
+             : NYX_E_HIP;
+}
+
+int nyx_mlp_adam(float* params, float* m, float* v, const float* grad, int t, double lr,
+                 double beta1, double beta2, double eps, void* stream) {
+  if (!params || !m || !v || !grad) return NYX_E_NULL;
+  if (t < 1 || !finite_pos(lr) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !finite_pos(eps))
+    return NYX_E_PARAM;
+  return launch_mlp_adam(params, m, v, grad, t, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                         (hipStream_t)stream) == hipSuccess
+             ? NYX_OK
+             : NYX_E_HIP;
+}
+
+int nyx_mlp_pack(const float* params, void* packed, void* stream) {
+  if (!params || !packed) return NYX_E_NULL;
+  if ((uintptr_t)packed & 15) return NYX_E_PARAM;
+  return launch_mlp_pack(params, packed, (hipStream_t)stream) == hipSuccess ? NYX_OK : NYX_E_HIP;
+}
+
+int nyx_mlp_predict(const void* packed, const float* records, long long n, double gamma,
+                    float* out, void* stream) {
+  if (!packed || !records || !out) return NYX_E_NULL;
+  if ((uintptr_t)packed & 15) return NYX_E_PARAM;
+  if (n < 0 || n > (1ll << 40) || !(gamma > 1.0)) return NYX_E_PARAM;
+  return launch_mlp_predict(packed, records, n, gamma, out, (hipStream_t)stream) == hipSuccess
              ? NYX_OK
              : NYX_E_HIP;
 }

@@ -146,6 +146,16 @@ struct StepArgs {
   unsigned long long* slots;  // kStatSlots x kStatFields partial counters (when stats)
   double* dt_next;
   hipEvent_t* ev;          // kStages + 1 events recorded around the stages, or nullptr
+  // learned Riemann flux (FP32-mixed build only)
+  const void* mlp;         // packed network, or nullptr
+  int learned_mask;        // bit s: stage s (0, 1, 2) uses the network
+  double mlp_tol;          // accepted two-shock residual
+  // harvest of final-stage faces for training
+  float* harvest;          // [cap][15] records, or nullptr
+  unsigned long long* harvest_count;
+  long long harvest_cap;
+  unsigned harvest_keep;   // keep a face when its 32-bit hash < harvest_keep
+  unsigned long long harvest_seed;
 };
 
 // stage order of launch_step (for timing)
@@ -165,6 +175,15 @@ hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, dou
                               hipStream_t s);
 hipError_t launch_min_dt(double* dt, int n, hipStream_t s);
 hipError_t launch_stats_reduce(const unsigned long long* slots, nyx_stats* stats, hipStream_t s);
+// learned flux (nyx_mlp.hip)
+hipError_t launch_mlp_init(float* P, unsigned long long seed, hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float* P, const float* rec, long long n, double gamma,
+                                float inv_n, float* grad, float* loss, hipStream_t st);
+hipError_t launch_mlp_adam(float* P, float* m, float* v, const float* g, int t, float lr, float b1,
+                           float b2, float eps, hipStream_t st);
+hipError_t launch_mlp_pack(const float* P, void* packed, hipStream_t st);
+hipError_t launch_mlp_predict(const void* packed, const float* rec, long long n, double gamma,
+                              float* out, hipStream_t st);
 hipError_t launch_fill_periodic(const StepArgs& a, const BoxDev* full, double* state, int ncomp,
                                 int mode, int gx, int gy, int gz, hipStream_t s);
 

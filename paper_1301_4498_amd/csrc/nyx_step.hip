@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "nyx_internal.h"
+#include "nyx_mlp_dev.h"
 
 #if defined(NYX_PREC_FP64)
 #define NYX_NS fp64
@@ -375,7 +376,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
 // two-shock Riemann solver (O5), always FP64
 // ---------------------------------------------------------------------------
 struct RiemannOut {
-  double r, u, v, w, p;
+  double r, u, v, w, p;          // Godunov state at x/t = 0 (rotated frame)
+  double pstar, ustar, rsL, rsR;  // star pressure, velocity and densities
   int iters;
 };
 
@@ -396,67 +398,67 @@ __device__ __forceinline__ double rsq64(double x) {
   return fma(0.5 * y, r, y);
 }
 
-// The same two-shock Newton iteration, rearranged so that each iteration
-// needs one reciprocal and two reciprocal square roots: with
+// The two-shock Newton iteration, rearranged so that each evaluation needs
+// one reciprocal and two reciprocal square roots: with
 // X_K = W_K^2 = C_K + (gamma+1)/2 rho_K (p - p_K) and w_K = 1/W_K,
 //   u*_L = u_L - (p - p_L) w_L,  u*_R = u_R + (p - p_R) w_R,
 //   1/Z_K = (X_K + C_K) w_K^3 / 2,
 //   p' = p - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
-//   u* = (u*_L/Z_R' ...) = (u*_L (1/Z_R) + u*_R (1/Z_L)) / (1/Z_L + 1/Z_R),
+//   u* = (u*_L / Z_R + u*_R / Z_L) / (1/Z_L + 1/Z_R),
 //   1/rho*_K = 1/rho_K - (p* - p_K) w_K^2.
-__device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
-                                                const double* qR) {
-  const double gam = A.gamma;
-  const double g2 = 0.5 * (gam + 1.0);
-  const double sp = A.small_pres;
-  const double rl = qL[0], ul = qL[1], pl = qL[4];
-  const double rr = qR[0], ur = qR[1], pr = qR[4];
-  const double CL = (gam * pl) * rl;
-  const double CR = (gam * pr) * rr;
-  const double W0L = CL * rsq64(CL), W0R = CR * rsq64(CR);
-  double p = ((W0R * pl + W0L * pr) + (W0L * W0R) * (ul - ur)) * rcp64(W0L + W0R);
-  p = vmax(p, sp);
-  const double gl = g2 * rl, gr = g2 * rr;
-  int it = 0;
+struct TwoShock {
+  double gam, sp, rl, ul, pl, rr, ur, pr, CL, CR, gl, gr;
+};
+struct TwoShockEval {
   double XL, XR, wL, wR, usL, usR, zL, zR;
-  while (it < A.maxiter) {
-    XL = CL + gl * (p - pl);
-    XR = CR + gr * (p - pr);
-    wL = rsq64(XL);
-    wR = rsq64(XR);
-    usL = ul - (p - pl) * wL;
-    usR = ur + (p - pr) * wR;
-    zL = 0.5 * (XL + CL) * (wL * wL * wL);
-    zR = 0.5 * (XR + CR) * (wR * wR * wR);
-    double pn = p - (usR - usL) * rcp64(zL + zR);
-    pn = vmax(pn, sp);
-    ++it;
-    bool conv = fabs(pn - p) <= A.riemann_tol * pn;
-    p = pn;
-    if (conv) break;
-  }
-  XL = CL + gl * (p - pl);
-  XR = CR + gr * (p - pr);
-  wL = rsq64(XL);
-  wR = rsq64(XR);
-  usL = ul - (p - pl) * wL;
-  usR = ur + (p - pr) * wR;
-  zL = 0.5 * (XL + CL) * (wL * wL * wL);
-  zR = 0.5 * (XR + CR) * (wR * wR * wR);
-  const double ustar = (usL * zR + usR * zL) * rcp64(zL + zR);
+};
+__device__ __forceinline__ TwoShock ts_setup(const StepArgs& A, const double* qL,
+                                             const double* qR) {
+  TwoShock t;
+  t.gam = A.gamma;
+  t.sp = A.small_pres;
+  t.rl = qL[0]; t.ul = qL[1]; t.pl = qL[4];
+  t.rr = qR[0]; t.ur = qR[1]; t.pr = qR[4];
+  t.CL = (t.gam * t.pl) * t.rl;
+  t.CR = (t.gam * t.pr) * t.rr;
+  const double g2 = 0.5 * (t.gam + 1.0);
+  t.gl = g2 * t.rl;
+  t.gr = g2 * t.rr;
+  return t;
+}
+__device__ __forceinline__ TwoShockEval ts_eval(const TwoShock& t, double p) {
+  TwoShockEval e;
+  e.XL = t.CL + t.gl * (p - t.pl);
+  e.XR = t.CR + t.gr * (p - t.pr);
+  e.wL = rsq64(e.XL);
+  e.wR = rsq64(e.XR);
+  e.usL = t.ul - (p - t.pl) * e.wL;
+  e.usR = t.ur + (p - t.pr) * e.wR;
+  e.zL = 0.5 * (e.XL + t.CL) * (e.wL * e.wL * e.wL);
+  e.zR = 0.5 * (e.XR + t.CR) * (e.wR * e.wR * e.wR);
+  return e;
+}
+__device__ __forceinline__ double ts_newton(const TwoShock& t, const TwoShockEval& e, double p) {
+  return vmax(p - (e.usR - e.usL) * rcp64(e.zL + e.zR), t.sp);
+}
+// star state, wave speeds and the sample at x/t = 0 from the pressure p
+__device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShockEval& e,
+                                                double p, const double* qL, const double* qR) {
+  const double gam = t.gam, rl = t.rl, ul = t.ul, pl = t.pl, rr = t.rr, ur = t.ur, pr = t.pr;
+  const double ustar = (e.usL * e.zR + e.usR * e.zL) * rcp64(e.zL + e.zR);
   const double pstar = p;
   const double irl = rcp64(rl), irr = rcp64(rr);
-  const double DL = irl - (pstar - pl) * (wL * wL);
-  const double DR = irr - (pstar - pr) * (wR * wR);
+  const double DL = irl - (pstar - pl) * (e.wL * e.wL);
+  const double DR = irr - (pstar - pr) * (e.wR * e.wR);
   const double rsL = rcp64(DL), rsR = rcp64(DR);
   double shdL, stlL, shdR, stlR;
-  if (pstar >= pl) { shdL = ul - (XL * wL) * irl; stlL = shdL; }
+  if (pstar >= pl) { shdL = ul - (e.XL * e.wL) * irl; stlL = shdL; }
   else {
     const double x0 = (gam * pl) * irl, x1 = (gam * pstar) * DL;
     shdL = ul - x0 * rsq64(x0);
     stlL = ustar - x1 * rsq64(x1);
   }
-  if (pstar >= pr) { shdR = ur + (XR * wR) * irr; stlR = shdR; }
+  if (pstar >= pr) { shdR = ur + (e.XR * e.wR) * irr; stlR = shdR; }
   else {
     const double x0 = (gam * pr) * irr, x1 = (gam * pstar) * DR;
     shdR = ur + x0 * rsq64(x0);
@@ -491,8 +493,60 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
     o.v = 0.5 * (qL[2] + qR[2]);
     o.w = 0.5 * (qL[3] + qR[3]);
   }
+  o.pstar = pstar;
+  o.ustar = ustar;
+  o.rsL = rsL;
+  o.rsR = rsR;
+  o.iters = 0;
+  return o;
+}
+
+__device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
+                                                const double* qR) {
+  const TwoShock t = ts_setup(A, qL, qR);
+  const double W0L = t.CL * rsq64(t.CL), W0R = t.CR * rsq64(t.CR);
+  double p = ((W0R * t.pl + W0L * t.pr) + (W0L * W0R) * (t.ul - t.ur)) * rcp64(W0L + W0R);
+  p = vmax(p, t.sp);
+  int it = 0;
+  while (it < A.maxiter) {
+    const TwoShockEval e = ts_eval(t, p);
+    const double pn = ts_newton(t, e, p);
+    ++it;
+    const bool conv = fabs(pn - p) <= A.riemann_tol * pn;
+    p = pn;
+    if (conv) break;
+  }
+  RiemannOut o = ts_finish(t, ts_eval(t, p), p, qL, qR);
   o.iters = it;
   return o;
+}
+
+// Learned solve.  The network's pressure guess p0 = Pbar exp(y0) is corrected
+// by one Newton step of the two-shock relations; the result is accepted when
+// the two-shock velocity residual |u*_R(p1) - u*_L(p1)| / cbar at the
+// corrected pressure is below tol and the star state is positive and finite.
+// Otherwise the plain two-shock solver decides the face (*used = false).
+__device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const double* qL,
+                                                    const double* qR, float y0, double pbar,
+                                                    double cbar, bool* used) {
+  const TwoShock t = ts_setup(A, qL, qR);
+  const double y = (double)(y0 < -40.0f ? -40.0f : (y0 > 40.0f ? 40.0f : y0));
+  const double p0 = vmax(pbar * exp(y), t.sp);
+  const double p1 = ts_newton(t, ts_eval(t, p0), p0);
+  const TwoShockEval e = ts_eval(t, p1);
+  const double resid = fabs(e.usR - e.usL) / cbar;
+  bool ok = resid < A.mlp_tol;  // never true for tol = 0 or a NaN residual
+  if (ok) {
+    RiemannOut o = ts_finish(t, e, p1, qL, qR);
+    ok = o.rsL > 0.0 && o.rsR > 0.0 && isfinite(o.rsL) && isfinite(o.rsR) && isfinite(o.r) &&
+         isfinite(o.u) && isfinite(o.p) && o.r > 0.0 && o.p > 0.0;
+    if (ok) {
+      *used = true;
+      return o;
+    }
+  }
+  *used = false;
+  return two_shock(A, qL, qR);
 }
 #else
 
@@ -570,6 +624,10 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
     o.v = 0.5 * (qL[2] + qR[2]);
     o.w = 0.5 * (qL[3] + qR[3]);
   }
+  o.pstar = pstar;
+  o.ustar = ustar;
+  o.rsL = rsL;
+  o.rsR = rsR;
   o.iters = it;
   return o;
 }
@@ -603,15 +661,6 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const real* G, lo
   f[7] = u;
 }
 
-// solve at a d-face from lab-frame double states
-__device__ __forceinline__ RiemannOut solve_face(const StepArgs& A, int d, const double* L,
-                                                 const double* R) {
-  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  double qL[5] = {L[0], L[1 + d], L[1 + t1], L[1 + t2], L[4]};
-  double qR[5] = {R[0], R[1 + d], R[1 + t1], R[1 + t2], R[4]};
-  return two_shock(A, qL, qR);
-}
-
 __device__ __forceinline__ void e_coords(const BoxDev& b, unsigned e, int* c) {
   space_coords(b, kSpaceE, e, c);
 }
@@ -620,45 +669,31 @@ __device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
 }
 
 // ---------------------------------------------------------------------------
-// stage 4: Riemann on stage-0 states, faces between cells of [-1, n]
+// O7: transverse correction of a lab-frame edge state (FP64 arithmetic).
+// Dc[5]: summed flux differences (high minus low t-face) of rho, m, E;
+// De: summed differences of the internal-energy flux plus the p div u term.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
-  int d;
-  Loc L = locate(A, kSpaceE, &d);
-  const BoxDev& b = *L.bd;
-  unsigned calls = 0, iters = 0;
-  if (L.idx < b.E) {
-    const long long e = L.idx;
-    int c[3];
-    e_coords(b, L.idx, c);
-    if (c[d] >= 1) {  // face f = c[d] - 1 in [0, n_d]
-      const long long eL = e - e_stride(b, d);
-      const real* W = (const real*)A.work + b.w_edge;
-      double ql[5], qr[5];
-      for (int v = 0; v < 5; ++v) {
-        ql[v] = (double)W[((d * 2 + 1) * 5 + v) * b.E + eL];
-        qr[v] = (double)W[((d * 2 + 0) * 5 + v) * b.E + e];
-      }
-      RiemannOut g = solve_face(A, d, ql, qr);
-      calls = 1;
-      iters = g.iters;
-      store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E + e, b.E, g);
-    }
+// add the differences of one transverse direction t (stored Godunov states
+// at the low and high t-faces of a cell) to Dc, De; the first direction sets
+// them, a second one is added, in that order
+template <bool FIRST>
+__device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, const real* Ghi,
+                                      long long E, double* Dc, double& De) {
+  real fm[8], fp[8];
+  face_flux(gamma, t, Glo, E, fm);
+  face_flux(gamma, t, Ghi, E, fp);
+  for (int c = 0; c < 5; ++c) {
+    const double dd = (double)fp[c] - (double)fm[c];
+    Dc[c] = FIRST ? dd : Dc[c] + dd;
   }
-  if (A.stats) {
-    count(A, kRiemannCalls, calls);
-    count(A, kRiemannIters, iters);
-  }
+  const double de = ((double)fp[5] - (double)fm[5]) +
+                    (0.5 * ((double)fp[6] + (double)fm[6])) * ((double)fp[7] - (double)fm[7]);
+  De = FIRST ? de : De + de;
 }
 
-// ---------------------------------------------------------------------------
-// O7: transverse correction of a lab-frame edge state (FP64 arithmetic).
-// fm[k], fp[k]: lab-frame fluxes at the low and high t_k-faces of the cell.
-// ---------------------------------------------------------------------------
-template <int NT>
 __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q,
-                                              const real (*fm)[8], const real (*fp)[8],
-                                              double kap, double* out) {
+                                              const double* Dc, double De, double kap,
+                                              double* out) {
   const double gm1 = A.gamma - 1.0;
   const double rho = q[0], ux = q[1], uy = q[2], uz = q[3], p = q[4];
   double U[5];
@@ -672,16 +707,6 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
   const double Ue = p / gm1;
 #endif
   U[4] = Ue + (0.5 * rho) * ((ux * ux + uy * uy) + uz * uz);
-  double Dc[5];
-  for (int c = 0; c < 5; ++c) {
-    Dc[c] = (double)fp[0][c] - (double)fm[0][c];
-    if (NT == 2) Dc[c] = Dc[c] + ((double)fp[1][c] - (double)fm[1][c]);
-  }
-  double De = ((double)fp[0][5] - (double)fm[0][5]) +
-              (0.5 * ((double)fp[0][6] + (double)fm[0][6])) * ((double)fp[0][7] - (double)fm[0][7]);
-  if (NT == 2)
-    De = De + (((double)fp[1][5] - (double)fm[1][5]) +
-               (0.5 * ((double)fp[1][6] + (double)fm[1][6])) * ((double)fp[1][7] - (double)fm[1][7]));
   double Un[5];
   for (int c = 0; c < 5; ++c) Un[c] = U[c] - kap * Dc[c];
   const double Uen = Ue - kap * De;
@@ -718,102 +743,241 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
 
 __device__ __forceinline__ int pair_index(int d, int t) { return d * 2 + (t == (d + 1) % 3 ? 0 : 1); }
 
+// rotate lab-frame states into the frame of a d-face
+__device__ __forceinline__ void rotate(int d, const double* L, double* q) {
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  q[0] = L[0];
+  q[1] = L[1 + d];
+  q[2] = L[1 + t1];
+  q[3] = L[1 + t2];
+  q[4] = L[4];
+}
+
+#if defined(NYX_PREC_MIXED)
+constexpr bool kHasLearned = true;
+#else
+constexpr bool kHasLearned = false;
+#endif
+
+// Riemann solve of one face of the wave.  LEARNED: every lane of the
+// wavefront must call it (the network runs wave-wide); `active` marks lanes
+// with a real face.  Returns the solution for active lanes.
+template <bool LEARNED>
+__device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, const double* qL,
+                                            const double* qR, __bf16* lds, unsigned* used,
+                                            unsigned* fallback) {
+  RiemannOut g{};
+#if defined(NYX_PREC_MIXED)
+  if constexpr (LEARNED) {
+    const double one[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    const double* a = active ? qL : one;
+    const double* b = active ? qR : one;
+    float x[kMlpIn], y[kMlpOut];
+    double rbar, cbar, ubar;
+    mlp_inputs(A.gamma, a, b, x, &rbar, &cbar, &ubar);
+    for (int k = 0; k < kMlpIn; ++k) x[k] = isfinite(x[k]) ? x[k] : 0.0f;
+    mlp_wave_forward(A.mlp, x, lds, y);
+    if (active) {
+      bool u = false;
+      g = learned_solve(A, qL, qR, y[0], rbar * cbar * cbar, cbar, &u);
+      *used += u ? 1u : 0u;
+      *fallback += u ? 0u : 1u;
+    }
+    return g;
+  }
+#endif
+  if (active) g = two_shock(A, qL, qR);
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// stage 4: Riemann on stage-0 states, faces between cells of [-1, n]
+// ---------------------------------------------------------------------------
+template <bool LEARNED>
+__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  int d;
+  Loc L = locate(A, kSpaceE, &d);
+  const BoxDev& b = *L.bd;
+  unsigned calls = 0, iters = 0, used = 0, fb = 0;
+  int c[3] = {0, 0, 0};
+  if (L.idx < b.E) e_coords(b, L.idx, c);
+  const bool active = L.idx < b.E && c[d] >= 1;  // face f = c[d] - 1 in [0, n_d]
+  const long long e = L.idx;
+  double ql[5], qr[5];
+  if (active) {
+    const long long eL = e - e_stride(b, d);
+    const real* W = (const real*)A.work + b.w_edge;
+    double Ls[5], Rs[5];
+    for (int v = 0; v < 5; ++v) {
+      Ls[v] = (double)W[((d * 2 + 1) * 5 + v) * b.E + eL];
+      Rs[v] = (double)W[((d * 2 + 0) * 5 + v) * b.E + e];
+    }
+    rotate(d, Ls, ql);
+    rotate(d, Rs, qr);
+  }
+  RiemannOut g = solve<LEARNED>(A, active, ql, qr, mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED,
+                                &used, &fb);
+  if (active) {
+    calls = 1;
+    iters = g.iters;
+    store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E + e, b.E, g);
+  }
+  if (A.stats) {
+    count(A, kRiemannCalls, calls);
+    count(A, kRiemannIters, iters);
+    if (LEARNED) {
+      count(A, kMlpUsed, used);
+      count(A, kMlpFallback, fb);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // stage 5: for one direction d, the d-states of a face's two cells corrected
 // by stage-0 t-fluxes (t = t1 and t = t2), Riemann -> F^{d|t1}, F^{d|t2}.
 // Both pairs share the loads of the d-states.
 // ---------------------------------------------------------------------------
+template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int d;
   Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
-  unsigned calls = 0, iters = 0, reverts = 0;
-  if (L.idx < b.E) {
-    const long long e = L.idx;
-    int c[3];
-    e_coords(b, L.idx, c);
-    const int ts[2] = {(d + 1) % 3, (d + 2) % 3};
-    const bool want[2] = {c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
-                          c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
-    if (c[d] >= 1 && (want[0] || want[1])) {
+  unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
+  int c[3] = {0, 0, 0};
+  if (L.idx < b.E) e_coords(b, L.idx, c);
+  const long long e = L.idx;
+  const int ts[2] = {(d + 1) % 3, (d + 2) % 3};
+  const bool inb = L.idx < b.E && c[d] >= 1;
+  const bool want[2] = {inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
+                        inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
+  double q[2][5];
+  const long long sdd = e_stride(b, d);
+  if (want[0] || want[1]) {
+    const real* W = (const real*)A.work + b.w_edge;
+    for (int s = 0; s < 2; ++s) {
+      const long long ec = s == 0 ? e - sdd : e;
+      const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
+      for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+    }
+  }
+  for (int k = 0; k < 2; ++k) {
+    const bool active = want[k];
+    double ql[5], qr[5];
+    if (active) {
       const StepC C = step_consts(A, b);
-      const long long sdd = e_stride(b, d);
-      const real* W = (const real*)A.work + b.w_edge;
-      double q[2][5];
+      const int t = ts[k];
+      const long long stt = e_stride(b, t);
+      const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
+      double qs[2][5];
       for (int s = 0; s < 2; ++s) {
         const long long ec = s == 0 ? e - sdd : e;
-        const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
-        for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+        double Dc[5], De;
+        tdiff<true>(A.gamma, t, G0 + ec, G0 + ec + stt, b.E, Dc, De);
+        reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
       }
-      for (int k = 0; k < 2; ++k) {
-        if (!want[k]) continue;
-        const int t = ts[k];
-        const long long stt = e_stride(b, t);
-        const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
-        double qs[2][5];
-        for (int s = 0; s < 2; ++s) {
-          const long long ec = s == 0 ? e - sdd : e;
-          real fm[1][8], fp[1][8];
-          face_flux(A.gamma, t, G0 + ec, b.E, fm[0]);
-          face_flux(A.gamma, t, G0 + ec + stt, b.E, fp[0]);
-          reverts += trans_correct<1>(A, q[s], fm, fp, C.kap1, qs[s]) ? 1u : 0u;
-        }
-        RiemannOut g = solve_face(A, d, qs[0], qs[1]);
-        calls += 1;
-        iters += g.iters;
-        store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, t) * kGod * b.E + e, b.E, g);
-      }
+      rotate(d, qs[0], ql);
+      rotate(d, qs[1], qr);
+    }
+    RiemannOut g = solve<LEARNED>(A, active, ql, qr,
+                                  mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED, &used, &fb);
+    if (active) {
+      calls += 1;
+      iters += g.iters;
+      store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E + e, b.E, g);
     }
   }
   if (A.stats) {
     count(A, kRiemannCalls, calls);
     count(A, kRiemannIters, iters);
     count(A, kTransReverts, reverts);
+    if (LEARNED) {
+      count(A, kMlpUsed, used);
+      count(A, kMlpFallback, fb);
+    }
   }
+}
+
+// 32-bit hash of a face for the training-sample harvest
+__device__ __forceinline__ unsigned face_hash(unsigned long long seed, int box, long long e, int d) {
+  unsigned long long z = seed ^ ((unsigned long long)box << 40) ^ ((unsigned long long)e << 2) ^
+                         (unsigned long long)d;
+  z = (z ^ (z >> 33)) * 0xff51afd7ed558ccdull;
+  z = (z ^ (z >> 33)) * 0xc4ceb9fe1a85ec53ull;
+  z ^= z >> 33;
+  return (unsigned)z;
 }
 
 // ---------------------------------------------------------------------------
 // stage 6: final d-states and comoving fluxes on valid faces
 // ---------------------------------------------------------------------------
+// MODE 0: plain; 1: learned; 2: plain and harvest training records
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+  constexpr bool LEARNED = MODE == 1;
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int d;
   Loc L = locate(A, kSpaceE, &d);
   const BoxDev& b = *L.bd;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  unsigned calls = 0, iters = 0, reverts = 0;
-  if (L.idx < b.E) {
-    const long long e = L.idx;
-    int c[3];
-    e_coords(b, L.idx, c);
-    if (c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 && c[t2] <= b.n[t2]) {
-      const StepC C = step_consts(A, b);
-      const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
-      const real* W = (const real*)A.work + b.w_edge;
-      const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
-      const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
-      double qs[2][5];
-      for (int s = 0; s < 2; ++s) {
-        const long long ec = s == 0 ? e - sdd : e;
-        const int side = s == 0 ? 1 : 0;
-        double q[5];
-        for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
-        real fm[2][8], fp[2][8];
-        face_flux(A.gamma, t1, G1a + ec, b.E, fm[0]);       // t1-flux corrected by t2
-        face_flux(A.gamma, t1, G1a + ec + s1, b.E, fp[0]);
-        face_flux(A.gamma, t2, G1b + ec, b.E, fm[1]);       // t2-flux corrected by t1
-        face_flux(A.gamma, t2, G1b + ec + s2, b.E, fp[1]);
-        reverts += trans_correct<2>(A, q, fm, fp, C.kap2, qs[s]) ? 1u : 0u;
+  unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
+  int c[3] = {0, 0, 0};
+  if (L.idx < b.E) e_coords(b, L.idx, c);
+  const long long e = L.idx;
+  const bool active = L.idx < b.E && c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 &&
+                      c[t2] <= b.n[t2];
+  double ql[5], qr[5];
+  if (active) {
+    const StepC C = step_consts(A, b);
+    const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
+    const real* W = (const real*)A.work + b.w_edge;
+    const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
+    const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
+    double qs[2][5];
+    for (int s = 0; s < 2; ++s) {
+      const long long ec = s == 0 ? e - sdd : e;
+      const int side = s == 0 ? 1 : 0;
+      double q[5];
+      for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+      double Dc[5], De;
+      tdiff<true>(A.gamma, t1, G1a + ec, G1a + ec + s1, b.E, Dc, De);   // t1-flux corrected by t2
+      tdiff<false>(A.gamma, t2, G1b + ec, G1b + ec + s2, b.E, Dc, De);  // t2-flux corrected by t1
+      reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
+    }
+    rotate(d, qs[0], ql);
+    rotate(d, qs[1], qr);
+  }
+  RiemannOut g = solve<LEARNED>(A, active, ql, qr, mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED,
+                                &used, &fb);
+  if (active) {
+    calls = 1;
+    iters = g.iters;
+    store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E + e, b.E, g);
+    if (MODE == 2 && face_hash(A.harvest_seed, b.gidx, e, d) < A.harvest_keep) {
+      const unsigned long long slot = atomicAdd(A.harvest_count, 1ull);
+      if (slot < (unsigned long long)A.harvest_cap) {
+        float* r = A.harvest + 15 * slot;
+        for (int v = 0; v < 5; ++v) {
+          r[v] = (float)ql[v];
+          r[5 + v] = (float)qr[v];
+        }
+        r[10] = (float)g.pstar;
+        r[11] = (float)g.ustar;
+        r[12] = (float)g.rsL;
+        r[13] = (float)g.rsR;
+        r[14] = (float)g.r;
       }
-      RiemannOut g = solve_face(A, d, qs[0], qs[1]);
-      calls = 1;
-      iters = g.iters;
-      store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E + e, b.E, g);
     }
   }
   if (A.stats) {
     count(A, kRiemannCalls, calls);
     count(A, kRiemannIters, iters);
     count(A, kTransReverts, reverts);
+    if (LEARNED) {
+      count(A, kMlpUsed, used);
+      count(A, kMlpFallback, fb);
+    }
   }
 }
 
@@ -943,6 +1107,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   auto mark = [&](int i) {
     if (a.ev) (void)hipEventRecord(a.ev[i], s);
   };
+  auto learned = [&](int stage) { return kHasLearned && a.mlp && (a.learned_mask >> stage & 1); };
   mark(0);
   hipLaunchKernelGGL(k_prim, dim3(a.nblocks[kSpaceP]), blk, 0, s, a);
   mark(1);
@@ -950,11 +1115,15 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   mark(2);
   hipLaunchKernelGGL(k_trace, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(3);
-  hipLaunchKernelGGL(k_riem0, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  if (learned(0)) hipLaunchKernelGGL(k_riem0<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  else hipLaunchKernelGGL(k_riem0<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(4);
-  hipLaunchKernelGGL(k_riem1, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  if (learned(1)) hipLaunchKernelGGL(k_riem1<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  else hipLaunchKernelGGL(k_riem1<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(5);
-  hipLaunchKernelGGL(k_riem2, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  if (learned(2)) hipLaunchKernelGGL(k_riem2<kHasLearned ? 1 : 0>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  else if (a.harvest) hipLaunchKernelGGL(k_riem2<2>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  else hipLaunchKernelGGL(k_riem2<0>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(6);
   hipLaunchKernelGGL(k_update, dim3(a.nblocks[kSpaceV]), blk, 0, s, a);
   mark(7);

@@ -92,6 +92,31 @@ def test_argument_errors(nyx):
         assert _step(nyx, q, b) == -3, field
 
 
+def test_learned_flux_argument_errors(nyx):
+    b = nyx.make_box((8, 8, 8), 4, 0.1)
+    # the learned flux exists in the FP32-mixed form only
+    p = nyx.default_params(riemann=nyx.NYX_RIEMANN_LEARNED, learned_stages_mask=7)
+    p.mlp_weights = 0x50000000
+    assert _step(nyx, p, b) == -6
+    p = nyx.default_params(precision=nyx.NYX_MIXED, riemann=nyx.NYX_RIEMANN_LEARNED,
+                           learned_stages_mask=7)
+    assert _step(nyx, p, b) == -1                     # no weights
+    p.mlp_weights = 0x50000008
+    assert _step(nyx, p, b) == -3                     # misaligned weights
+    p.mlp_weights = 0x50000000
+    p.learned_stages_mask = 0
+    assert _step(nyx, p, b) == -3
+    p.learned_stages_mask = 7
+    p.mlp_resid_tol = -1.0
+    assert _step(nyx, p, b) == -3
+    L = nyx.lib()
+    assert L.nyx_mlp_loss_grad(None, 1, 10, 5 / 3, 0.1, 1, 1, None) == -1
+    assert L.nyx_mlp_loss_grad(0x1000, 0x2000, 10, 1.0, 0.1, 0x3000, 0x4000, None) == -3
+    assert L.nyx_mlp_adam(0x1000, 0x2000, 0x3000, 0x4000, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -3
+    assert L.nyx_mlp_pack(0x1000, 0x2008, None) == -3
+    assert L.nyx_batch_set_harvest(None, 1, 1, 10, 0.5, 0) == -1
+
+
 def test_batch_argument_errors(nyx):
     L = nyx.lib()
     p = nyx.default_params()
