@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the comoving PPM gas step on one MI355X.
 
-Workload: one periodic 256^3 box (+4 ghost cells) with the smooth-flow fields
-of the single-box configuration (rho lognormal sigma_ln 0.3, k^-2 velocity
-sigma 0.5, p = 0.6 rho^gamma, g ~ N(0, 0.05^2)), a from 0.25 linearly over
-20 steps to 0.26, CFL 0.5, dt from the fused CFL reduction of the previous
-step (device-resident, no host round trip).  One timed step is
-[hydro step with fused dt_next -> periodic ghost fill] for every box.
+Headline workload (box256_smooth): one periodic 256^3 box (+4 ghost cells)
+with the smooth-flow fields of the single-box configuration (rho lognormal
+sigma_ln 0.3, k^-2 velocity sigma 0.5, p = 0.6 rho^gamma, g ~ N(0, 0.05^2)),
+a from 0.25 linearly over 20 steps to 0.26, CFL 0.5, dt from the fused CFL
+reduction of the previous step (device-resident, no host round trip).  One
+timed step is [hydro step with fused dt_next -> periodic ghost fill].
 
-Forms measured on the same GPU: plain FP64, and the FP32-mixed build.  The
-headline value is the chosen (fastest validated) form; every form's rate is
-reported.  Stage times come from HIP events the library records between its
-stage launches on the step's stream.
+Forms on the same GPU and inputs: plain FP64, FP32-mixed, and FP32-mixed with
+the learned Riemann flux (trained beforehand, untimed, on faces harvested
+from other seeds).  The headline value is the fastest form whose density
+stays within 1e-3 relative L1 of plain FP64 after the timed steps.
+
+Batched-level leg (level4096): 4096 boxes with edges drawn from {16, 24, 32,
+48, 64} per axis, self-periodic ghosts, per-box dt: one batched plan per
+step (also replayed as a captured HIP graph) against per-box launches.
+
+Stage times come from HIP events the library records between its stage
+launches on the step's stream.
 """
 from __future__ import annotations
 
@@ -27,56 +34,59 @@ sys.path.insert(0, ROOT)
 METRIC = "zone-updates/s (plain FP64 vs FP32+batched+learned flux) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+STAGES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")
 
-# Algorithmic floating-point operations per unit of work (+, -, *, /, sqrt
-# each count 1; comparisons, min/max and selects count 0), read off the
-# stage formulas.  `it` is the mean number of two-shock iterations.
-def flops_per_unit(stage, it):
+
+def flops_per_launch(stage, n, it):
+    """Algorithmic floating-point operations of one stage launch on an n^3 box
+    (+, -, *, /, sqrt count 1 each; comparisons, min/max, selects 0), read off
+    the stage formulas; `it` is the mean two-shock iteration count."""
+    P, E, V = (n + 8) ** 3, (n + 2) ** 3, n ** 3
+    solve = 76.0 + 36.0 * it
     return {
-        "prim": 10.0, "flat": 69.0, "trace": 530.0,
-        "riem0": 94.0 + 36.0 * it, "riem1": 194.0 + 36.0 * it, "riem2": 231.0 + 36.0 * it,
-        "update": 126.0,
+        "prim": 10.0 * P,
+        "flat": 69.0 * E,
+        "trace": 530.0 * 3 * E,
+        "riem0": solve * 3 * (n + 1) * (n + 2) ** 2,
+        "riem1": (172.0 + solve) * 6 * n * (n + 1) * (n + 2),
+        "riem2": (278.0 + solve) * 3 * n * n * (n + 1),
+        "update": 252.0 * V,
     }[stage]
 
 
-def units_per_launch(stage, n):
-    P = (n + 8) ** 3
-    E = (n + 2) ** 3
+def bytes_per_launch(stage, n, rb):
+    """Algorithmic HBM bytes of one stage launch: every distinct input value
+    read once and every output written once (rb = bytes of a stage-array
+    element: 8 in FP64, 4 in FP32-mixed)."""
+    P, E, V = (n + 8) ** 3, (n + 2) ** 3, n ** 3
     return {
-        "prim": P, "flat": E, "trace": 3 * E,
-        "riem0": 3 * (n + 1) * (n + 2) ** 2, "riem1": 6 * n * (n + 1) * (n + 2),
-        "riem2": 3 * n * n * (n + 1), "update": n ** 3,
+        "prim": 6 * 8 * P + 6 * rb * P,
+        "flat": 4 * rb * P + rb * E,
+        "trace": 6 * rb * P + 3 * rb * P + rb * E + 30 * rb * E,
+        "riem0": 30 * rb * E + 15 * rb * E,
+        "riem1": 30 * rb * E + 15 * rb * E + 30 * rb * E,
+        "riem2": 30 * rb * E + 30 * rb * E + 15 * rb * E,
+        "update": 15 * rb * E + (6 * 8 + 3 * rb) * V + 6 * 8 * V,
     }[stage]
 
 
-def bytes_per_unit(stage, rb):
-    """Algorithmic HBM bytes per unit: distinct values each unit must read
-    once and write once (rb = bytes of a stage-array element)."""
-    return {
-        "prim": 6 * 8 + 6 * rb,                 # U in (FP64), 6 primitives out
-        "flat": 4 * rb + 1 * rb,                # p and u_d along 3 lines, chi out
-        "trace": 5 * rb + 1 * rb + 1 * rb + 10 * rb,  # 5 prims + c + chi (+g) in, 10 edge values out
-        "riem0": 10 * rb + 8 * rb,              # 2 x 5 edge values in, 8 face values out
-        "riem1": 10 * rb + 8 * rb + 8 * rb,     # edge values, stage-0 t-fluxes, 8 out
-        "riem2": 10 * rb + 16 * rb + 8 * rb,    # edge values, two stage-1 fluxes, 8 out
-        "update": 8 * 3 * rb + 6 * 8 + 3 * rb + 6 * 8,  # final fluxes, U, g in; U out
-    }[stage]
+def aligned(torch, nbytes):
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + nbytes]
 
 
-def run_form(nyx, torch, w, precision, steps, warmup):
-    from paper_1301_4498_amd import synth  # noqa: F401
+def run_box(nyx, torch, w, prm, steps, warmup):
+    """Time `steps` steps (after `warmup`) of one periodic box with a one-box
+    batched plan; returns rates, stage times and the final density."""
     n = w.n[0]
-    prm = nyx.default_params(precision=precision)
     box = nyx.make_box(w.n, 4, w.dx)
-    gdt = torch.float64 if precision == nyx.NYX_FP64 else torch.float32
+    gdt = torch.float64 if prm.precision == nyx.NYX_FP64 else torch.float32
     U = torch.from_numpy(w.state).cuda()
     Uo = U.clone()
     G = torch.from_numpy(w.grav).to(gdt).cuda()
     _, one = nyx.Batch.workspace_bytes(prm, [box])
-    raw = torch.empty(one + 256, dtype=torch.uint8, device="cuda")
-    off = (-raw.data_ptr()) % 256
-    ws = raw[off:off + one]
+    ws = aligned(torch, one)
     plan = nyx.Batch(prm, [box], ws)
     dts = torch.zeros(2, dtype=torch.float64, device="cuda")
     plan.estimate_dt(U, w.a0, 0.5, dts[0:1])
@@ -84,20 +94,16 @@ def run_form(nyx, torch, w, precision, steps, warmup):
     bufs = [U, Uo]
     k = 0
 
-    def a_at(j):
-        return w.a0 + (w.a1 - w.a0) * j / w.steps
-
     def one_step(stats=None):
         nonlocal k
         src, dst = bufs[k % 2], bufs[(k + 1) % 2]
-        plan.step(src, G, dts[k % 2:k % 2 + 1], a_at(k), a_at(k + 1), dst,
+        plan.step(src, G, dts[k % 2:k % 2 + 1], w.a_at(k), w.a_at(k + 1), dst,
                   dt_next=dts[(k + 1) % 2:(k + 1) % 2 + 1], stats=stats)
         plan.fill_ghosts(dst)
         k += 1
 
-    # warmup; the first warmup step also collects counters (iterations)
     for i in range(max(warmup, 1)):
-        one_step(st if i == 0 else None)
+        one_step(st if i == 0 else None)  # counters of the first step
     torch.cuda.synchronize()
     stats = nyx.stats_dict(st)
     it = stats["riemann_iters"] / max(stats["riemann_calls"], 1)
@@ -114,38 +120,129 @@ def run_form(nyx, torch, w, precision, steps, warmup):
     ms = e0.elapsed_time(e1)
     stage_ms, seq = nyx._lib.profile_read(reset=True)
     nyx._lib.profile_enable(False)
-    dt_last = float(dts[k % 2].item())
+    rho = bufs[k % 2].reshape(6, n + 8, n + 8, n + 8)[0, 4:-4, 4:-4, 4:-4].cpu().numpy()
     finite = bool(torch.isfinite(bufs[k % 2]).all().item())
     plan.close()
-    del ws, raw, U, Uo, G
+    del ws, U, Uo, G, bufs
     torch.cuda.empty_cache()
-    zones = n ** 3 * steps
-    rb = 8 if precision == nyx.NYX_FP64 else 4
+    rb = 8 if prm.precision == nyx.NYX_FP64 else 4
     per_stage = {}
-    for s, t in stage_ms.items():
-        tl = t / max(seq, 1)  # ms per launch
-        u = units_per_launch(s, n)
-        per_stage[s] = {
-            "ms": round(tl, 4),
-            "gflops": round(flops_per_unit(s, it) * u / (tl * 1e-3) / 1e9, 1),
-            "gbs": round(bytes_per_unit(s, rb) * u / (tl * 1e-3) / 1e9, 1),
-        }
-    return {
-        "zone_updates_per_s": zones / (ms * 1e-3),
-        "ms_per_step": ms / steps,
-        "stage": per_stage,
-        "mean_riemann_iters": it,
-        "stats_first_step": stats,
-        "dt_last": dt_last,
-        "finite": finite,
-        "rb": rb,
-    }
+    for s in STAGES:
+        tl = stage_ms[s] / max(seq, 1)
+        per_stage[s] = {"ms": round(tl, 4),
+                        "tflops": round(flops_per_launch(s, n, it) / (tl * 1e-3) / 1e12, 3),
+                        "gbs": round(bytes_per_launch(s, n, rb) / (tl * 1e-3) / 1e9, 1)}
+    return {"zone_updates_per_s": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+            "stage": per_stage, "mean_riemann_iters": it, "stats_first_step": stats,
+            "finite": finite, "rho": rho}
+
+
+def train_learned(nyx, learn, synth, log):
+    """Harvest final-stage faces of plain FP64 steps on four 64^3 boxes of
+    the same field type (seeds 100-103) and train the network (untimed)."""
+    t0 = time.perf_counter()
+    ws = [synth.config2(n=64, seed=100 + s) for s in range(4)]
+    rec = learn.harvest(ws, steps=8, keep_fraction=0.15, capacity=6_000_000, seed=100)
+    f = learn.LearnedFlux(seed=1)
+    hist = f.train(rec, epochs=6, batch=16384)
+    f.pack()
+    info = {"records": int(rec.shape[0]), "epochs": 6, "loss_first_epoch": hist[0],
+            "loss_last_epoch": hist[-1], "seconds": round(time.perf_counter() - t0, 1)}
+    log("learned flux trained: %s" % info)
+    return f, info
+
+
+def level_leg(nyx, torch, synth, steps, log):
+    """4096 uneven boxes: batched plan (+ graph) against per-box launches."""
+    shapes = synth.config3_shapes()
+    t0 = time.perf_counter()
+    out = {"boxes": len(shapes), "valid_cells": int(sum(a * b * c for a, b, c in shapes))}
+    zones = out["valid_cells"]
+    res = {}
+    for form, prec in (("mixed", nyx.NYX_MIXED), ("fp64", nyx.NYX_FP64)):
+        gdt = torch.float32 if prec == nyx.NYX_MIXED else torch.float64
+        state, grav, offs = synth.level_fields_torch(shapes, grav_dtype=gdt)
+        log("level fields (%s) ready in %.1f s" % (form, time.perf_counter() - t0))
+        boxes = [nyx.make_box(n, 4, 1.0 / 256, state_off=so, grav_off=go)
+                 for n, (so, go) in zip(shapes, offs)]
+        prm = nyx.default_params(precision=prec)
+        mn, one = nyx.Batch.workspace_bytes(prm, boxes)
+        free = torch.cuda.mem_get_info()[0]
+        wsb = min(one, int(free - 2 * state.numel() * 8 - (8 << 30)))
+        ws = aligned(torch, wsb)
+        plan = nyx.Batch(prm, boxes, ws)
+        other = torch.empty_like(state)
+        dts = [torch.zeros(len(boxes), dtype=torch.float64, device="cuda") for _ in range(2)]
+        plan.estimate_dt(state, 0.25, 0.5, dts[0])
+        bufs = [state, other]
+
+        def step(k):
+            plan.step(bufs[k % 2], grav, dts[k % 2], 0.25, 0.25 + 5e-4, bufs[(k + 1) % 2],
+                      dt_next=dts[(k + 1) % 2])
+            plan.fill_ghosts(bufs[(k + 1) % 2])
+
+        step(0)
+        step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = {"batched_zone_updates_per_s": zones / (ms * 1e-3), "batched_ms_per_step": ms,
+             "groups": plan.num_groups}
+        if form == "mixed":
+            # two steps captured once, replayed
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    step(0)
+                    step(1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps // 2):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            gms = e0.elapsed_time(e1) / (2 * (steps // 2))
+            r["graph_zone_updates_per_s"] = zones / (gms * 1e-3)
+            r["graph_ms_per_step"] = gms
+        # per-box launches: one nyx_hydro_step per box (workspace of the largest box)
+        big = max(nyx.workspace_bytes(prm, b) for b in boxes)
+        wsb1 = aligned(torch, big)
+        dth = dts[0].cpu().tolist()
+        torch.cuda.synchronize()
+        e0.record()
+        for b, bx in enumerate(boxes):
+            nyx.hydro_step(prm, bx, bufs[0], grav, dth[b], 0.25, 0.25 + 5e-4, bufs[1],
+                           workspace=wsb1)
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1)
+        r["per_box_zone_updates_per_s"] = zones / (pms * 1e-3)
+        r["per_box_ms_per_step"] = pms
+        res[form] = r
+        log("level %s: %s" % (form, {k: (round(v, 3) if isinstance(v, float) else v)
+                                     for k, v in r.items()}))
+        plan.close()
+        del ws, wsb1, state, grav, other, bufs
+        torch.cuda.empty_cache()
+    out["forms"] = res
+    out["gain_batched_graph_vs_per_box_plain_fp64"] = (
+        res["mixed"]["graph_zone_updates_per_s"] / res["fp64"]["per_box_zone_updates_per_s"])
+    return out
 
 
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
-    import numpy as np
     import oracle
+    import numpy as np
     m = 64
     U = np.ascontiguousarray(w.state[:, :m + 8, :m + 8, :m + 8])
     g = np.ascontiguousarray(w.grav[:, :m + 8, :m + 8, :m + 8])
@@ -153,7 +250,7 @@ def cpu_baseline(w, budget_s=12.0):
     t0 = time.perf_counter()
     nstep = 0
     while True:
-        oracle.hydro_step(U, g, 4, dt, w.dx, w.a0, w.a0 + (w.a1 - w.a0) / w.steps)
+        oracle.hydro_step(U, g, 4, dt, w.dx, w.a0, w.a_at(1))
         nstep += 1
         if time.perf_counter() - t0 > budget_s:
             break
@@ -169,7 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,learned")
+    ap.add_argument("--no-level", action="store_true", help="skip the 4096-box batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
@@ -179,6 +277,10 @@ def main():
               "halo exchange; multi-GPU runs are not part of it)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     if args.copy_calibration:
         nbytes = 1 << 30
         a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -195,27 +297,45 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
                           "ms_per_copy": ms, "gbs_read_plus_write": 2 * nbytes / ms / 1e6}))
         return
+    import numpy as np
     import paper_1301_4498_amd as nyx
-    from paper_1301_4498_amd import synth
+    from paper_1301_4498_amd import learn, synth
     nyx.lib()
     t0 = time.perf_counter()
     w = synth.config2(n=args.n)
-    print("inputs ready in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
-    forms = {}
+    log("inputs ready in %.1f s" % (time.perf_counter() - t0))
+    forms, extra = {}, {}
     for f in args.forms.split(","):
-        prec = {"fp64": nyx.NYX_FP64, "mixed": nyx.NYX_MIXED}[f]
-        forms[f] = run_form(nyx, torch, w, prec, args.steps, args.warmup)
-        print("%s: %.3e zone-updates/s" % (f, forms[f]["zone_updates_per_s"]), file=sys.stderr,
-              flush=True)
-    chosen = "mixed" if "mixed" in forms else "fp64"
+        if f == "fp64":
+            prm = nyx.default_params(precision=nyx.NYX_FP64)
+        elif f == "mixed":
+            prm = nyx.default_params(precision=nyx.NYX_MIXED)
+        elif f == "learned":
+            flux, extra["learned_training"] = train_learned(nyx, learn, synth, log)
+            prm = learn.learned_params(flux, tol=1e-3, stages=7)
+        else:
+            raise SystemExit("unknown form " + f)
+        forms[f] = run_box(nyx, torch, w, prm, args.steps, args.warmup)
+        log("%s: %.3e zone-updates/s" % (f, forms[f]["zone_updates_per_s"]))
+    ref = forms.get("fp64")
+    for f, v in forms.items():
+        v["rho_l1_vs_fp64"] = (float(np.abs(v["rho"] - ref["rho"]).sum() / np.abs(ref["rho"]).sum())
+                               if ref is not None else None)
+    if "learned" in forms and "mixed" in forms:
+        v = forms["learned"]
+        v["rho_l1_vs_mixed"] = float(np.abs(v["rho"] - forms["mixed"]["rho"]).sum() /
+                                     np.abs(forms["mixed"]["rho"]).sum())
+        st = v["stats_first_step"]
+        v["fallback_rate"] = st["mlp_fallback"] / max(st["mlp_used"] + st["mlp_fallback"], 1)
+    ok = [f for f, v in forms.items() if v["finite"] and
+          (v["rho_l1_vs_fp64"] is None or v["rho_l1_vs_fp64"] <= 1e-3)]
+    chosen = max(ok, key=lambda f: forms[f]["zone_updates_per_s"])
     R = forms[chosen]
-    # dominant kernel of the chosen form
     dom = max(R["stage"], key=lambda s: R["stage"][s]["ms"])
     ds = R["stage"][dom]
-    alu_peak = FP64_PEAK_TFLOPS * 1e3  # the two-shock iteration is FP64 in every form
-    alu = {"bound": "alu", "achieved": ds["gflops"] / 1e3, "peak": alu_peak / 1e3,
-           "unit": "TFLOP/s", "frac": round(ds["gflops"] / alu_peak, 4), "traffic": None,
-           "kernel": dom}
+    alu = {"bound": "alu", "achieved": ds["tflops"], "peak": FP64_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(ds["tflops"] / FP64_PEAK_TFLOPS, 4),
+           "traffic": None, "kernel": dom}
     hbm = {"bound": "hbm", "achieved": ds["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ds["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
     roof, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
@@ -230,17 +350,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if chosen == "fp64" else "f32+f64",
+        "dtype": "f64" if chosen == "fp64" else ("f32+f64+bf16" if chosen == "learned" else "f32+f64"),
         "data": "synthetic",
         "config": {"workload": "box256_smooth: one periodic %d^3 box + 4 ghosts, smooth-flow "
                                "fields, a 0.25->0.26, CFL 0.5" % args.n,
                    "form": chosen, "parallelism": "none"},
-        "forms": {f: {"zone_updates_per_s": v["zone_updates_per_s"], "ms_per_step": v["ms_per_step"],
-                      "stage": v["stage"], "mean_riemann_iters": v["mean_riemann_iters"],
-                      "finite": v["finite"]} for f, v in forms.items()},
+        "forms": {f: {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage",
+                                         "mean_riemann_iters", "finite", "rho_l1_vs_fp64")
+                      if k in v} for f, v in forms.items()},
         "roofline": roof,
         "roofline_other": other,
     }
+    if "learned" in forms:
+        out["forms"]["learned"]["rho_l1_vs_mixed"] = forms["learned"].get("rho_l1_vs_mixed")
+        out["forms"]["learned"]["fallback_rate"] = forms["learned"].get("fallback_rate")
+        out["learned_training"] = extra["learned_training"]
+    if not args.no_level:
+        out["level4096"] = level_leg(nyx, torch, synth, max(args.steps // 2 * 2, 2), log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

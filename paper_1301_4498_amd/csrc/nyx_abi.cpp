@@ -84,6 +84,7 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   a.small_dens = p->small_dens;
   a.small_pres = p->small_pres;
   a.riemann_tol = p->riemann_tol;
+  a.riemann_tol_sqrt = std::sqrt(p->riemann_tol);
   a.cfl = p->cfl;
   a.maxiter = p->riemann_maxiter;
   const bool learned = p->riemann == NYX_RIEMANN_LEARNED;

@@ -507,12 +507,15 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
   const double W0L = t.CL * rsq64(t.CL), W0R = t.CR * rsq64(t.CR);
   double p = ((W0R * t.pl + W0L * t.pr) + (W0L * W0R) * (t.ul - t.ur)) * rcp64(W0L + W0R);
   p = vmax(p, t.sp);
+  // Newton converges quadratically here (Z_K is the exact slope), so once a
+  // step is below sqrt(tol) p the next one would be below about tol p: stop
+  // there instead of taking that confirming step.
   int it = 0;
   while (it < A.maxiter) {
     const TwoShockEval e = ts_eval(t, p);
     const double pn = ts_newton(t, e, p);
     ++it;
-    const bool conv = fabs(pn - p) <= A.riemann_tol * pn;
+    const bool conv = fabs(pn - p) <= A.riemann_tol_sqrt * pn;
     p = pn;
     if (conv) break;
   }
@@ -838,11 +841,15 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
 // by stage-0 t-fluxes (t = t1 and t = t2), Riemann -> F^{d|t1}, F^{d|t2}.
 // Both pairs share the loads of the d-states.
 // ---------------------------------------------------------------------------
+// Plain form: grid.y = 3 directions, both pairs of a direction per thread.
+// Learned form: grid.y = 6, one (direction, pair) per thread (fewer live
+// registers next to the network's accumulators).
 template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
-  int d;
-  Loc L = locate(A, kSpaceE, &d);
+  int y;
+  Loc L = locate(A, kSpaceE, &y);
+  const int d = LEARNED ? y >> 1 : y;
   const BoxDev& b = *L.bd;
   unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
   int c[3] = {0, 0, 0};
@@ -850,8 +857,9 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
   const long long e = L.idx;
   const int ts[2] = {(d + 1) % 3, (d + 2) % 3};
   const bool inb = L.idx < b.E && c[d] >= 1;
-  const bool want[2] = {inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
-                        inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
+  const bool pick0 = !LEARNED || (y & 1) == 0, pick1 = !LEARNED || (y & 1) == 1;
+  const bool want[2] = {pick0 && inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
+                        pick1 && inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
   double q[2][5];
   const long long sdd = e_stride(b, d);
   if (want[0] || want[1]) {
@@ -862,7 +870,8 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
       for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
     }
   }
-  for (int k = 0; k < 2; ++k) {
+  const int kfirst = LEARNED ? (y & 1) : 0, klast = LEARNED ? (y & 1) : 1;
+  for (int k = kfirst; k <= klast; ++k) {
     const bool active = want[k];
     double ql[5], qr[5];
     if (active) {
@@ -1118,7 +1127,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   if (learned(0)) hipLaunchKernelGGL(k_riem0<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   else hipLaunchKernelGGL(k_riem0<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(4);
-  if (learned(1)) hipLaunchKernelGGL(k_riem1<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  if (learned(1)) hipLaunchKernelGGL(k_riem1<kHasLearned>, dim3(a.nblocks[kSpaceE], 6), blk, 0, s, a);
   else hipLaunchKernelGGL(k_riem1<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(5);
   if (learned(2)) hipLaunchKernelGGL(k_riem2<kHasLearned ? 1 : 0>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);

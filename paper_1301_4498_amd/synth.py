@@ -189,3 +189,57 @@ def random_box(n, seed: int, a: float = 0.5, kind: int = 1):
     rng = np.random.default_rng(seed)
     U, g = (_box_fields_cfg1 if kind == 1 else _box_fields_cfg2)(rng, n, a)
     return pad_periodic(U), pad_periodic(g)
+
+
+def level_fields_torch(shapes, seed: int = 3, a: float = 0.25, gamma: float = GAMMA,
+                       ng: int = NG, grav_dtype=None, device: str = "cuda"):
+    """The batched AMR level (config-2 distributions per box) generated on the
+    device with torch's seeded generator, for levels too large to draw with
+    numpy in reasonable time.  Returns (state, grav, offsets) where state and
+    grav are flat device tensors holding every padded box back to back and
+    offsets[b] = (state_off, grav_off) in elements."""
+    import torch
+    gdt = grav_dtype or torch.float64
+    sizes = [(n[0] + 2 * ng) * (n[1] + 2 * ng) * (n[2] + 2 * ng) for n in shapes]
+    tot = sum(sizes)
+    state = torch.empty(6 * tot, dtype=torch.float64, device=device)
+    grav = torch.empty(3 * tot, dtype=gdt, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    offs = []
+    so = go = 0
+    cache = {}
+    for (nx, ny, nz), P in zip(shapes, sizes):
+        shape = (nz, ny, nx)
+        if shape not in cache:
+            kz = torch.fft.fftfreq(nz, device=device) * nz
+            ky = torch.fft.fftfreq(ny, device=device) * ny
+            kx = torch.fft.rfftfreq(nx, device=device) * nx
+            k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+            filt = torch.where(k2 > 0, k2.clamp_min(1e-30).rsqrt(), torch.zeros_like(k2))
+            cache[shape] = filt.to(torch.float64)
+        filt = cache[shape]
+        s_ln = 0.3
+        rho = torch.exp(torch.randn(shape, generator=gen, device=device, dtype=torch.float64) * s_ln
+                        - 0.5 * s_ln * s_ln)
+        u = []
+        for _ in range(3):
+            w = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+            f = torch.fft.irfftn(torch.fft.rfftn(w) * filt, s=shape)
+            f = f - f.mean()
+            sd = f.std(unbiased=False)
+            u.append(f * (0.5 / sd))
+        p = 0.6 * rho ** gamma
+        g = torch.randn((3,) + shape, generator=gen, device=device, dtype=torch.float64) * 0.05
+        ke = 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+        rei = p / (gamma - 1.0)
+        U = torch.stack([rho, a * rho * u[0], a * rho * u[1], a * rho * u[2],
+                         a * a * (rei + ke), a * a * rei])
+        Up = torch.nn.functional.pad(U[None], (ng,) * 6, mode="circular")[0]
+        gp = torch.nn.functional.pad(g[None], (ng,) * 6, mode="circular")[0]
+        state[so:so + 6 * P] = Up.reshape(-1)
+        grav[go:go + 3 * P] = gp.reshape(-1).to(gdt)
+        offs.append((so, go))
+        so += 6 * P
+        go += 3 * P
+    return state, grav, offs
