@@ -17,9 +17,15 @@ using namespace nyx;
 namespace {
 
 // Single-box workspace header: [0, 256) running maximum of the CFL reduction,
-// then kStatSlots x kStatFields partial counters; stage arrays follow.
+// then kStatSlots x kStatFields partial counters, the one-entry box table, its
+// block prefixes and the box's step constants; stage arrays follow.
 constexpr size_t kSlotBytes = sizeof(unsigned long long) * kStatSlots * kStatFields;
-constexpr size_t kHeaderBytes = 256 + (kSlotBytes + 255) / 256 * 256;
+constexpr size_t kOffSlots = 256;
+constexpr size_t kOffTable = kOffSlots + (kSlotBytes + 255) / 256 * 256;
+constexpr size_t kOffPrefix = kOffTable + 256;
+constexpr size_t kOffConsts = kOffPrefix + 256;
+constexpr size_t kHeaderBytes = kOffConsts + 256;
+static_assert(sizeof(BoxDev) <= 256 && sizeof(StepC) <= 256, "header slots");
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -222,9 +228,17 @@ int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_
   A.a_old = a_old;
   A.a_new = a_new;
   A.stats = stats;
-  A.slots = (unsigned long long*)((char*)workspace + 256);
+  A.slots = (unsigned long long*)((char*)workspace + kOffSlots);
   A.dt_next = dt_next;
   hipStream_t s = (hipStream_t)stream;
+  BoxDev* tab = (BoxDev*)((char*)workspace + kOffTable);
+  int* pre = (int*)((char*)workspace + kOffPrefix);
+  StepC* cst = (StepC*)((char*)workspace + kOffConsts);
+  if (launch_prologue(A, 1, cst, tab, pre, s) != hipSuccess) return NYX_E_HIP;
+  A.table = tab;
+  A.nb = 1;
+  for (int k = 0; k < 3; ++k) A.prefix[k] = pre + 2 * k;
+  A.consts = cst;
   if (dt_next && launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
   if (stats && launch_zero_u64(A.slots, kStatSlots * kStatFields, s) != hipSuccess) return NYX_E_HIP;
   if (run_stages(p, A, s) != hipSuccess) return NYX_E_HIP;
@@ -251,6 +265,7 @@ struct nyx_batch {
   BoxDev* table;                 // device, nbox entries in box order
   unsigned long long* smax;      // device, nbox entries
   unsigned long long* slots;     // device, partial counters
+  StepC* consts;                 // device, per-box step constants
   void* stage;                   // device stage region
   size_t state_span;             // bytes spanned by the state of all boxes
   // training-record harvest (final-stage faces)
@@ -268,7 +283,8 @@ size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 // bytes of the table region for a plan with `ngroups` groups
 size_t table_bytes(int nbox, int ngroups) {
   return round256(sizeof(BoxDev) * (size_t)nbox) + round256(sizeof(int) * 3 * (size_t)(nbox + ngroups)) +
-         round256(sizeof(unsigned long long) * (size_t)nbox) + round256(kSlotBytes);
+         round256(sizeof(unsigned long long) * (size_t)nbox) + round256(kSlotBytes) +
+         round256(sizeof(StepC) * (size_t)nbox);
 }
 
 int check_boxes(const nyx_params* p, int nbox, const nyx_box* boxes) {
@@ -360,6 +376,7 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
   int* pre_dev = (int*)(w + round256(sizeof(BoxDev) * (size_t)nbox));
   plan->smax = (unsigned long long*)((char*)pre_dev + round256(sizeof(int) * 3 * (size_t)(nbox + nbox)));
   plan->slots = (unsigned long long*)((char*)plan->smax + round256(sizeof(unsigned long long) * (size_t)nbox));
+  plan->consts = (StepC*)((char*)plan->slots + round256(kSlotBytes));
   plan->stage = w + tbytes;
   plan->state_span = span;
   for (auto& g : plan->groups)
@@ -399,6 +416,7 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   A.work = plan->stage;
   A.smax = plan->smax;
   A.slots = plan->slots;
+  A.consts = plan->consts;
   fill_physics(A, &plan->prm);
   A.harvest = plan->harvest;
   A.harvest_count = plan->harvest_count;
@@ -451,6 +469,14 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
   if (dt_next && launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
   if (stats && launch_zero_u64(plan->slots, kStatSlots * kStatFields, s) != hipSuccess)
     return NYX_E_HIP;
+  {
+    StepArgs P = all_boxes_args(plan);
+    P.dt_dev = dt;
+    P.a_old = a_old;
+    P.a_new = a_new;
+    if (launch_prologue(P, plan->nbox, plan->consts, nullptr, nullptr, s) != hipSuccess)
+      return NYX_E_HIP;
+  }
   for (const auto& g : plan->groups) {
     StepArgs A = group_args(plan, g);
     A.Uin = state_in;

@@ -92,6 +92,13 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   return o;
 }
 
+// Per-box constants of a step, computed once per box by the step's prologue
+// kernel (the same expressions the oracle evaluates on the host).
+struct StepC {
+  double dt, a_h, da, kh, hdt_a, hda_a, pexp, kap1, kap2, k, gm1;
+  double pad_;
+};
+
 // Which cell range a launch walks.
 enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2 };
 
@@ -125,7 +132,8 @@ __device__ __forceinline__ void space_coords(const BoxDev& b, int space, unsigne
 
 // Launch-wide arguments of a step.
 struct StepArgs {
-  // box selection: either one box by value, or a device table + block prefix
+  // box selection: a device table + block prefix per Space (the single-box
+  // entry points write a one-entry table in their prologue)
   BoxDev single;
   const BoxDev* table;     // device, nb entries (batched) or nullptr
   const int* prefix[3];    // device, nb+1 block prefixes per Space (batched)
@@ -147,6 +155,7 @@ struct StepArgs {
   unsigned long long* slots;  // kStatSlots x kStatFields partial counters (when stats)
   double* dt_next;
   hipEvent_t* ev;          // kStages + 1 events recorded around the stages, or nullptr
+  const StepC* consts;     // per-box step constants, indexed by gidx
   // learned Riemann flux (FP32-mixed build only)
   const void* mlp;         // packed network, or nullptr
   int learned_mask;        // bit s: stage s (0, 1, 2) uses the network
@@ -176,6 +185,11 @@ hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, dou
                               hipStream_t s);
 hipError_t launch_min_dt(double* dt, int n, hipStream_t s);
 hipError_t launch_stats_reduce(const unsigned long long* slots, nyx_stats* stats, hipStream_t s);
+// Step prologue: per-box step constants of boxes [0, nbox) of `a.table` (or
+// of a.single when single_dst is given, which also receives a.single and the
+// one-box block prefixes).
+hipError_t launch_prologue(const StepArgs& a, int nbox, StepC* consts, BoxDev* single_dst,
+                           int* prefix_dst, hipStream_t s);
 // learned flux (nyx_mlp.hip)
 hipError_t launch_mlp_init(float* P, unsigned long long seed, hipStream_t st);
 hipError_t launch_mlp_loss_grad(const float* P, const float* rec, long long n, double gamma,

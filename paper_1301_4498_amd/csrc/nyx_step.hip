@@ -63,50 +63,25 @@ struct Loc {
 // grid-y coordinate (direction or direction pair) after XCD renumbering.
 __device__ __forceinline__ Loc locate(const StepArgs& A, int space, int* ylane = nullptr) {
   Loc L;
-  unsigned lb;
   const unsigned lin = xcd_linear_block();
   const unsigned bx = lin % gridDim.x;
   if (ylane) *ylane = (int)(lin / gridDim.x);
-  if (A.table == nullptr) {
-    L.bd = &A.single;
-    lb = bx;
-  } else {
-    const int* pre = A.prefix[space];
-    int lo = 0, hi = A.nb;  // find b with pre[b] <= bx < pre[b+1]
-    int x = (int)bx;
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (pre[mid] <= x) lo = mid;
-      else hi = mid;
-    }
-    L.bd = A.table + lo;
-    lb = x - pre[lo];
+  const int* pre = A.prefix[space];
+  int lo = 0, hi = A.nb;  // find b with pre[b] <= bx < pre[b+1]
+  const int x = (int)bx;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (pre[mid] <= x) lo = mid;
+    else hi = mid;
   }
-  L.idx = lb * (unsigned)kBlock + threadIdx.x;
+  L.bd = A.table + lo;
+  L.idx = (unsigned)(x - pre[lo]) * (unsigned)kBlock + threadIdx.x;
   return L;
 }
 
-// ---------------------------------------------------------------------------
-// per-box constants of the step (same expressions as the host reference)
-// ---------------------------------------------------------------------------
-struct StepC {
-  double dt, a_h, da, kh, hdt_a, hda_a, pexp, kap1, kap2, k, gm1;
-};
-
-__device__ __forceinline__ StepC step_consts(const StepArgs& A, const BoxDev& b) {
-  StepC c;
-  c.dt = A.dt_dev ? A.dt_dev[b.gidx] : A.dt_host;
-  c.gm1 = A.gamma - 1.0;
-  c.a_h = 0.5 * (A.a_old + A.a_new);
-  c.da = A.a_new - A.a_old;
-  c.kh = c.dt / (c.a_h * b.dx);
-  c.hdt_a = (0.5 * c.dt) / c.a_h;
-  c.hda_a = (0.5 * c.da) / c.a_h;
-  c.pexp = (1.5 * c.gm1) * (c.da / c.a_h);
-  c.kap1 = c.kh / 3.0;
-  c.kap2 = c.kh / 2.0;
-  c.k = c.dt / b.dx;
-  return c;
+// per-box constants of the step, computed once per box by the prologue
+__device__ __forceinline__ const StepC& step_consts(const StepArgs& A, const BoxDev& b) {
+  return A.consts[b.gidx];
 }
 
 // ---------------------------------------------------------------------------
@@ -232,16 +207,22 @@ __device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
   }
   return (real)0;
 }
-// interface value between the second and third of four consecutive cells
-__device__ __forceinline__ real ppm_face(real q0, real q1, real q2, real q3) {
-  real s0 = lim_slope(q0, q1, q2);
-  real s1 = lim_slope(q1, q2, q3);
-  return (q1 + (real)0.5 * (q2 - q1)) - (s1 - s0) / (real)6;
+// interface value between cells a and b from their limited slopes sa, sb
+__device__ __forceinline__ real ppm_face(real qa, real qb, real sa, real sb) {
+#if defined(NYX_PREC_MIXED)
+  return (qa + (real)0.5 * (qb - qa)) - (sb - sa) * (real)(1.0 / 6.0);
+#else
+  return (qa + (real)0.5 * (qb - qa)) - (sb - sa) / (real)6;
+#endif
 }
 __device__ __forceinline__ void ppm_edges(const real* q5, real chi, real& qm_o, real& qp_o) {
   real qj = q5[2];
-  real qp = ppm_face(q5[1], q5[2], q5[3], q5[4]);
-  real qm = ppm_face(q5[0], q5[1], q5[2], q5[3]);
+  // slopes of cells j-1, j, j+1, each computed once
+  const real sm = lim_slope(q5[0], q5[1], q5[2]);
+  const real s0 = lim_slope(q5[1], q5[2], q5[3]);
+  const real sp = lim_slope(q5[2], q5[3], q5[4]);
+  real qp = ppm_face(q5[2], q5[3], s0, sp);
+  real qm = ppm_face(q5[1], q5[2], sm, s0);
   qp = chi * qp + ((real)1 - chi) * qj;
   qm = chi * qm + ((real)1 - chi) * qj;
   if ((qp - qj) * (qj - qm) <= (real)0) {
@@ -250,7 +231,11 @@ __device__ __forceinline__ void ppm_edges(const real* q5, real chi, real& qm_o, 
   } else {
     real dq = qp - qm;
     real t = dq * (qj - (real)0.5 * (qm + qp));
+#if defined(NYX_PREC_MIXED)
+    real s = dq * dq * (real)(1.0 / 6.0);
+#else
     real s = dq * dq / (real)6;
+#endif
     if (t > s) qm = (real)3 * qj - (real)2 * qp;
     else if (-s > t) qp = (real)3 * qj - (real)2 * qm;
   }
@@ -325,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
     int ec[3];
     space_coords(b, kSpaceE, L.idx, ec);
     const int ie = ec[0], je = ec[1], ke = ec[2];
-    const StepC C = step_consts(A, b);
+    const StepC& C = step_consts(A, b);
     const real* prim = (const real*)A.work + b.w_prim;
     const long long c0 = pidx_e(b, ie, je, ke);
     const long long s = d == 0 ? 1 : (d == 1 ? (long long)b.px : (long long)b.px * b.py);
@@ -657,9 +642,16 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const real* G, lo
   f[1 + d] = ru * u + p;
   f[1 + t1] = ru * v;
   f[1 + t2] = ru * w;
+#if defined(NYX_PREC_MIXED)
+  const real igm1 = (real)1 / gm1;
+  const real rE = p * igm1 + ((real)0.5 * r) * ((u * u + v * v) + w * w);
+  f[4] = u * (rE + p);
+  f[5] = (u * p) * igm1;
+#else
   const real rE = p / gm1 + ((real)0.5 * r) * ((u * u + v * v) + w * w);
   f[4] = u * (rE + p);
   f[5] = (u * p) / gm1;
+#endif
   f[6] = p;
   f[7] = u;
 }
@@ -685,12 +677,21 @@ __device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, cons
   real fm[8], fp[8];
   face_flux(gamma, t, Glo, E, fm);
   face_flux(gamma, t, Ghi, E, fp);
+#if defined(NYX_PREC_MIXED)
+  // flux differences are flux arithmetic: FP32, widened once
+  for (int c = 0; c < 5; ++c) {
+    const double dd = (double)(fp[c] - fm[c]);
+    Dc[c] = FIRST ? dd : Dc[c] + dd;
+  }
+  const double de = (double)((fp[5] - fm[5]) + (0.5f * (fp[6] + fm[6])) * (fp[7] - fm[7]));
+#else
   for (int c = 0; c < 5; ++c) {
     const double dd = (double)fp[c] - (double)fm[c];
     Dc[c] = FIRST ? dd : Dc[c] + dd;
   }
   const double de = ((double)fp[5] - (double)fm[5]) +
                     (0.5 * ((double)fp[6] + (double)fm[6])) * ((double)fp[7] - (double)fm[7]);
+#endif
   De = FIRST ? de : De + de;
 }
 
@@ -714,7 +715,7 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
   for (int c = 0; c < 5; ++c) Un[c] = U[c] - kap * Dc[c];
   const double Uen = Ue - kap * De;
 #if defined(NYX_PREC_MIXED)
-  const double iU0 = 1.0 / Un[0];
+  const double iU0 = rcp64(Un[0]);
   const double ke = (0.5 * ((Un[1] * Un[1] + Un[2] * Un[2]) + Un[3] * Un[3])) * iU0;
 #else
   const double ke = (0.5 * ((Un[1] * Un[1] + Un[2] * Un[2]) + Un[3] * Un[3])) / Un[0];
@@ -875,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
     const bool active = want[k];
     double ql[5], qr[5];
     if (active) {
-      const StepC C = step_consts(A, b);
+      const StepC& C = step_consts(A, b);
       const int t = ts[k];
       const long long stt = e_stride(b, t);
       const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
                       c[t2] <= b.n[t2];
   double ql[5], qr[5];
   if (active) {
-    const StepC C = step_consts(A, b);
+    const StepC& C = step_consts(A, b);
     const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
     const real* W = (const real*)A.work + b.w_edge;
     const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
@@ -1007,6 +1008,17 @@ __device__ __forceinline__ double cell_speed(const StepArgs& A, double U0, doubl
                                              double m2, double Ue, double a) {
   const double gm1 = A.gamma - 1.0;
   double rho = vmax(U0, A.small_dens);
+#if defined(NYX_PREC_MIXED)
+  const double iar = rcp64(a * rho);
+  double re = Ue * rcp64(a * a);
+  double p = vmax(gm1 * re, A.small_pres);
+  const double x = (A.gamma * p) * rcp64(rho);
+  double c = x * rsq64(x);
+  double s = 0.0;
+  s = vmax(s, fabs(m0 * iar) + c);
+  s = vmax(s, fabs(m1 * iar) + c);
+  s = vmax(s, fabs(m2 * iar) + c);
+#else
   double re = Ue / (a * a);
   double p = vmax(gm1 * re, A.small_pres);
   double c = sqrt((A.gamma * p) / rho);
@@ -1014,6 +1026,7 @@ __device__ __forceinline__ double cell_speed(const StepArgs& A, double U0, doubl
   s = vmax(s, fabs(m0 / (a * rho)) + c);
   s = vmax(s, fabs(m1 / (a * rho)) + c);
   s = vmax(s, fabs(m2 / (a * rho)) + c);
+#endif
   return s;
 }
 
@@ -1041,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     int vc[3];
     space_coords(b, kSpaceV, L.idx, vc);
     const int i = vc[0], j = vc[1], k = vc[2];
-    const StepC C = step_consts(A, b);
+    const StepC& C = step_consts(A, b);
     const long long e = ((long long)(k + 1) * b.ey + (j + 1)) * b.ex + (i + 1);
     const real* G2 = (const real*)A.work + b.w_f2;
     const real ah = (real)C.a_h;
@@ -1081,7 +1094,11 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
                                    (sm[2] - Um[2]) * g[2]);
     double ne = se;
     // dual-energy sync (Step 6)
+#if defined(NYX_PREC_MIXED)
+    const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) * rcp64(s0);
+#else
     const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;
+#endif
     if (nE - ke > A.eta * nE) {
       ne = nE - ke;
     } else {

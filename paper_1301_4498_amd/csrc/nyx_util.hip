@@ -91,6 +91,41 @@ hipError_t launch_dt_finalize(const StepArgs& a, double a_state, double cfl, dou
   return hipGetLastError();
 }
 
+__global__ void k_prologue(StepArgs A, int nbox, StepC* consts, BoxDev* single_dst,
+                           int* prefix_dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbox) return;
+  const BoxDev& b = single_dst ? A.single : A.table[i];
+  if (single_dst && i == 0) {
+    *single_dst = A.single;
+    for (int s = 0; s < 3; ++s) {
+      prefix_dst[2 * s] = 0;
+      prefix_dst[2 * s + 1] = A.nblocks[s];
+    }
+  }
+  StepC c;
+  c.dt = A.dt_dev ? A.dt_dev[b.gidx] : A.dt_host;
+  c.gm1 = A.gamma - 1.0;
+  c.a_h = 0.5 * (A.a_old + A.a_new);
+  c.da = A.a_new - A.a_old;
+  c.kh = c.dt / (c.a_h * b.dx);
+  c.hdt_a = (0.5 * c.dt) / c.a_h;
+  c.hda_a = (0.5 * c.da) / c.a_h;
+  c.pexp = (1.5 * c.gm1) * (c.da / c.a_h);
+  c.kap1 = c.kh / 3.0;
+  c.kap2 = c.kh / 2.0;
+  c.k = c.dt / b.dx;
+  c.pad_ = 0.0;
+  consts[b.gidx] = c;
+}
+
+hipError_t launch_prologue(const StepArgs& a, int nbox, StepC* consts, BoxDev* single_dst,
+                           int* prefix_dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_prologue, dim3((nbox + 63) / 64), dim3(64), 0, s, a, nbox, consts, single_dst,
+                     prefix_dst);
+  return hipGetLastError();
+}
+
 // sum the per-slot partial counters into the caller's nyx_stats
 __global__ void k_stats_reduce(const unsigned long long* slots, unsigned long long* stats) {
   const int f = threadIdx.x;
