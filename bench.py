@@ -17,6 +17,11 @@ Batched-level leg (level4096): 4096 boxes with edges drawn from {16, 24, 32,
 48, 64} per axis, self-periodic ghosts, per-box dt: one batched plan per
 step (also replayed as a captured HIP graph) against per-box launches.
 
+Stress leg (box512_stress): a 512^3 domain with density contrast up to 10^4
+and flows up to Mach 30, plain FP64 as one box against FP32-mixed (and the
+learned flux) on an 8^3 grid of 64^3 patches with the same-level ghost fill
+and one level dt; density relative L1 against FP64 and the fallback rate.
+
 Stage times come from HIP events the library records between its stage
 launches on the step's stream.
 """
@@ -267,6 +272,92 @@ def level_leg(nyx, torch, synth, steps, log):
     return out
 
 
+def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
+    """box512_stress: plain FP64 with the domain as one box, against FP32-mixed
+    (and mixed + learned flux) on an (n/m)^3 grid of m^3 patches with the
+    same-level ghost fill and one level dt (the FP64 run's dt sequence).
+    Reports rates, density relative L1 against FP64 and the fallback rate."""
+    t0 = time.perf_counter()
+    grid = (n // m,) * 3
+    nb = grid[0] * grid[1] * grid[2]
+    a0, a1 = 0.10, 0.11
+
+    def a_at(k):
+        return a0 + (a1 - a0) * k / steps
+
+    state, grav = synth.stress_fields_torch(n=n)
+    A0 = torch.cat([p.reshape(-1) for p in synth.split_patches(state, grid)])
+    G32 = torch.cat([p.reshape(-1).float() for p in synth.split_patches(grav, grid)])
+    log("stress fields ready in %.1f s" % (time.perf_counter() - t0))
+    zones = n ** 3
+    out = {"workload": "box512_stress: %d^3, density contrast <= 1e4, Mach <= 30, g ~ N(0, 0.2^2), "
+                       "a 0.10->0.11" % n, "steps": steps, "patches": "%d x %d^3" % (nb, m)}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # plain FP64, one box
+    prm = nyx.default_params()
+    box = nyx.make_box((n, n, n), 4, 1.0 / n)
+    _, one = nyx.Batch.workspace_bytes(prm, [box])
+    ws = aligned(torch, one)
+    plan = nyx.Batch(prm, [box], ws)
+    bufs = [state, torch.empty_like(state)]
+    dts = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    st = torch.zeros(10, dtype=torch.int64, device="cuda")
+    plan.estimate_dt(state, a0, 0.5, dts[0:1])
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(steps):
+        plan.step(bufs[k % 2], grav, dts[k:k + 1], a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
+                  dt_next=dts[k + 1:k + 2], stats=st if k == 0 else None)
+        plan.fill_ghosts(bufs[(k + 1) % 2])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rho64 = bufs[steps % 2][0, 4:-4, 4:-4, 4:-4].contiguous()
+    s64 = nyx.stats_dict(st)
+    out["fp64_one_box"] = {"zone_updates_per_s": zones * steps / (ms * 1e-3),
+                           "ms_per_step": ms / steps, "stats_first_step": s64}
+    plan.close()
+    del plan, ws, bufs, state, grav
+    torch.cuda.empty_cache()
+    dtp = dts[:steps, None].expand(steps, nb).contiguous()
+    P = (m + 8) ** 3
+    boxes = [nyx.make_box((m, m, m), 4, 1.0 / n, state_off=6 * P * b, grav_off=3 * P * b)
+             for b in range(nb)]
+    runs = [("mixed_patches", nyx.default_params(precision=nyx.NYX_MIXED))]
+    if flux is not None:
+        runs.append(("learned_patches", learn.learned_params(flux, tol=1e-3, stages=7)))
+    for name, prm in runs:
+        _, one = nyx.Batch.workspace_bytes(prm, boxes)
+        ws = aligned(torch, one)
+        plan = nyx.Batch(prm, boxes, ws)
+        bufs = [A0.clone(), torch.empty_like(A0)]
+        st.zero_()
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            plan.step(bufs[k % 2], G32, dtp[k], a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
+                      stats=st if k == 0 else None)
+            plan.fill_ghosts(bufs[(k + 1) % 2], mode=1, grid=grid)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rho = synth.join_valid(bufs[steps % 2], grid, (m, m, m))[0]
+        l1 = float((rho - rho64).abs().sum() / rho64.abs().sum())
+        s = nyx.stats_dict(st)
+        r = {"zone_updates_per_s": zones * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+             "rho_l1_vs_fp64": l1, "finite": bool(torch.isfinite(bufs[steps % 2]).all().item()),
+             "stats_first_step": s}
+        if name == "learned_patches":
+            r["fallback_rate"] = s["mlp_fallback"] / max(s["mlp_used"] + s["mlp_fallback"], 1)
+        out[name] = r
+        log("stress %s: %.3e zone-updates/s, rho L1 vs FP64 %.2e" % (name, r["zone_updates_per_s"], l1))
+        plan.close()
+        del plan, ws, bufs
+        torch.cuda.empty_cache()
+    log("stress fp64 one box: %.3e zone-updates/s" % out["fp64_one_box"]["zone_updates_per_s"])
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
     import oracle
@@ -297,6 +388,7 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed,learned")
     ap.add_argument("--no-level", action="store_true", help="skip the 4096-box batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 512^3 stress leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -333,6 +425,7 @@ def main():
     w = synth.config2(n=args.n)
     log("inputs ready in %.1f s" % (time.perf_counter() - t0))
     forms, extra = {}, {}
+    flux = None
     for f in args.forms.split(","):
         if f == "fp64":
             prm = nyx.default_params(precision=nyx.NYX_FP64)
@@ -405,6 +498,9 @@ def main():
         out["learned_training"] = extra["learned_training"]
     if not args.no_level:
         out["level4096"] = level_leg(nyx, torch, synth, max(args.steps // 2 * 2, 2), log)
+    if not args.no_stress:
+        out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
+                                          flux if "learned" in forms else None, 10, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

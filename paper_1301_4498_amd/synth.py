@@ -43,7 +43,7 @@ def smooth_k2(rng: np.random.Generator, shape, sigma: float) -> np.ndarray:
     filt = np.zeros_like(k2)
     nz = k2 > 0
     filt[nz] = 1.0 / np.sqrt(k2[nz])
-    f = np.fft.irfftn(fk * filt, s=shape)
+    f = np.fft.irfftn(fk * filt, s=shape, axes=(0, 1, 2))
     f -= f.mean()
     sd = f.std()
     return f * (sigma / sd) if sd > 0 else f
@@ -243,3 +243,99 @@ def level_fields_torch(shapes, seed: int = 3, a: float = 0.25, gamma: float = GA
         so += 6 * P
         go += 3 * P
     return state, grav, offs
+
+
+def _k2_filter_torch(shape, device):
+    """|k|^-1 filter (k = 0 removed) on the rfft grid of ``shape`` = (nz, ny, nx)."""
+    import torch
+    nz, ny, nx = shape
+    kz = torch.fft.fftfreq(nz, device=device, dtype=torch.float64) * nz
+    ky = torch.fft.fftfreq(ny, device=device, dtype=torch.float64) * ny
+    kx = torch.fft.rfftfreq(nx, device=device, dtype=torch.float64) * nx
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    return torch.where(k2 > 0, k2.clamp_min(1e-30).rsqrt(), torch.zeros_like(k2))
+
+
+def stress_fields_torch(n: int = 512, seed: int = 5, a: float = 0.10, gamma: float = GAMMA,
+                        ng: int = NG, device: str = "cuda"):
+    """The box512_stress fields of ``config5`` drawn on the device with torch's
+    seeded generator (the numpy version of a 512^3 box takes minutes on the
+    host).  Same distributions, different random stream.  Returns the padded
+    state (6, n+2ng, n+2ng, n+2ng) and gravity (3, ...) as float64 device
+    tensors."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    shape = (n, n, n)
+    f64 = torch.float64
+
+    def randn(sh):
+        return torch.randn(sh, generator=gen, device=device, dtype=f64)
+
+    lnr = (randn(shape) * 2.0).clamp_(-float(np.log(100.0)), float(np.log(100.0)))
+    rho = torch.exp(lnr)
+    del lnr
+    s_t = 1.5
+    T = torch.exp(randn(shape) * s_t - 0.5 * s_t * s_t)
+    c0 = 0.05
+    p = rho * T * (c0 * c0 / gamma)
+    del T
+    filt = _k2_filter_torch(shape, device)
+    u = []
+    for _ in range(3):
+        f = torch.fft.irfftn(torch.fft.rfftn(randn(shape)) * filt, s=shape)
+        f -= f.mean()
+        f *= 0.5 / f.std(unbiased=False)
+        u.append(f)
+    del filt
+    c = torch.sqrt(gamma * p / rho)
+    umag = torch.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+    scale = torch.clamp(30.0 * c / umag.clamp_min(1e-300), max=1.0)
+    del c, umag
+    u = [x * scale for x in u]
+    del scale
+    ke = 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    rei = p / (gamma - 1.0)
+    del p
+    state = torch.empty((6,) + tuple(s + 2 * ng for s in shape), dtype=f64, device=device)
+    comps = [rho, a * rho * u[0], a * rho * u[1], a * rho * u[2], a * a * (rei + ke), a * a * rei]
+    del u, ke, rei, rho
+    for i, comp in enumerate(comps):
+        state[i] = torch.nn.functional.pad(comp[None, None], (ng,) * 6, mode="circular")[0, 0]
+        comps[i] = None
+    grav = torch.empty((3,) + state.shape[1:], dtype=f64, device=device)
+    for i in range(3):
+        grav[i] = torch.nn.functional.pad((randn(shape) * 0.2)[None, None], (ng,) * 6,
+                                          mode="circular")[0, 0]
+    return state, grav
+
+
+def split_patches(f, grid, ng: int = NG):
+    """Cut a padded periodic domain (ncomp, Z + 2ng, Y + 2ng, X + 2ng) into
+    gx * gy * gz padded patches of equal size, x fastest, each with its true
+    neighbours as ghost cells.  Works on numpy arrays and torch tensors;
+    returns views."""
+    gx, gy, gz = grid
+    mz = (f.shape[1] - 2 * ng) // gz
+    my = (f.shape[2] - 2 * ng) // gy
+    mx = (f.shape[3] - 2 * ng) // gx
+    out = []
+    for bz in range(gz):
+        for by in range(gy):
+            for bx in range(gx):
+                out.append(f[:, bz * mz:bz * mz + mz + 2 * ng, by * my:by * my + my + 2 * ng,
+                             bx * mx:bx * mx + mx + 2 * ng])
+    return out
+
+
+def join_valid(flat, grid, m, ncomp: int = 6, ng: int = NG):
+    """Inverse of packing ``split_patches`` back to back: the valid cells of a
+    flat patch buffer (equal m = (mx, my, mz) patches, x fastest) as one
+    (ncomp, gz mz, gy my, gx mx) domain array (numpy or torch)."""
+    gx, gy, gz = grid
+    mx, my, mz = m
+    v = flat.reshape(gz, gy, gx, ncomp, mz + 2 * ng, my + 2 * ng, mx + 2 * ng)
+    v = v[:, :, :, :, ng:-ng, ng:-ng, ng:-ng]
+    order = (3, 0, 4, 1, 5, 2, 6)
+    v = v.transpose(*order) if isinstance(v, np.ndarray) else v.permute(*order)
+    return v.reshape(ncomp, gz * mz, gy * my, gx * mx)
