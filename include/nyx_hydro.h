@@ -65,7 +65,10 @@ typedef struct {
   double eta_dual;       /* dual-energy threshold (Sec. 3.6 Step 6: 1e-4) */
   double small_dens;     /* density floor of primitives and edge states */
   double small_pres;     /* pressure floor of primitives, edge states, Riemann */
-  double riemann_tol;    /* relative stopping tolerance of the two-shock iteration */
+  double riemann_tol;    /* relative stopping tolerance of the two-shock iteration;
+                          * the FP32-mixed form stores the star state in FP32 and
+                          * stops once a Newton step is below
+                          * max(sqrt(riemann_tol), 2^-12) of the pressure */
   double mlp_resid_tol;  /* learned flux: accepted two-shock residual (tau_r) */
   double cfl;            /* hydro CFL factor used for dt_next (Sec. 3.5) */
   int32_t riemann_maxiter;     /* 1..64 */

@@ -3,6 +3,7 @@
 // Validation runs on the host before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -90,7 +91,10 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   a.small_dens = p->small_dens;
   a.small_pres = p->small_pres;
   a.riemann_tol = p->riemann_tol;
-  a.riemann_tol_sqrt = std::sqrt(p->riemann_tol);
+  // FP32-mixed stopping step: the star state is stored in FP32, so the
+  // iteration stops once the next Newton correction would be far below FP32
+  // resolution (see two_shock in the mixed build).
+  a.mixed_stop = std::max(std::sqrt(p->riemann_tol), 0x1p-12);
   a.cfl = p->cfl;
   a.maxiter = p->riemann_maxiter;
   const bool learned = p->riemann == NYX_RIEMANN_LEARNED;

@@ -149,7 +149,7 @@ struct StepArgs {
   double dt_host;
   double a_old, a_new;
   double gamma, eta, small_dens, small_pres, riemann_tol, cfl;
-  double riemann_tol_sqrt;  // FP32-mixed stopping rule (see two_shock)
+  double mixed_stop;  // FP32-mixed stopping rule (see two_shock)
   int maxiter;
   nyx_stats* stats;
   unsigned long long* slots;  // kStatSlots x kStatFields partial counters (when stats)
