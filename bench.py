@@ -123,6 +123,9 @@ def run_box(nyx, torch, w, prm, steps, warmup):
     plan = nyx.Batch(prm, [box], ws)
     dts = torch.zeros(2, dtype=torch.float64, device="cuda")
     plan.estimate_dt(U, w.a0, 0.5, dts[0:1])
+    # launch orders per stage from the library's autotuner (untimed)
+    tune, tune_ms = plan.autotune(U, G, dts[0:1], w.a_at(0), w.a_at(1), Uo, dt_next=dts[1:2],
+                                  reps=2)
     st = torch.zeros(10, dtype=torch.int64, device="cuda")
     bufs = [U, Uo]
     k = 0
@@ -167,7 +170,7 @@ def run_box(nyx, torch, w, prm, steps, warmup):
                         "gbs": round(bytes_per_launch(s, n, rb) / (tl * 1e-3) / 1e9, 1)}
     return {"zone_updates_per_s": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
             "stage": per_stage, "mean_riemann_iters": it, "stats_first_step": stats,
-            "finite": finite, "rho": rho}
+            "finite": finite, "rho": rho, "tuning": tune, "tuning_ms": tune_ms}
 
 
 def train_learned(nyx, learn, synth, log):
@@ -207,6 +210,8 @@ def level_leg(nyx, torch, synth, steps, log):
         other = torch.empty_like(state)
         dts = [torch.zeros(len(boxes), dtype=torch.float64, device="cuda") for _ in range(2)]
         plan.estimate_dt(state, 0.25, 0.5, dts[0])
+        tune, tune_ms = plan.autotune(state, grav, dts[0], 0.25, 0.25 + 5e-4, other,
+                                      dt_next=dts[1], reps=2)
         bufs = [state, other]
 
         def step(k):
@@ -225,7 +230,7 @@ def level_leg(nyx, torch, synth, steps, log):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         r = {"batched_zone_updates_per_s": zones / (ms * 1e-3), "batched_ms_per_step": ms,
-             "groups": plan.num_groups}
+             "groups": plan.num_groups, "tuning": tune, "tuning_ms": tune_ms}
         if form == "mixed":
             # two steps captured once, replayed
             g = torch.cuda.CUDAGraph()
@@ -487,7 +492,8 @@ def main():
                                "fields, a 0.25->0.26, CFL 0.5" % args.n,
                    "form": chosen, "parallelism": "none"},
         "forms": {f: {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage",
-                                         "mean_riemann_iters", "finite", "rho_l1_vs_fp64")
+                                         "mean_riemann_iters", "finite", "rho_l1_vs_fp64",
+                                         "tuning", "tuning_ms")
                       if k in v} for f, v in forms.items()},
         "roofline": roof,
         "roofline_other": other,

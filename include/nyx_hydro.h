@@ -161,6 +161,42 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
                            double* state_out, double* dt_next, nyx_stats* stats,
                            void* stream);
 
+/* ---------------- launch-order autotuning of a plan ----------------
+ * Each of the NYX_NSTAGES stage kernels of a plan's step walks its cells in
+ * one of NYX_TUNE_CANDIDATES launch orders (bits of a tuning entry):
+ *   NYX_TUNE_CELL_MAJOR  kernels with one launch row per direction walk the
+ *                        directions of one range of cells back to back (the
+ *                        stage arrays the directions share are then reread
+ *                        through one L2) instead of one direction after the
+ *                        other;
+ *   NYX_TUNE_HW_ORDER    the hardware's workgroup order instead of numbering
+ *                        the workgroups so that each XCD walks one contiguous
+ *                        range of the grid.
+ * The order changes no result bit (every cell and face computes the same
+ * expressions).  A new plan uses entry 0 for every stage.
+ *
+ * nyx_batch_autotune runs reps + 1 steps per candidate with the arguments of
+ * nyx_hydro_step_batched (no counters; state_out and dt_next, when not NULL,
+ * receive the step's results; pass dt_next when the tuned steps will produce
+ * it, since the fused CFL maximum is part of the update stage's time), times
+ * every stage from HIP events around its launches,
+ * keeps the fastest candidate per stage in the plan and returns it in
+ * tune_out[NYX_NSTAGES] (host, or NULL); ms_out (host, NYX_NSTAGES x
+ * NYX_TUNE_CANDIDATES floats, or NULL) receives the mean milliseconds per
+ * stage and candidate.  It synchronises the stream and must not be called
+ * while the stream is being captured.  nyx_batch_set_tuning /
+ * nyx_batch_get_tuning store and read a plan's entries (host arrays of
+ * NYX_NSTAGES ints in 0..NYX_TUNE_CANDIDATES-1), e.g. from a cache of earlier
+ * tuning runs. */
+#define NYX_TUNE_CELL_MAJOR 1
+#define NYX_TUNE_HW_ORDER 2
+#define NYX_TUNE_CANDIDATES 4
+int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav,
+                       const double* dt, double a_old, double a_new, double* state_out,
+                       double* dt_next, int reps, float* ms_out, int* tune_out, void* stream);
+int nyx_batch_set_tuning(nyx_batch* plan, const int* tune);
+int nyx_batch_get_tuning(const nyx_batch* plan, int* tune);
+
 /* ---------------- ghost fills (outside the step) ---------------- */
 /* Periodic ghost cells of one box from its own valid cells (the box is its
  * own periodic domain).  state (device), ncomp components at box->state_off

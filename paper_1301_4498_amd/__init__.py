@@ -134,6 +134,65 @@ class Batch:
             self.handle, _ptr(state_in), _ptr(grav), _ptr(dt), float(a_old), float(a_new),
             _ptr(state_out), _ptr(dt_next), _ptr(stats), _stream(stream)))
 
+    def tuning(self):
+        t = (ctypes.c_int * _lib.STAGES)()
+        check("nyx_batch_get_tuning", lib().nyx_batch_get_tuning(self.handle, t))
+        return list(t)
+
+    def set_tuning(self, tune):
+        t = (ctypes.c_int * _lib.STAGES)(*tune)
+        check("nyx_batch_set_tuning", lib().nyx_batch_set_tuning(self.handle, t))
+
+    def tuning_key(self, device_name: str = "") -> str:
+        """Cache key of this plan's tuning: form, device and box-shape histogram."""
+        import hashlib
+        hist = {}
+        for b in self._boxes:
+            k = (b.n[0], b.n[1], b.n[2])
+            hist[k] = hist.get(k, 0) + 1
+        h = hashlib.sha1(repr(sorted(hist.items())).encode()).hexdigest()[:16]
+        p = self.params
+        return "%s|prec%d|riem%d|mask%d|nbox%d|groups%d|%s" % (
+            device_name, p.precision, p.riemann, p.learned_stages_mask, self.nbox,
+            self.num_groups, h)
+
+    def autotune(self, state_in, grav, dt, a_old, a_new, state_out, dt_next=None, reps=3,
+                 cache=None, stream=None):
+        """Pick each stage's launch order (nyx_batch_autotune).  With a cache
+        file (JSON), a stored choice for the same key is applied without
+        timing, and a new one is stored.  Returns (tune, ms or None)."""
+        import json
+        import os
+        key = None
+        if cache is not None:
+            import torch
+            key = self.tuning_key(torch.cuda.get_device_name())
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    db = json.load(fh)
+                if key in db:
+                    self.set_tuning(db[key]["tune"])
+                    return db[key]["tune"], None
+        nst, nc = _lib.STAGES, _lib.TUNE_CANDIDATES
+        ms = (ctypes.c_float * (nst * nc))()
+        t = (ctypes.c_int * nst)()
+        check("nyx_batch_autotune", lib().nyx_batch_autotune(
+            self.handle, _ptr(state_in), _ptr(grav), _ptr(dt), float(a_old), float(a_new),
+            _ptr(state_out), _ptr(dt_next), int(reps), ms, t, _stream(stream)))
+        tune = list(t)
+        table = [[round(float(ms[i * nc + c]), 4) for c in range(nc)] for i in range(nst)]
+        if cache is not None:
+            db = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    db = json.load(fh)
+            db[key] = {"tune": tune, "ms": table}
+            tmp = cache + ".tmp%d" % os.getpid()
+            with open(tmp, "w") as fh:
+                json.dump(db, fh, indent=1)
+            os.replace(tmp, cache)
+        return tune, table
+
     def fill_ghosts(self, state, mode=0, grid=(1, 1, 1), stream=None):
         check("nyx_batch_fill_ghosts", lib().nyx_batch_fill_ghosts(
             self.handle, mode, grid[0], grid[1], grid[2], _ptr(state), _stream(stream)))

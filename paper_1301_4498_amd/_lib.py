@@ -98,6 +98,10 @@ def lib():
             "nyx_mlp_pack": (i, [vp, vp, vp]),
             "nyx_mlp_predict": (i, [vp, vp, ctypes.c_longlong, d, vp, vp]),
             "nyx_profile_read": (i, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), i]),
+            "nyx_batch_autotune": (i, [vp, vp, vp, vp, d, d, vp, vp, i, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(i), vp]),
+            "nyx_batch_set_tuning": (i, [vp, ctypes.POINTER(i)]),
+            "nyx_batch_get_tuning": (i, [vp, ctypes.POINTER(i)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -119,13 +123,16 @@ def exported_symbols():
             "nyx_batch_min_dt", "nyx_hydro_step_batched", "nyx_fill_ghosts_periodic",
             "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read",
             "nyx_batch_set_harvest", "nyx_mlp_init", "nyx_mlp_loss_grad", "nyx_mlp_adam",
-            "nyx_mlp_pack", "nyx_mlp_predict"]
+            "nyx_mlp_pack", "nyx_mlp_predict", "nyx_batch_autotune", "nyx_batch_set_tuning",
+            "nyx_batch_get_tuning"]
 
+TUNE_CANDIDATES = 4
 MLP_NPARAM = 9349
 MLP_PACKED_BYTES = 23552
 
 
 STAGE_NAMES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")
+STAGES = len(STAGE_NAMES)
 
 
 def profile_enable(on: bool) -> None:

@@ -278,6 +278,7 @@ struct nyx_batch {
   long long harvest_cap = 0;
   unsigned harvest_keep = 0;
   unsigned long long harvest_seed = 0;
+  int tune[kStages] = {0};        // launch-order candidate per stage
 };
 
 namespace {
@@ -427,6 +428,7 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   A.harvest_cap = plan->harvest_cap;
   A.harvest_keep = plan->harvest_keep;
   A.harvest_seed = plan->harvest_seed;
+  for (int i = 0; i < kStages; ++i) A.tune[i] = plan->tune[i];
   return A;
 }
 
@@ -463,13 +465,15 @@ int nyx_batch_min_dt(nyx_batch* plan, double* dt, void* stream) {
   return launch_min_dt(dt, plan->nbox, (hipStream_t)stream) == hipSuccess ? NYX_OK : NYX_E_HIP;
 }
 
-int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* grav,
-                           const double* dt, double a_old, double a_new, double* state_out,
-                           double* dt_next, nyx_stats* stats, void* stream) {
-  if (!plan || !state_in || !grav || !dt || !state_out) return NYX_E_NULL;
-  if (!finite_pos(a_old) || !finite_pos(a_new)) return NYX_E_PARAM;
-  if (overlaps(state_in, plan->state_span, state_out, plan->state_span)) return NYX_E_ALIAS;
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// Enqueue one batched step.  group_ev: per group, kStages + 1 events to
+// record around its stages (autotuning), or nullptr for the profiler's.
+int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, const double* dt,
+                    double a_old, double a_new, double* state_out, double* dt_next,
+                    nyx_stats* stats, hipStream_t s, hipEvent_t* const* group_ev) {
   if (dt_next && launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
   if (stats && launch_zero_u64(plan->slots, kStatSlots * kStatFields, s) != hipSuccess)
     return NYX_E_HIP;
@@ -491,12 +495,111 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
     A.a_new = a_new;
     A.stats = stats;
     A.dt_next = dt_next;
-    if (run_stages(&plan->prm, A, s) != hipSuccess) return NYX_E_HIP;
+    hipError_t e;
+    if (group_ev) {
+      A.ev = group_ev[&g - plan->groups.data()];
+      e = plan->prm.precision == NYX_MIXED ? mixed::launch_step(A, s) : fp64::launch_step(A, s);
+    } else {
+      e = run_stages(&plan->prm, A, s);
+    }
+    if (e != hipSuccess) return NYX_E_HIP;
   }
   if (stats && launch_stats_reduce(plan->slots, stats, s) != hipSuccess) return NYX_E_HIP;
   if (dt_next &&
       launch_dt_finalize(all_boxes_args(plan), a_new, plan->prm.cfl, dt_next, s) != hipSuccess)
     return NYX_E_HIP;
+  return NYX_OK;
+}
+
+int check_step_args(nyx_batch* plan, const double* state_in, const void* grav, const double* dt,
+                    double a_old, double a_new, double* state_out) {
+  if (!plan || !state_in || !grav || !dt || !state_out) return NYX_E_NULL;
+  if (!finite_pos(a_old) || !finite_pos(a_new)) return NYX_E_PARAM;
+  if (overlaps(state_in, plan->state_span, state_out, plan->state_span)) return NYX_E_ALIAS;
+  return NYX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* grav,
+                           const double* dt, double a_old, double a_new, double* state_out,
+                           double* dt_next, nyx_stats* stats, void* stream) {
+  int rc = check_step_args(plan, state_in, grav, dt, a_old, a_new, state_out);
+  if (rc) return rc;
+  return enqueue_batched(plan, state_in, grav, dt, a_old, a_new, state_out, dt_next, stats,
+                         (hipStream_t)stream, nullptr);
+}
+
+int nyx_batch_set_tuning(nyx_batch* plan, const int* tune) {
+  if (!plan || !tune) return NYX_E_NULL;
+  for (int i = 0; i < kStages; ++i)
+    if (tune[i] < 0 || tune[i] >= kTuneCandidates) return NYX_E_PARAM;
+  for (int i = 0; i < kStages; ++i) plan->tune[i] = tune[i];
+  return NYX_OK;
+}
+
+int nyx_batch_get_tuning(const nyx_batch* plan, int* tune) {
+  if (!plan || !tune) return NYX_E_NULL;
+  for (int i = 0; i < kStages; ++i) tune[i] = plan->tune[i];
+  return NYX_OK;
+}
+
+int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav,
+                       const double* dt, double a_old, double a_new, double* state_out,
+                       double* dt_next, int reps, float* ms_out, int* tune_out, void* stream) {
+  int rc = check_step_args(plan, state_in, grav, dt, a_old, a_new, state_out);
+  if (rc) return rc;
+  if (reps < 1 || reps > 1000) return NYX_E_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t ng = plan->groups.size();
+  std::vector<hipEvent_t> evs(ng * (kStages + 1));
+  std::vector<hipEvent_t*> gev(ng);
+  size_t made = 0;
+  rc = NYX_OK;
+  for (; made < evs.size(); ++made)
+    if (hipEventCreate(&evs[made]) != hipSuccess) {
+      rc = NYX_E_HIP;
+      break;
+    }
+  for (size_t g = 0; g < ng; ++g) gev[g] = evs.data() + g * (kStages + 1);
+  const std::vector<int> saved(plan->tune, plan->tune + kStages);
+  double tot[kTuneCandidates][kStages] = {};
+  // every candidate is applied to all stages at once; each stage's time is
+  // read from the events around its launches, so one pass per candidate
+  // times all stages
+  for (int c = 0; c < kTuneCandidates && rc == NYX_OK; ++c) {
+    for (int i = 0; i < kStages; ++i) plan->tune[i] = c;
+    for (int r = 0; r <= reps && rc == NYX_OK; ++r) {  // r = 0 warms up
+      rc = enqueue_batched(plan, state_in, grav, dt, a_old, a_new, state_out, dt_next, nullptr, s,
+                           gev.data());
+      if (rc == NYX_OK && hipStreamSynchronize(s) != hipSuccess) rc = NYX_E_HIP;
+      for (size_t g = 0; g < ng && rc == NYX_OK && r > 0; ++g)
+        for (int i = 0; i < kStages; ++i) {
+          float t = 0.f;
+          if (hipEventElapsedTime(&t, gev[g][i], gev[g][i + 1]) != hipSuccess) {
+            rc = NYX_E_HIP;
+            break;
+          }
+          tot[c][i] += t;
+        }
+    }
+  }
+  for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(evs[i]);
+  if (rc != NYX_OK) {
+    for (int i = 0; i < kStages; ++i) plan->tune[i] = saved[i];
+    return rc;
+  }
+  for (int i = 0; i < kStages; ++i) {
+    int best = 0;
+    for (int c = 1; c < kTuneCandidates; ++c)
+      if (tot[c][i] < tot[best][i]) best = c;
+    plan->tune[i] = best;
+    if (tune_out) tune_out[i] = best;
+    if (ms_out)
+      for (int c = 0; c < kTuneCandidates; ++c) ms_out[i * kTuneCandidates + c] = (float)(tot[c][i] / reps);
+  }
   return NYX_OK;
 }
 

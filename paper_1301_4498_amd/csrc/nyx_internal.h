@@ -107,12 +107,24 @@ enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2 };
 // with its own L2.  Renumber them so that every XCD walks one contiguous
 // range of the (linearised) grid: neighbouring rows and planes of a stage
 // array are then read through the same L2.  A bijection for any grid size.
-__device__ __forceinline__ unsigned xcd_linear_block() {
+// With remap = false the hardware order is kept (the autotuner's other
+// candidate).
+__device__ __forceinline__ unsigned xcd_linear_block(bool remap = true) {
   const unsigned n = gridDim.x * gridDim.y;
   const unsigned lin = blockIdx.x + blockIdx.y * gridDim.x;
+  if (!remap) return lin;
   const unsigned q = n >> 3, r = n & 7;
   const unsigned xcd = lin & 7, pos = lin >> 3;
   return xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+}
+
+// Raise *dst (bits of a non-negative double) to the bits of m.  The stored
+// maximum only grows, so a read that already shows a value at least as large
+// (even a stale one) makes the atomic unnecessary; most blocks of a box then
+// skip it instead of queueing on one address.
+__device__ __forceinline__ void max_bits(unsigned long long* dst, double m) {
+  const unsigned long long v = (unsigned long long)__double_as_longlong(m);
+  if (__hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) atomicMax(dst, v);
 }
 
 __device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
@@ -129,6 +141,21 @@ __device__ __forceinline__ void space_coords(const BoxDev& b, int space, unsigne
   c[2] = (int)q2;
 }
 #endif
+
+// Stage kernels of a step, in launch order (also the order of the timing
+// events and of the tuning entries).
+constexpr int kStages = 7;
+enum Stage { kStPrim = 0, kStFlat, kStTrace, kStRiem0, kStRiem1, kStRiem2, kStUpdate };
+// Launch-order candidates of a stage (bits of a tuning entry):
+//  kTuneCellMajor  grids with one row per direction (or direction pair) walk
+//                  the rows of one cell range back to back, so the stage
+//                  arrays the directions share are reread from the same L2;
+//                  otherwise one direction after the other;
+//  kTuneHwOrder    hardware workgroup order instead of the XCD-contiguous
+//                  numbering.
+constexpr int kTuneCellMajor = 1;
+constexpr int kTuneHwOrder = 2;
+constexpr int kTuneCandidates = 4;
 
 // Launch-wide arguments of a step.
 struct StepArgs {
@@ -166,10 +193,9 @@ struct StepArgs {
   long long harvest_cap;
   unsigned harvest_keep;   // keep a face when its 32-bit hash < harvest_keep
   unsigned long long harvest_seed;
+  int tune[kStages];       // launch-order candidate per stage (kTune* bits)
 };
 
-// stage order of launch_step (for timing)
-constexpr int kStages = 7;
 
 // The two precision builds of the stage kernels.
 namespace fp64 {

@@ -60,12 +60,22 @@ struct Loc {
 };
 
 // Returns the box and cell index of this thread; *ylane receives the
-// grid-y coordinate (direction or direction pair) after XCD renumbering.
-__device__ __forceinline__ Loc locate(const StepArgs& A, int space, int* ylane = nullptr) {
+// grid-y coordinate (direction or direction pair).  The workgroup's place in
+// the walk follows the stage's tuning entry (kTune* bits).
+__device__ __forceinline__ Loc locate(const StepArgs& A, int stage, int space,
+                                      int* ylane = nullptr) {
   Loc L;
-  const unsigned lin = xcd_linear_block();
-  const unsigned bx = lin % gridDim.x;
-  if (ylane) *ylane = (int)(lin / gridDim.x);
+  const int tune = A.tune[stage];
+  const unsigned lin = xcd_linear_block(!(tune & kTuneHwOrder));
+  unsigned bx, yl;
+  if (tune & kTuneCellMajor) {
+    bx = lin / gridDim.y;
+    yl = lin % gridDim.y;
+  } else {
+    bx = lin % gridDim.x;
+    yl = lin / gridDim.x;
+  }
+  if (ylane) *ylane = (int)yl;
   const int* pre = A.prefix[space];
   int lo = 0, hi = A.nb;  // find b with pre[b] <= bx < pre[b+1]
   const int x = (int)bx;
@@ -115,7 +125,7 @@ __device__ __forceinline__ void count(const StepArgs& A, int field, unsigned v) 
 // stage 1: primitives on every padded cell
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
-  Loc L = locate(A, kSpaceP);
+  Loc L = locate(A, kStPrim, kSpaceP);
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.P) {
@@ -160,7 +170,7 @@ __device__ __forceinline__ real flat_tilde(real sp, real pm2, real pm1, real pp1
 }
 
 __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
-  Loc L = locate(A, kSpaceE);
+  Loc L = locate(A, kStFlat, kSpaceE);
   const BoxDev& b = *L.bd;
   if (L.idx >= b.E) return;
   const long long e = L.idx;
@@ -302,7 +312,7 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
 
 __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
   int d;
-  Loc L = locate(A, kSpaceE, &d);
+  Loc L = locate(A, kStTrace, kSpaceE, &d);
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.E) {
@@ -835,7 +845,7 @@ template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int d;
-  Loc L = locate(A, kSpaceE, &d);
+  Loc L = locate(A, kStRiem0, kSpaceE, &d);
   const BoxDev& b = *L.bd;
   unsigned calls = 0, iters = 0, used = 0, fb = 0;
   int c[3] = {0, 0, 0};
@@ -883,7 +893,7 @@ template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int y;
-  Loc L = locate(A, kSpaceE, &y);
+  Loc L = locate(A, kStRiem1, kSpaceE, &y);
   const int d = LEARNED ? y >> 1 : y;
   const BoxDev& b = *L.bd;
   unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
   constexpr bool LEARNED = MODE == 1;
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int d;
-  Loc L = locate(A, kSpaceE, &d);
+  Loc L = locate(A, kStRiem2, kSpaceE, &d);
   const BoxDev& b = *L.bd;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
@@ -1072,7 +1082,7 @@ __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* d
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int i = 1; i < kBlock / 64; ++i) m = vmax(m, red[i]);
-    if (m > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0) max_bits(dst, m);
   }
 }
 
@@ -1080,7 +1090,7 @@ __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* d
 // stage 7: conservative update, gravity corrector, dual-energy sync
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
-  Loc L = locate(A, kSpaceV);
+  Loc L = locate(A, kStUpdate, kSpaceV);
   const BoxDev& b = *L.bd;
   unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
   double smax = 0.0;

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_dtmax(StepArgs A, double a) {
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < kBlock / 64; ++w) m = dmaxd(m, red[w]);
-    if (m > 0.0) atomicMax(A.smax + b.gidx, (unsigned long long)__double_as_longlong(m));
+    if (m > 0.0) max_bits(A.smax + b.gidx, m);
   }
 }
 

@@ -116,6 +116,10 @@ def test_learned_flux_argument_errors(nyx):
     assert L.nyx_mlp_adam(0x1000, 0x2000, 0x3000, 0x4000, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -3
     assert L.nyx_mlp_pack(0x1000, 0x2008, None) == -3
     assert L.nyx_batch_set_harvest(None, 1, 1, 10, 0.5, 0) == -1
+    t = (ctypes.c_int * 7)()
+    assert L.nyx_batch_set_tuning(None, t) == -1
+    assert L.nyx_batch_get_tuning(None, t) == -1
+    assert L.nyx_batch_autotune(None, 1, 1, 1, 0.5, 0.5, 2, None, 3, None, t, None) == -1
 
 
 def test_batch_argument_errors(nyx):

@@ -3,7 +3,9 @@
 Bar: FP64 batched results are bitwise equal to the oracle box by box (the
 same arithmetic as a single-box launch), independent of how boxes are grouped;
 per-box CFL steps are bitwise; ghost fills equal numpy's periodic copies; a
-captured HIP graph replays to the same state as eager launches."""
+captured HIP graph replays to the same state as eager launches; every launch
+order the autotuner can pick gives the same bits, and its cached choice is
+reapplied without timing."""
 import numpy as np
 import pytest
 
@@ -202,3 +204,48 @@ def test_graph_replay_matches_eager(nyx):
         torch.cuda.synchronize()
         _ = (A2 * 1.0).sum().item()  # unrelated eager work between replays
         assert np.array_equal(A2.cpu().numpy(), eager[r]), r
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_every_launch_order_gives_the_same_bits(nyx, prec, tmp_path):
+    import torch
+    p = nyx.default_params(precision=nyx.NYX_FP64 if prec == "fp64" else nyx.NYX_MIXED)
+    boxes, states, gravs, flat, gflat = _pack(nyx, SHAPES)
+    mn, one = nyx.Batch.workspace_bytes(p, boxes)
+    plan = nyx.Batch(p, boxes, aligned_ws(mn))  # several groups
+    assert plan.num_groups > 1
+    Ui = to_dev(flat)
+    G = to_dev(gflat, torch.float64 if prec == "fp64" else torch.float32)
+    dt = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+    plan.estimate_dt(Ui, 0.25, 0.5, dt)
+    outs = []
+    for c in range(4):
+        plan.set_tuning([c] * 7)
+        assert plan.tuning() == [c] * 7
+        Uo = torch.zeros_like(Ui)
+        dn = torch.zeros_like(dt)
+        plan.step(Ui, G, dt, 0.25, 0.2505, Uo, dt_next=dn)
+        torch.cuda.synchronize()
+        outs.append((Uo.cpu().numpy(), dn.cpu().numpy()))
+    for U, dn in outs[1:]:
+        assert np.array_equal(U, outs[0][0])
+        assert np.array_equal(dn, outs[0][1])
+    # the autotuner keeps one candidate per stage, reports its timings and
+    # writes the same result as a step
+    cache = str(tmp_path / "tune.json")
+    Uo = torch.zeros_like(Ui)
+    dn = torch.zeros_like(dt)
+    tune, ms = plan.autotune(Ui, G, dt, 0.25, 0.2505, Uo, dt_next=dn, reps=2, cache=cache)
+    torch.cuda.synchronize()
+    assert np.array_equal(dn.cpu().numpy(), outs[0][1])
+    print(prec, "tuning", tune, "ms per stage and candidate", ms)
+    assert len(tune) == 7 and all(0 <= t < 4 for t in tune)
+    assert plan.tuning() == tune
+    assert all(ms[i][tune[i]] == min(ms[i]) for i in range(7))
+    assert np.array_equal(Uo.cpu().numpy(), outs[0][0])
+    # a second plan over the same boxes takes the cached choice
+    plan2 = nyx.Batch(p, boxes, aligned_ws(mn))
+    tune2, ms2 = plan2.autotune(Ui, G, dt, 0.25, 0.2505, Uo, cache=cache)
+    assert ms2 is None and tune2 == tune and plan2.tuning() == tune
+    plan.close()
+    plan2.close()
