@@ -310,15 +310,17 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
                  : qe[t2];
 }
 
-__global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
-  int d;
-  Loc L = locate(A, kStTrace, kSpaceE, &d);
-  const BoxDev& b = *L.bd;
+// The direction of a launch row is uniform per workgroup; each stage body is
+// instantiated per direction so that component and stride choices are
+// compile-time constants instead of selects.
+template <int D>
+__device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b, unsigned idx) {
+  constexpr int d = D;
   unsigned floors = 0;
-  if (L.idx < b.E) {
-    const long long e = L.idx;
+  {
+    const long long e = idx;
     int ec[3];
-    space_coords(b, kSpaceE, L.idx, ec);
+    space_coords(b, kSpaceE, idx, ec);
     const int ie = ec[0], je = ec[1], ke = ec[2];
     const StepC& C = step_consts(A, b);
     const real* prim = (const real*)A.work + b.w_prim;
@@ -363,6 +365,19 @@ __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
       W[((d * 2 + 0) * 5 + v) * b.E] = lo[v];
       W[((d * 2 + 1) * 5 + v) * b.E] = hi[v];
     }
+  }
+  return floors;
+}
+
+__global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
+  int d;
+  Loc L = locate(A, kStTrace, kSpaceE, &d);
+  const BoxDev& b = *L.bd;
+  unsigned floors = 0;
+  if (L.idx < b.E) {
+    if (d == 0) floors = trace_dir<0>(A, b, L.idx);
+    else if (d == 1) floors = trace_dir<1>(A, b, L.idx);
+    else floors = trace_dir<2>(A, b, L.idx);
   }
   if (A.stats) count(A, kFloorHits, floors);
 }
@@ -841,17 +856,18 @@ __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, cons
 // ---------------------------------------------------------------------------
 // stage 4: Riemann on stage-0 states, faces between cells of [-1, n]
 // ---------------------------------------------------------------------------
-template <bool LEARNED>
-__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
-  int d;
-  Loc L = locate(A, kStRiem0, kSpaceE, &d);
-  const BoxDev& b = *L.bd;
-  unsigned calls = 0, iters = 0, used = 0, fb = 0;
+struct Tally {
+  unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
+};
+
+template <bool LEARNED, int D>
+__device__ __forceinline__ void riem0_dir(const StepArgs& A, const BoxDev& b, unsigned idx,
+                                          __bf16* lds, Tally& T) {
+  constexpr int d = D;
   int c[3] = {0, 0, 0};
-  if (L.idx < b.E) e_coords(b, L.idx, c);
-  const bool active = L.idx < b.E && c[d] >= 1;  // face f = c[d] - 1 in [0, n_d]
-  const long long e = L.idx;
+  if (idx < b.E) e_coords(b, idx, c);
+  const bool active = idx < b.E && c[d] >= 1;  // face f = c[d] - 1 in [0, n_d]
+  const long long e = idx;
   double ql[5], qr[5];
   if (active) {
     const long long eL = e - e_stride(b, d);
@@ -864,21 +880,39 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
     rotate(d, Ls, ql);
     rotate(d, Rs, qr);
   }
-  RiemannOut g = solve<LEARNED>(A, active, ql, qr, mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED,
-                                &used, &fb);
+  RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
   if (active) {
-    calls = 1;
-    iters = g.iters;
+    T.calls = 1;
+    T.iters = g.iters;
     store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E + e, b.E, g);
   }
+}
+
+template <bool LEARNED>
+__device__ __forceinline__ void count_tally(const StepArgs& A, const Tally& T, bool reverts) {
   if (A.stats) {
-    count(A, kRiemannCalls, calls);
-    count(A, kRiemannIters, iters);
+    count(A, kRiemannCalls, T.calls);
+    count(A, kRiemannIters, T.iters);
+    if (reverts) count(A, kTransReverts, T.reverts);
     if (LEARNED) {
-      count(A, kMlpUsed, used);
-      count(A, kMlpFallback, fb);
+      count(A, kMlpUsed, T.used);
+      count(A, kMlpFallback, T.fb);
     }
   }
+}
+
+template <bool LEARNED>
+__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  int d;
+  Loc L = locate(A, kStRiem0, kSpaceE, &d);
+  const BoxDev& b = *L.bd;
+  __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
+  Tally T;
+  if (d == 0) riem0_dir<LEARNED, 0>(A, b, L.idx, lds, T);
+  else if (d == 1) riem0_dir<LEARNED, 1>(A, b, L.idx, lds, T);
+  else riem0_dir<LEARNED, 2>(A, b, L.idx, lds, T);
+  count_tally<LEARNED>(A, T, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,20 +923,17 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
 // Plain form: grid.y = 3 directions, both pairs of a direction per thread.
 // Learned form: grid.y = 6, one (direction, pair) per thread (fewer live
 // registers next to the network's accumulators).
-template <bool LEARNED>
-__global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
-  int y;
-  Loc L = locate(A, kStRiem1, kSpaceE, &y);
-  const int d = LEARNED ? y >> 1 : y;
-  const BoxDev& b = *L.bd;
-  unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
+// KSEL: -1 both pairs of direction D (plain form), else pair KSEL only
+template <bool LEARNED, int D, int KSEL>
+__device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, unsigned idx,
+                                          __bf16* lds, Tally& T) {
+  constexpr int d = D;
   int c[3] = {0, 0, 0};
-  if (L.idx < b.E) e_coords(b, L.idx, c);
-  const long long e = L.idx;
-  const int ts[2] = {(d + 1) % 3, (d + 2) % 3};
-  const bool inb = L.idx < b.E && c[d] >= 1;
-  const bool pick0 = !LEARNED || (y & 1) == 0, pick1 = !LEARNED || (y & 1) == 1;
+  if (idx < b.E) e_coords(b, idx, c);
+  const long long e = idx;
+  constexpr int ts[2] = {(D + 1) % 3, (D + 2) % 3};
+  const bool inb = idx < b.E && c[d] >= 1;
+  constexpr bool pick0 = KSEL != 1, pick1 = KSEL != 0;
   const bool want[2] = {pick0 && inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
                         pick1 && inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
   double q[2][5];
@@ -915,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
       for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
     }
   }
-  const int kfirst = LEARNED ? (y & 1) : 0, klast = LEARNED ? (y & 1) : 1;
+  constexpr int kfirst = KSEL < 0 ? 0 : KSEL, klast = KSEL < 0 ? 1 : KSEL;
   for (int k = kfirst; k <= klast; ++k) {
     const bool active = want[k];
     double ql[5], qr[5];
@@ -929,28 +960,43 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
         const long long ec = s == 0 ? e - sdd : e;
         double Dc[5], De;
         tdiff<true>(A.gamma, t, G0 + ec, G0 + ec + stt, b.E, Dc, De);
-        reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
+        T.reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
       }
       rotate(d, qs[0], ql);
       rotate(d, qs[1], qr);
     }
-    RiemannOut g = solve<LEARNED>(A, active, ql, qr,
-                                  mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED, &used, &fb);
+    RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
     if (active) {
-      calls += 1;
-      iters += g.iters;
+      T.calls += 1;
+      T.iters += g.iters;
       store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E + e, b.E, g);
     }
   }
-  if (A.stats) {
-    count(A, kRiemannCalls, calls);
-    count(A, kRiemannIters, iters);
-    count(A, kTransReverts, reverts);
-    if (LEARNED) {
-      count(A, kMlpUsed, used);
-      count(A, kMlpFallback, fb);
+}
+
+template <bool LEARNED>
+__global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  int y;
+  Loc L = locate(A, kStRiem1, kSpaceE, &y);
+  const BoxDev& b = *L.bd;
+  __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
+  Tally T;
+  if constexpr (LEARNED) {
+    switch (y) {
+      case 0: riem1_dir<LEARNED, 0, 0>(A, b, L.idx, lds, T); break;
+      case 1: riem1_dir<LEARNED, 0, 1>(A, b, L.idx, lds, T); break;
+      case 2: riem1_dir<LEARNED, 1, 0>(A, b, L.idx, lds, T); break;
+      case 3: riem1_dir<LEARNED, 1, 1>(A, b, L.idx, lds, T); break;
+      case 4: riem1_dir<LEARNED, 2, 0>(A, b, L.idx, lds, T); break;
+      default: riem1_dir<LEARNED, 2, 1>(A, b, L.idx, lds, T); break;
     }
+  } else {
+    if (y == 0) riem1_dir<LEARNED, 0, -1>(A, b, L.idx, lds, T);
+    else if (y == 1) riem1_dir<LEARNED, 1, -1>(A, b, L.idx, lds, T);
+    else riem1_dir<LEARNED, 2, -1>(A, b, L.idx, lds, T);
   }
+  count_tally<LEARNED>(A, T, true);
 }
 
 // 32-bit hash of a face for the training-sample harvest
@@ -966,20 +1012,16 @@ __device__ __forceinline__ unsigned face_hash(unsigned long long seed, int box, 
 // ---------------------------------------------------------------------------
 // stage 6: final d-states and comoving fluxes on valid faces
 // ---------------------------------------------------------------------------
-// MODE 0: plain; 1: learned; 2: plain and harvest training records
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+template <int MODE, int D>
+__device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, unsigned idx,
+                                          __bf16* lds, Tally& T) {
   constexpr bool LEARNED = MODE == 1;
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
-  int d;
-  Loc L = locate(A, kStRiem2, kSpaceE, &d);
-  const BoxDev& b = *L.bd;
-  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-  unsigned calls = 0, iters = 0, reverts = 0, used = 0, fb = 0;
+  constexpr int d = D;
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   int c[3] = {0, 0, 0};
-  if (L.idx < b.E) e_coords(b, L.idx, c);
-  const long long e = L.idx;
-  const bool active = L.idx < b.E && c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 &&
+  if (idx < b.E) e_coords(b, idx, c);
+  const long long e = idx;
+  const bool active = idx < b.E && c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 &&
                       c[t2] <= b.n[t2];
   double ql[5], qr[5];
   if (active) {
@@ -997,16 +1039,15 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
       double Dc[5], De;
       tdiff<true>(A.gamma, t1, G1a + ec, G1a + ec + s1, b.E, Dc, De);   // t1-flux corrected by t2
       tdiff<false>(A.gamma, t2, G1b + ec, G1b + ec + s2, b.E, Dc, De);  // t2-flux corrected by t1
-      reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
+      T.reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
     }
     rotate(d, qs[0], ql);
     rotate(d, qs[1], qr);
   }
-  RiemannOut g = solve<LEARNED>(A, active, ql, qr, mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED,
-                                &used, &fb);
+  RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
   if (active) {
-    calls = 1;
-    iters = g.iters;
+    T.calls = 1;
+    T.iters = g.iters;
     store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E + e, b.E, g);
     if (MODE == 2 && face_hash(A.harvest_seed, b.gidx, e, d) < A.harvest_keep) {
       const unsigned long long slot = atomicAdd(A.harvest_count, 1ull);
@@ -1024,15 +1065,22 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
       }
     }
   }
-  if (A.stats) {
-    count(A, kRiemannCalls, calls);
-    count(A, kRiemannIters, iters);
-    count(A, kTransReverts, reverts);
-    if (LEARNED) {
-      count(A, kMlpUsed, used);
-      count(A, kMlpFallback, fb);
-    }
-  }
+}
+
+// MODE 0: plain; 1: learned; 2: plain and harvest training records
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+  constexpr bool LEARNED = MODE == 1;
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  int d;
+  Loc L = locate(A, kStRiem2, kSpaceE, &d);
+  const BoxDev& b = *L.bd;
+  __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
+  Tally T;
+  if (d == 0) riem2_dir<MODE, 0>(A, b, L.idx, lds, T);
+  else if (d == 1) riem2_dir<MODE, 1>(A, b, L.idx, lds, T);
+  else riem2_dir<MODE, 2>(A, b, L.idx, lds, T);
+  count_tally<LEARNED>(A, T, true);
 }
 
 // O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
