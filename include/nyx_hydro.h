@@ -163,7 +163,7 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
 
 /* ---------------- launch-order autotuning of a plan ----------------
  * Each of the NYX_NSTAGES stage kernels of a plan's step walks its cells in
- * one of NYX_TUNE_CANDIDATES launch orders (bits of a tuning entry):
+ * one of NYX_TUNE_CANDIDATES launch orders (fields of a tuning entry):
  *   NYX_TUNE_CELL_MAJOR  kernels with one launch row per direction walk the
  *                        directions of one range of cells back to back (the
  *                        stage arrays the directions share are then reread
@@ -171,7 +171,11 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  *                        other;
  *   NYX_TUNE_HW_ORDER    the hardware's workgroup order instead of numbering
  *                        the workgroups so that each XCD walks one contiguous
- *                        range of the grid.
+ *                        range of the grid;
+ *   bits NYX_TUNE_SLAB_SHIFT.. (0-3): cell order within a box, 0 plane by
+ *                        plane; s > 0 tiles of 2^(s+2) rows, each walked
+ *                        plane by plane along z (z-pencils of row tiles), so
+ *                        that a cell's z-neighbours are read soon after it.
  * The order changes no result bit (every cell and face computes the same
  * expressions).  A new plan uses entry 0 for every stage.
  *
@@ -190,7 +194,8 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  * tuning runs. */
 #define NYX_TUNE_CELL_MAJOR 1
 #define NYX_TUNE_HW_ORDER 2
-#define NYX_TUNE_CANDIDATES 4
+#define NYX_TUNE_SLAB_SHIFT 2
+#define NYX_TUNE_CANDIDATES 16
 int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav,
                        const double* dt, double a_old, double a_new, double* state_out,
                        double* dt_next, int reps, float* ms_out, int* tune_out, void* stream);

@@ -126,7 +126,7 @@ def exported_symbols():
             "nyx_mlp_pack", "nyx_mlp_predict", "nyx_batch_autotune", "nyx_batch_set_tuning",
             "nyx_batch_get_tuning"]
 
-TUNE_CANDIDATES = 4
+TUNE_CANDIDATES = 16
 MLP_NPARAM = 9349
 MLP_PACKED_BYTES = 23552
 

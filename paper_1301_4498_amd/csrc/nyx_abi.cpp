@@ -23,10 +23,10 @@ namespace {
 constexpr size_t kSlotBytes = sizeof(unsigned long long) * kStatSlots * kStatFields;
 constexpr size_t kOffSlots = 256;
 constexpr size_t kOffTable = kOffSlots + (kSlotBytes + 255) / 256 * 256;
-constexpr size_t kOffPrefix = kOffTable + 256;
+constexpr size_t kOffPrefix = kOffTable + 512;
 constexpr size_t kOffConsts = kOffPrefix + 256;
 constexpr size_t kHeaderBytes = kOffConsts + 256;
-static_assert(sizeof(BoxDev) <= 256 && sizeof(StepC) <= 256, "header slots");
+static_assert(sizeof(BoxDev) <= 512 && sizeof(StepC) <= 256, "header slots");
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 

@@ -44,8 +44,9 @@ struct BoxDev {
   int pad_;
   double dx;
   FastDiv dv[3][2];        // per Space: row length and plane size
+  FastDiv dz[3];           // per Space: number of planes
   unsigned sy[3];          // per Space: rows per plane
-  unsigned pad2_;
+  unsigned sc[3];          // per Space: cell count (< 2^31)
 };
 
 // Stage-array element count for a box (before alignment padding).
@@ -85,9 +86,15 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   d.dv[1][1] = make_fastdiv((unsigned)d.ex * (unsigned)d.ey);
   d.dv[2][0] = make_fastdiv((unsigned)b.n[0]);
   d.dv[2][1] = make_fastdiv((unsigned)b.n[0] * (unsigned)b.n[1]);
+  d.dz[0] = make_fastdiv((unsigned)d.pz);
+  d.dz[1] = make_fastdiv((unsigned)d.ez);
+  d.dz[2] = make_fastdiv((unsigned)b.n[2]);
   d.sy[0] = (unsigned)d.py;
   d.sy[1] = (unsigned)d.ey;
   d.sy[2] = (unsigned)b.n[1];
+  d.sc[0] = (unsigned)d.P;
+  d.sc[1] = (unsigned)d.E;
+  d.sc[2] = (unsigned)d.V;
   if (out) *out = d;
   return o;
 }
@@ -130,6 +137,35 @@ __device__ __forceinline__ void max_bits(unsigned long long* dst, double m) {
 __device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
   return (__umulhi(n, f.m) + n) >> f.l;
 }
+// Natural (x fastest, then y, then z) flat index of the cell at position q
+// of a slab walk with 2^lg rows per slab (kTuneSlabShift); q >= the cell
+// count is returned unchanged (lanes past the end of the box).
+__device__ __forceinline__ unsigned slab_to_natural(const BoxDev& b, int space, unsigned q,
+                                                    int lg) {
+  if (q >= b.sc[space]) return q;
+  const FastDiv& r = b.dv[space][0];
+  const FastDiv& zd = b.dz[space];
+  const unsigned ex = r.d, ey = b.sy[space], ez = zd.d;
+  const unsigned t = fast_div(q, r);  // (slab, z, row) index
+  const unsigned x = q - t * ex;
+  const unsigned nfull = ey >> lg;    // whole slabs
+  const unsigned tfull = (nfull << lg) * ez;
+  unsigned y, z;
+  if (t < tfull) {
+    const unsigned yin = t & ((1u << lg) - 1u);
+    const unsigned u = t >> lg;
+    const unsigned sl = fast_div(u, zd);
+    z = u - sl * ez;
+    y = (sl << lg) + yin;
+  } else {
+    const unsigned t2 = t - tfull;
+    const unsigned yin = fast_div(t2, zd);
+    z = t2 - yin * ez;
+    y = (nfull << lg) + yin;
+  }
+  return x + ex * (y + ey * z);
+}
+
 // (x, y, z) of flat index idx < 2^31 in the given Space of a box
 __device__ __forceinline__ void space_coords(const BoxDev& b, int space, unsigned idx, int* c) {
   const FastDiv& r = b.dv[space][0];
@@ -146,16 +182,23 @@ __device__ __forceinline__ void space_coords(const BoxDev& b, int space, unsigne
 // events and of the tuning entries).
 constexpr int kStages = 7;
 enum Stage { kStPrim = 0, kStFlat, kStTrace, kStRiem0, kStRiem1, kStRiem2, kStUpdate };
-// Launch-order candidates of a stage (bits of a tuning entry):
-//  kTuneCellMajor  grids with one row per direction (or direction pair) walk
-//                  the rows of one cell range back to back, so the stage
-//                  arrays the directions share are reread from the same L2;
-//                  otherwise one direction after the other;
-//  kTuneHwOrder    hardware workgroup order instead of the XCD-contiguous
-//                  numbering.
+// Launch-order candidates of a stage (fields of a tuning entry):
+//  bit 0 (kTuneCellMajor)  grids with one row per direction (or direction
+//                  pair) walk the rows of one cell range back to back, so the
+//                  stage arrays the directions share are reread from the same
+//                  L2; otherwise one direction after the other;
+//  bit 1 (kTuneHwOrder)    hardware workgroup order instead of the
+//                  XCD-contiguous numbering;
+//  bits 2-3 (kTuneSlabShift) cell order within a box: 0 plane by plane (x,
+//                  then y, then z); s = 1, 2, 3: slabs of 2^(s+2) rows, each
+//                  walked plane by plane along z (a z-pencil of row tiles), so
+//                  a cell's z-neighbours are read shortly after it through
+//                  the same L2; rows left over below a whole slab are walked
+//                  one row at a time along z.
 constexpr int kTuneCellMajor = 1;
 constexpr int kTuneHwOrder = 2;
-constexpr int kTuneCandidates = 4;
+constexpr int kTuneSlabShift = 2;
+constexpr int kTuneCandidates = 16;
 
 // Launch-wide arguments of a step.
 struct StepArgs {

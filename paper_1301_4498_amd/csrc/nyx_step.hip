@@ -86,6 +86,8 @@ __device__ __forceinline__ Loc locate(const StepArgs& A, int stage, int space,
   }
   L.bd = A.table + lo;
   L.idx = (unsigned)(x - pre[lo]) * (unsigned)kBlock + threadIdx.x;
+  const int slab = (tune >> kTuneSlabShift) & 3;
+  if (slab) L.idx = slab_to_natural(*L.bd, space, L.idx, slab + 2);
   return L;
 }
 

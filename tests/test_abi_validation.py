@@ -51,7 +51,7 @@ def test_workspace_bytes(nyx):
     # Riemann stages (5 values per face)
     elems = al(6 * P) + al(E) + al(30 * E) + al(15 * E) + al(30 * E) + al(15 * E)
     # CFL maximum, partial counters, one-entry box table, block prefixes, step constants
-    header = 256 + 64 * 10 * 8 + 256 + 256 + 256
+    header = 256 + 64 * 10 * 8 + 512 + 256 + 256
     assert nyx.workspace_bytes(p, b) == header + 8 * elems
     p.precision = nyx.NYX_MIXED
     assert nyx.workspace_bytes(p, b) == header + 4 * elems
