@@ -125,7 +125,7 @@ def run_box(nyx, torch, w, prm, steps, warmup):
     plan.estimate_dt(U, w.a0, 0.5, dts[0:1])
     # launch orders per stage from the library's autotuner (untimed)
     tune, tune_ms = plan.autotune(U, G, dts[0:1], w.a_at(0), w.a_at(1), Uo, dt_next=dts[1:2],
-                                  reps=2)
+                                  reps=3)
     st = torch.zeros(10, dtype=torch.int64, device="cuda")
     bufs = [U, Uo]
     k = 0

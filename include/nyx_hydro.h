@@ -19,7 +19,9 @@
  *      element (c, k, j, i) at off + c*comp_stride
  *                            + ((k+ng)*(ny+2ng) + (j+ng))*(nx+2ng) + (i+ng)
  *    for i in [-ng, nx+ng) and likewise j, k; comp_stride >= the padded cell
- *    count.  dx is the comoving cell size, the same on every axis (Sec. 4.1).
+ *    count, which must stay below 2^29 (a box of up to about 800^3 cells;
+ *    per-box offsets are 32-bit byte offsets).  dx is the comoving cell size,
+ *    the same on every axis (Sec. 4.1).
  *  - Memory: every pointer marked (device) is device memory owned by the
  *    caller; the library never allocates or frees device memory.  Workspace
  *    sizes are queried first and passed in.  Host pointers are read during
@@ -186,8 +188,8 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  * every stage from HIP events around its launches,
  * keeps the fastest candidate per stage in the plan and returns it in
  * tune_out[NYX_NSTAGES] (host, or NULL); ms_out (host, NYX_NSTAGES x
- * NYX_TUNE_CANDIDATES floats, or NULL) receives the mean milliseconds per
- * stage and candidate.  It synchronises the stream and must not be called
+ * NYX_TUNE_CANDIDATES floats, or NULL) receives each stage's fastest
+ * repetition per candidate, in milliseconds.  It synchronises the stream and must not be called
  * while the stream is being captured.  nyx_batch_set_tuning /
  * nyx_batch_get_tuning store and read a plan's entries (host arrays of
  * NYX_NSTAGES ints in 0..NYX_TUNE_CANDIDATES-1), e.g. from a cache of earlier

@@ -57,7 +57,7 @@ int check_box(const nyx_box* b) {
   if (b->ng < 4 || b->ng > 64) return NYX_E_SHAPE;
   long long P = 1;
   for (int d = 0; d < 3; ++d) P *= (long long)(b->n[d] + 2 * b->ng);
-  if (P >= (1ll << 31)) return NYX_E_SHAPE;  // per-box indices are 32-bit
+  if (P >= (1ll << 29)) return NYX_E_SHAPE;  // per-box byte offsets of FP64 arrays are 32-bit
   if (b->comp_stride < P || b->grav_stride < P) return NYX_E_SHAPE;
   if (b->state_off < 0 || b->grav_off < 0) return NYX_E_SHAPE;
   if (!finite_pos(b->dx)) return NYX_E_PARAM;
@@ -565,16 +565,20 @@ int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav
     }
   for (size_t g = 0; g < ng; ++g) gev[g] = evs.data() + g * (kStages + 1);
   const std::vector<int> saved(plan->tune, plan->tune + kStages);
-  double tot[kTuneCandidates][kStages] = {};
+  double best_ms[kTuneCandidates][kStages];
+  for (auto& row : best_ms)
+    for (double& v : row) v = 1e30;
   // every candidate is applied to all stages at once; each stage's time is
   // read from the events around its launches, so one pass per candidate
-  // times all stages
+  // times all stages; a stage keeps its fastest repetition (least disturbed
+  // by other work on the device)
   for (int c = 0; c < kTuneCandidates && rc == NYX_OK; ++c) {
     for (int i = 0; i < kStages; ++i) plan->tune[i] = c;
     for (int r = 0; r <= reps && rc == NYX_OK; ++r) {  // r = 0 warms up
       rc = enqueue_batched(plan, state_in, grav, dt, a_old, a_new, state_out, dt_next, nullptr, s,
                            gev.data());
       if (rc == NYX_OK && hipStreamSynchronize(s) != hipSuccess) rc = NYX_E_HIP;
+      double step_ms[kStages] = {};
       for (size_t g = 0; g < ng && rc == NYX_OK && r > 0; ++g)
         for (int i = 0; i < kStages; ++i) {
           float t = 0.f;
@@ -582,8 +586,10 @@ int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav
             rc = NYX_E_HIP;
             break;
           }
-          tot[c][i] += t;
+          step_ms[i] += t;
         }
+      if (r > 0)
+        for (int i = 0; i < kStages; ++i) best_ms[c][i] = std::min(best_ms[c][i], step_ms[i]);
     }
   }
   for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(evs[i]);
@@ -594,11 +600,11 @@ int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav
   for (int i = 0; i < kStages; ++i) {
     int best = 0;
     for (int c = 1; c < kTuneCandidates; ++c)
-      if (tot[c][i] < tot[best][i]) best = c;
+      if (best_ms[c][i] < best_ms[best][i]) best = c;
     plan->tune[i] = best;
     if (tune_out) tune_out[i] = best;
     if (ms_out)
-      for (int c = 0; c < kTuneCandidates; ++c) ms_out[i * kTuneCandidates + c] = (float)(tot[c][i] / reps);
+      for (int c = 0; c < kTuneCandidates; ++c) ms_out[i * kTuneCandidates + c] = (float)best_ms[c][i];
   }
   return NYX_OK;
 }

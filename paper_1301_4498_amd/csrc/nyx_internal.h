@@ -137,6 +137,20 @@ __device__ __forceinline__ void max_bits(unsigned long long* dst, double m) {
 __device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
   return (__umulhi(n, f.m) + n) >> f.l;
 }
+// Element i of an array whose base is uniform over the workgroup, addressed
+// through a 32-bit byte offset: the access takes the scalar-base form of the
+// memory instructions, with no 64-bit address arithmetic per lane.  Every
+// per-box array has fewer than 2^29 elements (checked on the host), so the
+// byte offset fits 32 bits.
+template <class T>
+__device__ __forceinline__ T ldu(const T* base, unsigned i) {
+  return *(const T*)((const char*)base + i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stu(T* base, unsigned i, T v) {
+  *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
+}
+
 // Natural (x fastest, then y, then z) flat index of the cell at position q
 // of a slab walk with 2^lg rows per slab (kTuneSlabShift); q >= the cell
 // count is returned unchanged (lanes past the end of the box).

@@ -131,32 +131,33 @@ __global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.P) {
-    const long long id = L.idx;
-    const double* U = A.Uin + b.soff + id;
+    const unsigned id = L.idx;
+    const double* U = A.Uin + b.soff;
     const double ao = A.a_old;
-    double rho = U[0];
+    double rho = ldu(U, id);
     if (rho < A.small_dens) { rho = A.small_dens; floors++; }
-    double u = U[b.sstride] / (ao * rho);
-    double v = U[2 * b.sstride] / (ao * rho);
-    double w = U[3 * b.sstride] / (ao * rho);
-    double re = U[5 * b.sstride] / (ao * ao);
+    double u = ldu(U + b.sstride, id) / (ao * rho);
+    double v = ldu(U + 2 * b.sstride, id) / (ao * rho);
+    double w = ldu(U + 3 * b.sstride, id) / (ao * rho);
+    double re = ldu(U + 5 * b.sstride, id) / (ao * ao);
     double p = (A.gamma - 1.0) * re;
     if (p < A.small_pres) { p = A.small_pres; floors++; }
     double c = sqrt((A.gamma * p) / rho);
-    real* q = (real*)A.work + b.w_prim + id;
-    q[0] = (real)rho;
-    q[b.P] = (real)u;
-    q[2 * b.P] = (real)v;
-    q[3 * b.P] = (real)w;
-    q[4 * b.P] = (real)p;
-    q[5 * b.P] = (real)c;
+    real* q = (real*)A.work + b.w_prim;
+    stu(q, id, (real)rho);
+    stu(q + b.P, id, (real)u);
+    stu(q + 2 * b.P, id, (real)v);
+    stu(q + 3 * b.P, id, (real)w);
+    stu(q + 4 * b.P, id, (real)p);
+    stu(q + 5 * b.P, id, (real)c);
   }
   if (A.stats) count(A, kFloorHits, floors);
 }
 
 // padded index of the cell at E-array coordinates (ie, je, ke) (cell ie - 1)
-__device__ __forceinline__ long long pidx_e(const BoxDev& b, int ie, int je, int ke) {
-  return ((long long)(ke - 1 + b.ng) * b.py + (je - 1 + b.ng)) * b.px + (ie - 1 + b.ng);
+__device__ __forceinline__ unsigned pidx_e(const BoxDev& b, int ie, int je, int ke) {
+  return ((unsigned)(ke - 1 + b.ng) * (unsigned)b.py + (unsigned)(je - 1 + b.ng)) * (unsigned)b.px +
+         (unsigned)(ie - 1 + b.ng);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,22 +176,23 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
   Loc L = locate(A, kStFlat, kSpaceE);
   const BoxDev& b = *L.bd;
   if (L.idx >= b.E) return;
-  const long long e = L.idx;
+  const unsigned e = L.idx;
   int ec[3];
   space_coords(b, kSpaceE, L.idx, ec);
   const int ie = ec[0], je = ec[1], ke = ec[2];
   const real* prim = (const real*)A.work + b.w_prim;
   const real* P = prim + 4 * b.P;
   const real sp = (real)A.small_pres;
-  const long long c0 = pidx_e(b, ie, je, ke);
-  const long long sd[3] = {1, b.px, (long long)b.px * b.py};
+  const unsigned c0 = pidx_e(b, ie, je, ke);
+  const unsigned sd[3] = {1u, (unsigned)b.px, (unsigned)b.px * (unsigned)b.py};
   real cmin = (real)1;
   for (int d = 0; d < 3; ++d) {
-    const long long s = sd[d];
+    const unsigned s = sd[d];
     const real* U = prim + (1 + d) * b.P;
     real p[7], u[5];
-    for (int o = -3; o <= 3; ++o) p[o + 3] = P[c0 + o * s];
-    for (int o = -2; o <= 2; ++o) u[o + 2] = U[c0 + o * s];
+    // neighbour shifts go into the (uniform) base; all loads share c0
+    for (int o = -3; o <= 3; ++o) p[o + 3] = ldu(P + (long long)o * s, c0);
+    for (int o = -2; o <= 2; ++o) u[o + 2] = ldu(U + (long long)o * s, c0);
     real fm = flat_tilde(sp, p[0], p[1], p[3], p[4], u[0], u[2]);
     real f0 = flat_tilde(sp, p[1], p[2], p[4], p[5], u[1], u[3]);
     real fp = flat_tilde(sp, p[2], p[3], p[5], p[6], u[2], u[4]);
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
     real cd = (real)1 - f;
     cmin = (d == 0) ? cd : vmin(cmin, cd);
   }
-  ((real*)A.work)[b.w_chi + e] = cmin;
+  stu((real*)A.work + b.w_chi, e, cmin);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,26 +322,26 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
   constexpr int d = D;
   unsigned floors = 0;
   {
-    const long long e = idx;
+    const unsigned e = idx;
     int ec[3];
     space_coords(b, kSpaceE, idx, ec);
     const int ie = ec[0], je = ec[1], ke = ec[2];
     const StepC& C = step_consts(A, b);
     const real* prim = (const real*)A.work + b.w_prim;
-    const long long c0 = pidx_e(b, ie, je, ke);
-    const long long s = d == 0 ? 1 : (d == 1 ? (long long)b.px : (long long)b.px * b.py);
-    const real chi = ((const real*)A.work)[b.w_chi + e];
+    const unsigned c0 = pidx_e(b, ie, je, ke);
+    const unsigned s = d == 0 ? 1u : (d == 1 ? (unsigned)b.px : (unsigned)b.px * (unsigned)b.py);
+    const real chi = ldu((const real*)A.work + b.w_chi, e);
     real qc[5], qm[5], qp[5], dq[5], q6[5];
     for (int v = 0; v < 5; ++v) {
       const real* Q = prim + v * b.P;
       real q5[5];
-      for (int o = -2; o <= 2; ++o) q5[o + 2] = Q[c0 + o * s];
+      for (int o = -2; o <= 2; ++o) q5[o + 2] = ldu(Q + (long long)o * s, c0);
       qc[v] = q5[2];
       ppm_edges(q5, chi, qm[v], qp[v]);
       dq[v] = qp[v] - qm[v];
       q6[v] = (real)6 * qc[v] - (real)3 * (qm[v] + qp[v]);
     }
-    const real c = prim[5 * b.P + c0];
+    const real c = ldu(prim + 5 * b.P, c0);
     const int nv = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
     const real u = qc[nv];
     real lam[3] = {u - c, u, u + c};
@@ -350,8 +352,8 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
     trace_side<+1>(qc, c, qp, dq, q6, lam, sig, nv, t1, t2, hi);
     trace_side<-1>(qc, c, qm, dq, q6, lam, sig, nv, t1, t2, lo);
     // half-step gravity and expansion sources, then floors
-    const real* G = (const real*)A.grav + b.goff + c0;
-    real g[3] = {G[0], G[b.gstride], G[2 * b.gstride]};
+    const real* G = (const real*)A.grav + b.goff;
+    real g[3] = {ldu(G, c0), ldu(G + b.gstride, c0), ldu(G + 2 * b.gstride, c0)};
     const real hdt_a = (real)C.hdt_a, hda_a = (real)C.hda_a, pexp = (real)C.pexp;
     const real sd_ = (real)A.small_dens, sp_ = (real)A.small_pres;
     real* out[2] = {lo, hi};
@@ -362,10 +364,10 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
       if (q[0] < sd_) { q[0] = sd_; floors++; }
       if (q[4] < sp_) { q[4] = sp_; floors++; }
     }
-    real* W = (real*)A.work + b.w_edge + e;
+    real* W = (real*)A.work + b.w_edge;
     for (int v = 0; v < 5; ++v) {
-      W[((d * 2 + 0) * 5 + v) * b.E] = lo[v];
-      W[((d * 2 + 1) * 5 + v) * b.E] = hi[v];
+      stu(W + ((d * 2 + 0) * 5 + v) * b.E, e, lo[v]);
+      stu(W + ((d * 2 + 1) * 5 + v) * b.E, e, hi[v]);
     }
   }
   return floors;
@@ -683,20 +685,21 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
 #endif  // NYX_PREC_MIXED
 
 // Godunov state of a d-face as stored (rotated frame: rho, u_n, v_t1, w_t2, p)
-__device__ __forceinline__ void store_god(real* G, long long E, const RiemannOut& g) {
-  G[0] = (real)g.r;
-  G[E] = (real)g.u;
-  G[2 * E] = (real)g.v;
-  G[3 * E] = (real)g.w;
-  G[4 * E] = (real)g.p;
+__device__ __forceinline__ void store_god(real* G, long long E, unsigned i, const RiemannOut& g) {
+  stu(G, i, (real)g.r);
+  stu(G + E, i, (real)g.u);
+  stu(G + 2 * E, i, (real)g.v);
+  stu(G + 3 * E, i, (real)g.w);
+  stu(G + 4 * E, i, (real)g.p);
 }
 
 // O6: lab-frame fluxes of a d-face from its stored Godunov state (flux
 // arithmetic in real): f = (f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g).
 __device__ __forceinline__ void face_flux(double gamma, int d, const real* G, long long E,
-                                          real* f) {
+                                          unsigned i, real* f) {
   const real gm1 = (real)(gamma - 1.0);
-  const real r = G[0], u = G[E], v = G[2 * E], w = G[3 * E], p = G[4 * E];
+  const real r = ldu(G, i), u = ldu(G + E, i), v = ldu(G + 2 * E, i), w = ldu(G + 3 * E, i),
+             p = ldu(G + 4 * E, i);
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const real ru = r * u;
   f[0] = ru;
@@ -720,8 +723,8 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const real* G, lo
 __device__ __forceinline__ void e_coords(const BoxDev& b, unsigned e, int* c) {
   space_coords(b, kSpaceE, e, c);
 }
-__device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
-  return d == 0 ? 1 : (d == 1 ? (long long)b.ex : (long long)b.ex * b.ey);
+__device__ __forceinline__ unsigned e_stride(const BoxDev& b, int d) {
+  return d == 0 ? 1u : (d == 1 ? (unsigned)b.ex : (unsigned)b.ex * (unsigned)b.ey);
 }
 
 // ---------------------------------------------------------------------------
@@ -734,10 +737,10 @@ __device__ __forceinline__ long long e_stride(const BoxDev& b, int d) {
 // them, a second one is added, in that order
 template <bool FIRST>
 __device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, const real* Ghi,
-                                      long long E, double* Dc, double& De) {
+                                      unsigned i, long long E, double* Dc, double& De) {
   real fm[8], fp[8];
-  face_flux(gamma, t, Glo, E, fm);
-  face_flux(gamma, t, Ghi, E, fp);
+  face_flux(gamma, t, Glo, E, i, fm);
+  face_flux(gamma, t, Ghi, E, i, fp);
 #if defined(NYX_PREC_MIXED)
   // flux differences are flux arithmetic: FP32, widened once
   for (int c = 0; c < 5; ++c) {
@@ -869,15 +872,15 @@ __device__ __forceinline__ void riem0_dir(const StepArgs& A, const BoxDev& b, un
   int c[3] = {0, 0, 0};
   if (idx < b.E) e_coords(b, idx, c);
   const bool active = idx < b.E && c[d] >= 1;  // face f = c[d] - 1 in [0, n_d]
-  const long long e = idx;
+  const unsigned e = idx;
   double ql[5], qr[5];
   if (active) {
-    const long long eL = e - e_stride(b, d);
+    const long long sL = e_stride(b, d);  // left cell: shift in the base, same offset e
     const real* W = (const real*)A.work + b.w_edge;
     double Ls[5], Rs[5];
     for (int v = 0; v < 5; ++v) {
-      Ls[v] = (double)W[((d * 2 + 1) * 5 + v) * b.E + eL];
-      Rs[v] = (double)W[((d * 2 + 0) * 5 + v) * b.E + e];
+      Ls[v] = (double)ldu(W + ((d * 2 + 1) * 5 + v) * b.E - sL, e);
+      Rs[v] = (double)ldu(W + ((d * 2 + 0) * 5 + v) * b.E, e);
     }
     rotate(d, Ls, ql);
     rotate(d, Rs, qr);
@@ -886,7 +889,7 @@ __device__ __forceinline__ void riem0_dir(const StepArgs& A, const BoxDev& b, un
   if (active) {
     T.calls = 1;
     T.iters = g.iters;
-    store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E + e, b.E, g);
+    store_god((real*)A.work + b.w_f0 + (long long)d * kGod * b.E, b.E, e, g);
   }
 }
 
@@ -932,20 +935,22 @@ __device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, un
   constexpr int d = D;
   int c[3] = {0, 0, 0};
   if (idx < b.E) e_coords(b, idx, c);
-  const long long e = idx;
+  const unsigned e = idx;
   constexpr int ts[2] = {(D + 1) % 3, (D + 2) % 3};
   const bool inb = idx < b.E && c[d] >= 1;
   constexpr bool pick0 = KSEL != 1, pick1 = KSEL != 0;
   const bool want[2] = {pick0 && inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
                         pick1 && inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
   double q[2][5];
+  // the left cell's arrays are read through bases shifted by -sdd, so every
+  // load of the thread uses the one offset e
   const long long sdd = e_stride(b, d);
   if (want[0] || want[1]) {
     const real* W = (const real*)A.work + b.w_edge;
     for (int s = 0; s < 2; ++s) {
-      const long long ec = s == 0 ? e - sdd : e;
+      const long long sh = s == 0 ? -sdd : 0;
       const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
-      for (int v = 0; v < 5; ++v) q[s][v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+      for (int v = 0; v < 5; ++v) q[s][v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
     }
   }
   constexpr int kfirst = KSEL < 0 ? 0 : KSEL, klast = KSEL < 0 ? 1 : KSEL;
@@ -959,9 +964,9 @@ __device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, un
       const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
       double qs[2][5];
       for (int s = 0; s < 2; ++s) {
-        const long long ec = s == 0 ? e - sdd : e;
+        const real* Gc = G0 + (s == 0 ? -sdd : 0);
         double Dc[5], De;
-        tdiff<true>(A.gamma, t, G0 + ec, G0 + ec + stt, b.E, Dc, De);
+        tdiff<true>(A.gamma, t, Gc, Gc + stt, e, b.E, Dc, De);
         T.reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
       }
       rotate(d, qs[0], ql);
@@ -971,7 +976,7 @@ __device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, un
     if (active) {
       T.calls += 1;
       T.iters += g.iters;
-      store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E + e, b.E, g);
+      store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E, b.E, e, g);
     }
   }
 }
@@ -1022,7 +1027,7 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   int c[3] = {0, 0, 0};
   if (idx < b.E) e_coords(b, idx, c);
-  const long long e = idx;
+  const unsigned e = idx;
   const bool active = idx < b.E && c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 &&
                       c[t2] <= b.n[t2];
   double ql[5], qr[5];
@@ -1034,13 +1039,13 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
     const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
     double qs[2][5];
     for (int s = 0; s < 2; ++s) {
-      const long long ec = s == 0 ? e - sdd : e;
+      const long long sh = s == 0 ? -sdd : 0;  // cell shift in the bases, offset e
       const int side = s == 0 ? 1 : 0;
       double q[5];
-      for (int v = 0; v < 5; ++v) q[v] = (double)W[((d * 2 + side) * 5 + v) * b.E + ec];
+      for (int v = 0; v < 5; ++v) q[v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
       double Dc[5], De;
-      tdiff<true>(A.gamma, t1, G1a + ec, G1a + ec + s1, b.E, Dc, De);   // t1-flux corrected by t2
-      tdiff<false>(A.gamma, t2, G1b + ec, G1b + ec + s2, b.E, Dc, De);  // t2-flux corrected by t1
+      tdiff<true>(A.gamma, t1, G1a + sh, G1a + sh + s1, e, b.E, Dc, De);   // t1-flux corrected by t2
+      tdiff<false>(A.gamma, t2, G1b + sh, G1b + sh + s2, e, b.E, Dc, De);  // t2-flux corrected by t1
       T.reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
     }
     rotate(d, qs[0], ql);
@@ -1050,7 +1055,7 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
   if (active) {
     T.calls = 1;
     T.iters = g.iters;
-    store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E + e, b.E, g);
+    store_god((real*)A.work + b.w_f2 + (long long)d * kGod * b.E, b.E, e, g);
     if (MODE == 2 && face_hash(A.harvest_seed, b.gidx, e, d) < A.harvest_keep) {
       const unsigned long long slot = atomicAdd(A.harvest_count, 1ull);
       if (slot < (unsigned long long)A.harvest_cap) {
@@ -1088,8 +1093,8 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
 // O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
 // F_m = f_m, F_E = a_h f_E, F_e = a_h f_e; p_g and u_g kept for S_e.
 __device__ __forceinline__ void final_flux(double gamma, int d, const real* G, long long E,
-                                           real ah, real* f) {
-  face_flux(gamma, d, G, E, f);
+                                           unsigned i, real ah, real* f) {
+  face_flux(gamma, d, G, E, i, f);
   f[0] = f[0] / ah;
   f[4] = ah * f[4];
   f[5] = ah * f[5];
@@ -1149,17 +1154,17 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     space_coords(b, kSpaceV, L.idx, vc);
     const int i = vc[0], j = vc[1], k = vc[2];
     const StepC& C = step_consts(A, b);
-    const long long e = ((long long)(k + 1) * b.ey + (j + 1)) * b.ex + (i + 1);
+    const unsigned e = ((unsigned)(k + 1) * (unsigned)b.ey + (unsigned)(j + 1)) * (unsigned)b.ex +
+                       (unsigned)(i + 1);
     const real* G2 = (const real*)A.work + b.w_f2;
     const real ah = (real)C.a_h;
     double D[6];
     double Pi = 0.0;
     for (int d = 0; d < 3; ++d) {
       const real* G = G2 + (long long)d * kGod * b.E;
-      const long long eu = e + e_stride(b, d);
       real fl[8], fh[8];
-      final_flux(A.gamma, d, G + e, b.E, ah, fl);
-      final_flux(A.gamma, d, G + eu, b.E, ah, fh);
+      final_flux(A.gamma, d, G, b.E, e, ah, fl);
+      final_flux(A.gamma, d, G + (long long)e_stride(b, d), b.E, e, ah, fh);
       for (int c = 0; c < 6; ++c) {
         double dF = (double)fh[c] - (double)fl[c];
         D[c] = (d == 0) ? dF : D[c] + dF;
@@ -1167,13 +1172,16 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
       double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
       Pi = (d == 0) ? pd : Pi + pd;
     }
-    const long long id = ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
-    const double* U = A.Uin + b.soff + id;
-    const double U0 = U[0];
-    const double Um[3] = {U[b.sstride], U[2 * b.sstride], U[3 * b.sstride]};
-    const double UE = U[4 * b.sstride], Ue = U[5 * b.sstride];
-    const real* G = (const real*)A.grav + b.goff + id;
-    const double g[3] = {(double)G[0], (double)G[b.gstride], (double)G[2 * b.gstride]};
+    const unsigned id = ((unsigned)(k + b.ng) * (unsigned)b.py + (unsigned)(j + b.ng)) *
+                            (unsigned)b.px + (unsigned)(i + b.ng);
+    const double* U = A.Uin + b.soff;
+    const double U0 = ldu(U, id);
+    const double Um[3] = {ldu(U + b.sstride, id), ldu(U + 2 * b.sstride, id),
+                          ldu(U + 3 * b.sstride, id)};
+    const double UE = ldu(U + 4 * b.sstride, id), Ue = ldu(U + 5 * b.sstride, id);
+    const real* G = (const real*)A.grav + b.goff;
+    const double g[3] = {(double)ldu(G, id), (double)ldu(G + b.gstride, id),
+                         (double)ldu(G + 2 * b.gstride, id)};
     const double dt = C.dt, kk = C.k;
     // predictor (Step 2)
     const double s0 = U0 - kk * D[0];
@@ -1199,13 +1207,13 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
       nE = ne + ke;
       nsync = 1;
     }
-    double* O = A.Uout + b.soff + id;
-    O[0] = s0;
-    O[b.sstride] = nm[0];
-    O[2 * b.sstride] = nm[1];
-    O[3 * b.sstride] = nm[2];
-    O[4 * b.sstride] = nE;
-    O[5 * b.sstride] = ne;
+    double* O = A.Uout + b.soff;
+    stu(O, id, s0);
+    stu(O + b.sstride, id, nm[0]);
+    stu(O + 2 * b.sstride, id, nm[1]);
+    stu(O + 3 * b.sstride, id, nm[2]);
+    stu(O + 4 * b.sstride, id, nE);
+    stu(O + 5 * b.sstride, id, ne);
     bool fin = isfinite(s0) && isfinite(nm[0]) && isfinite(nm[1]) && isfinite(nm[2]) &&
                isfinite(nE) && isfinite(ne);
     nnf = fin ? 0 : 1;

@@ -83,6 +83,11 @@ def test_argument_errors(nyx):
     for bad in ((7, 8, 8), (8, 0, 8), (8, 8, -2)):
         assert _step(nyx, p, nyx.make_box(bad, 4, 0.1)) == -2
     assert _step(nyx, p, nyx.make_box((8, 8, 8), 3, 0.1)) == -2
+    # padded cell count at or above 2^29 (32-bit byte offsets of FP64 arrays)
+    assert _step(nyx, p, nyx.make_box((808, 808, 808), 4, 0.1)) == -2
+    ws = ctypes.c_size_t()
+    assert nyx.lib().nyx_workspace_bytes(ctypes.byref(p), ctypes.byref(nyx.make_box((800, 800, 792), 4, 0.1)),
+                                         ctypes.byref(ws)) == 0
     assert _step(nyx, p, nyx.make_box((8, 8, 8), 4, 0.0)) == -3
     b2 = nyx.make_box((8, 8, 8), 4, 0.1)
     b2.comp_stride = 10
