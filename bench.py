@@ -20,8 +20,9 @@ step (also replayed as a captured HIP graph) against per-box launches.
 
 Stress leg (box512_stress): a 512^3 domain with density contrast up to 10^4
 and flows up to Mach 30, plain FP64 as one box against FP32-mixed (and the
-learned flux) on an 8^3 grid of 64^3 patches with the same-level ghost fill
-and one level dt; density relative L1 against FP64 and the fallback rate.
+learned flux, trained on smooth flows or on stress faces) on an 8^3 grid of
+64^3 patches with the same-level ghost fill and one level dt; density
+relative L1 against FP64 and the fallback rate.
 
 Stage times come from HIP events the library records between its stage
 launches on the step's stream.
@@ -192,6 +193,24 @@ def train_learned(nyx, learn, synth, log):
     return f, info
 
 
+def train_learned_stress(nyx, learn, synth, log):
+    """A second network for the stress workload: about 2e7 final-stage faces
+    of plain FP64 steps on ten 64^3 boxes of the stress fields (seeds
+    500-509), trained like the first (untimed)."""
+    t0 = time.perf_counter()
+    ws = [synth.config5(n=64, seed=500 + s) for s in range(10)]
+    rec = learn.harvest(ws, steps=8, keep_fraction=0.31, capacity=21_000_000, seed=500)
+    f = learn.LearnedFlux(seed=2)
+    epochs = 4
+    hist = f.train(rec, epochs=epochs, batch=16384)
+    f.pack()
+    info = {"records": int(rec.shape[0]), "boxes": "10 x 64^3 stress fields, seeds 500-509, 8 steps",
+            "epochs": epochs, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+            "seconds": round(time.perf_counter() - t0, 1)}
+    log("stress network trained: %s" % info)
+    return f, info
+
+
 def level_leg(nyx, torch, synth, steps, log):
     """4096 uneven boxes: batched plan (+ graph) against per-box launches."""
     shapes = synth.config3_shapes()
@@ -334,7 +353,11 @@ def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
              for b in range(nb)]
     runs = [("mixed_patches", nyx.default_params(precision=nyx.NYX_MIXED))]
     if flux is not None:
+        # the network trained on smooth flows, and one trained on stress faces
         runs.append(("learned_patches", learn.learned_params(flux, tol=1e-3, stages=7)))
+        sflux, out["stress_training"] = train_learned_stress(nyx, learn, synth, log)
+        runs.append(("learned_patches_stress_trained",
+                     learn.learned_params(sflux, tol=1e-3, stages=7)))
     for name, prm in runs:
         _, one = nyx.Batch.workspace_bytes(prm, boxes)
         ws = aligned(torch, one)
@@ -356,7 +379,7 @@ def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
         r = {"zone_updates_per_s": zones * steps / (ms * 1e-3), "ms_per_step": ms / steps,
              "rho_l1_vs_fp64": l1, "finite": bool(torch.isfinite(bufs[steps % 2]).all().item()),
              "stats_first_step": s}
-        if name == "learned_patches":
+        if name.startswith("learned"):
             r["fallback_rate"] = s["mlp_fallback"] / max(s["mlp_used"] + s["mlp_fallback"], 1)
         out[name] = r
         log("stress %s: %.3e zone-updates/s, rho L1 vs FP64 %.2e" % (name, r["zone_updates_per_s"], l1))

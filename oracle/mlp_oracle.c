@@ -20,7 +20,9 @@
  * output.  Flat parameter vector (9349 values):
  *   W1[64][10], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[5][64], b4[5]
  * (W[o][i] multiplies input i into output o).
- * Loss L = (1/n) sum_samples sum_outputs (yhat - y)^2.
+ * Loss L = (1/n) sum over in-domain samples of sum_outputs (yhat - y)^2
+ * (a sample is in the training domain when its inputs and targets are finite
+ * and at most 64 in magnitude; see nyxo_mlp_in_domain).
  */
 #include <math.h>
 #include <stdint.h>
@@ -110,6 +112,20 @@ uint64_t nyxo_mlp_relu_pattern(const double* P, const double* x, long n) {
 }
 
 /* loss and gradient over n samples; grad (NPARAM) is overwritten */
+/* Training domain: a sample enters the loss only when its ten inputs and
+ * five targets are finite and at most DOMAIN in magnitude (faces with floored
+ * pressures or near-vacuum states normalise to huge values; the network is
+ * not asked to fit them, and in a step they fall back to the two-shock
+ * solver).  The loss stays normalised by the batch size n. */
+#define DOMAIN 64.0
+int nyxo_mlp_in_domain(const double* xs, const double* ys) {
+  for (int k = 0; k < NI; ++k)
+    if (!(fabs(xs[k]) <= DOMAIN)) return 0;
+  for (int k = 0; k < NO; ++k)
+    if (!(fabs(ys[k]) <= DOMAIN)) return 0;
+  return 1;
+}
+
 double nyxo_mlp_loss_grad(const double* P, const double* x, const double* y, long n,
                           double* grad) {
   memset(grad, 0, sizeof(double) * NPARAM);
@@ -119,6 +135,7 @@ double nyxo_mlp_loss_grad(const double* P, const double* x, const double* y, lon
   for (long s = 0; s < n; ++s) {
     const double* xs = x + NI * s;
     const double* ys = y + NO * s;
+    if (!nyxo_mlp_in_domain(xs, ys)) continue;
     forward_one(P, xs, z1, h1, z2, h2, z3, h3, yh);
     for (int o = 0; o < NO; ++o) {
       double e = yh[o] - ys[o];

@@ -117,12 +117,16 @@ __global__ __launch_bounds__(64) void k_mlp_loss_grad(const float* __restrict__ 
                                                       double gamma, float inv_n,
                                                       float* __restrict__ grad, float* loss) {
   const long long s = (long long)blockIdx.x * 64 + threadIdx.x;
-  const bool valid = s < n;
+  bool valid = s < n;
   const bool lead = (threadIdx.x & 63) == 0;
   float x[kMlpIn], y[kMlpOut];
   if (valid) {
     record_xy(gamma, rec + 15 * s, x, y);
-  } else {
+    // only samples inside the training domain enter the loss
+    for (int k = 0; k < kMlpIn; ++k) valid = valid && fabsf(x[k]) <= kMlpDomain;
+    for (int k = 0; k < kMlpOut; ++k) valid = valid && fabsf(y[k]) <= kMlpDomain;
+  }
+  if (!valid) {
     for (int k = 0; k < kMlpIn; ++k) x[k] = 0.0f;
     for (int k = 0; k < kMlpOut; ++k) y[k] = 0.0f;
   }

@@ -29,6 +29,11 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMlpIn = 10, kMlpHid = 64, kMlpOut = 5;
+// Training domain: a face's normalised inputs and targets must be finite and
+// at most this large in magnitude (floored pressures or near-vacuum faces
+// normalise to huge values; they are left out of training and, in a step,
+// fall back to the two-shock solver).
+constexpr float kMlpDomain = 64.0f;
 constexpr int kMlpNParam = kMlpHid * kMlpIn + kMlpHid + 2 * (kMlpHid * kMlpHid + kMlpHid) +
                            kMlpOut * kMlpHid + kMlpOut;  // 9349
 // offsets in the flat FP32 parameter vector: W[o][i] row-major, then b

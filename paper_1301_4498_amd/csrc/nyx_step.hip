@@ -574,19 +574,20 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
 
 // Learned solve.  The network's pressure guess p0 = Pbar exp(y0) is corrected
 // by one Newton step of the two-shock relations; the result is accepted when
-// the two-shock velocity residual |u*_R(p1) - u*_L(p1)| / cbar at the
-// corrected pressure is below tol and the star state is positive and finite.
-// Otherwise the plain two-shock solver decides the face (*used = false).
+// the face's inputs lie in the training domain (`in_domain`), the two-shock
+// velocity residual |u*_R(p1) - u*_L(p1)| / cbar at the corrected pressure
+// is below tol and the star state is positive and finite.  Otherwise the
+// plain two-shock solver decides the face (*used = false).
 __device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const double* qL,
                                                     const double* qR, float y0, double pbar,
-                                                    double cbar, bool* used) {
+                                                    double cbar, bool in_domain, bool* used) {
   const TwoShock t = ts_setup(A, qL, qR);
   const double y = (double)(y0 < -40.0f ? -40.0f : (y0 > 40.0f ? 40.0f : y0));
   const double p0 = vmax(pbar * exp(y), t.sp);
   const double p1 = ts_newton(t, ts_eval(t, p0), p0);
   const TwoShockEval e = ts_eval(t, p1);
   const double resid = fabs(e.usR - e.usL) / cbar;
-  bool ok = resid < A.mlp_tol;  // never true for tol = 0 or a NaN residual
+  bool ok = in_domain && resid < A.mlp_tol;  // never true for tol = 0 or a NaN residual
   if (ok) {
     RiemannOut o = ts_finish(t, e, p1, qL, qR);
     ok = o.rsL > 0.0 && o.rsR > 0.0 && isfinite(o.rsL) && isfinite(o.rsR) && isfinite(o.r) &&
@@ -843,11 +844,16 @@ __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, cons
     float x[kMlpIn], y[kMlpOut];
     double rbar, cbar, ubar;
     mlp_inputs(A.gamma, a, b, x, &rbar, &cbar, &ubar);
-    for (int k = 0; k < kMlpIn; ++k) x[k] = isfinite(x[k]) ? x[k] : 0.0f;
+    bool in_domain = true;
+    for (int k = 0; k < kMlpIn; ++k) {
+      const bool inside = fabsf(x[k]) <= kMlpDomain;  // false for NaN
+      in_domain = in_domain && inside;
+      x[k] = inside ? x[k] : 0.0f;
+    }
     mlp_wave_forward(A.mlp, x, lds, y);
     if (active) {
       bool u = false;
-      g = learned_solve(A, qL, qR, y[0], rbar * cbar * cbar, cbar, &u);
+      g = learned_solve(A, qL, qR, y[0], rbar * cbar * cbar, cbar, in_domain, &u);
       *used += u ? 1u : 0u;
       *fallback += u ? 0u : 1u;
     }

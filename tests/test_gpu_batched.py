@@ -159,14 +159,18 @@ def test_ghost_fills(nyx):
     assert np.array_equal(T.cpu().numpy(), want)
 
 
-def test_graph_replay_matches_eager(nyx):
+@pytest.mark.parametrize("tune", [0, 13])
+def test_graph_replay_matches_eager(nyx, tune):
     # capture [step with fused dt_next -> ghost fill] x 2 into a HIP graph and
-    # replay it; every replay must reproduce the eager sequence bitwise
+    # replay it; every replay must reproduce the eager sequence bitwise (with
+    # the default launch order and with a tuned one: cell-major rows, slab
+    # pencils of 32 rows)
     import torch
     prm = nyx.default_params()
     boxes, states, gravs, flat, gflat = _pack(nyx, SHAPES[:3])
     _, one = nyx.Batch.workspace_bytes(prm, boxes)
     plan = nyx.Batch(prm, boxes, aligned_ws(one))
+    plan.set_tuning([tune] * 7)
     G = to_dev(gflat)
     nb = len(boxes)
 

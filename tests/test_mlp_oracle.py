@@ -87,3 +87,33 @@ def test_normalisation_special_cases():
     r3[[4, 9, 10]] *= 3.0
     x3, y3 = oracle.mlp_normalize(r3[None])
     assert np.allclose(x1, x3, atol=1e-13) and np.allclose(y1, y3, atol=1e-13)
+
+
+def test_training_domain_excludes_outlier_samples():
+    # a face whose pressures sit at the floor (sound speeds ~ 1e-10) while its
+    # velocities differ normalises to inputs far outside the training domain
+    # (|x| > 64): it contributes nothing, and the loss stays normalised by the
+    # batch size
+    rng = np.random.default_rng(3)
+    n = 40
+    raw = np.zeros((n, 15))
+    raw[:, 0] = rng.uniform(0.5, 2.0, n)
+    raw[:, 1] = rng.normal(0, 0.3, n)
+    raw[:, 4] = rng.uniform(0.5, 2.0, n)
+    raw[:, 5] = rng.uniform(0.5, 2.0, n)
+    raw[:, 6] = rng.normal(0, 0.3, n)
+    raw[:, 9] = rng.uniform(0.5, 2.0, n)
+    raw[:, 10] = 0.5 * (raw[:, 4] + raw[:, 9])
+    raw[:, 11] = 0.5 * (raw[:, 1] + raw[:, 6])
+    raw[:, 12:15] = raw[:, [0, 5, 0]]
+    out = raw[:1].copy()
+    out[0, 4] = out[0, 9] = 1e-20
+    out[0, 1], out[0, 6] = 1.0, -1.0   # (u_L - ubar) / cbar ~ 1e10, finite
+    x, y = oracle.mlp_normalize(raw)
+    xo, yo = oracle.mlp_normalize(out)
+    assert np.isfinite(xo).all() and np.abs(xo).max() > 64
+    P = rng.normal(0, 0.1, 9349)
+    l_in, g_in = oracle.mlp_loss_grad(P, x, y)
+    l_all, g_all = oracle.mlp_loss_grad(P, np.vstack([x, xo]), np.vstack([y, yo]))
+    assert l_all * (n + 1) == pytest.approx(l_in * n, rel=1e-12)
+    assert np.allclose(g_all * (n + 1), g_in * n, rtol=1e-12, atol=1e-15)
