@@ -51,8 +51,14 @@ class _Params(ctypes.Structure):
         ("small_pres", ctypes.c_double),
         ("riemann_tol", ctypes.c_double),
         ("riemann_maxiter", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("recon", ctypes.c_int32),
+        ("riemann", ctypes.c_int32),
+        ("grav_form", ctypes.c_int32),
     ]
+
+
+RECON_PPM, RECON_PLM = 0, 1
+RIEMANN_TWOSHOCK, RIEMANN_LINEAR = 0, 1
 
 
 class _Stats(ctypes.Structure):
@@ -73,10 +79,14 @@ class Params:
     small_pres: float = 1e-20
     riemann_tol: float = 1e-14
     riemann_maxiter: int = 20
+    recon: int = RECON_PPM          # Sec. 3.2: PPM, or PLM
+    riemann: int = RIEMANN_TWOSHOCK  # Sec. 3.2: two-shock, or the linearised solver
+    grav_form: int = 1               # Sec. 3.2: energy gravity term, form 1 or 2
 
     def c(self) -> _Params:
         return _Params(self.gamma, self.eta, self.small_dens, self.small_pres,
-                       self.riemann_tol, int(self.riemann_maxiter), 0)
+                       self.riemann_tol, int(self.riemann_maxiter), int(self.recon),
+                       int(self.riemann), int(self.grav_form))
 
 
 _lib = None
@@ -101,6 +111,8 @@ def lib():
         L.nyxo_riemann.restype = None
         L.nyxo_ppm_line.argtypes = [i, _D, _D, _D, _D]
         L.nyxo_ppm_line.restype = None
+        L.nyxo_plm_line.argtypes = [i, _D, _D, _D, _D]
+        L.nyxo_plm_line.restype = None
         L.nyxo_ppm_interface.argtypes = [_D]
         L.nyxo_ppm_interface.restype = d
         L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
@@ -167,7 +179,8 @@ def hydro_step(state: np.ndarray, grav: np.ndarray, ng: int, dt: float,
 
 
 def riemann(qL, qR, params: Params | None = None):
-    """Two-shock solve on rotated states (rho, u_n, u_t1, u_t2, p).
+    """Riemann solve (two-shock, or the linearised solver per params) on
+    rotated states (rho, u_n, u_t1, u_t2, p).
     Returns (godunov_state[5], {p, u, rhoL, rhoR}, iterations)."""
     params = params or Params()
     qL = np.ascontiguousarray(qL, dtype=np.float64)
@@ -193,6 +206,17 @@ def ppm_line(q, chi=None):
     qm = np.full(m, np.nan)
     qp = np.full(m, np.nan)
     lib().nyxo_ppm_line(m, _ptr(q), _ptr(chi), _ptr(qm), _ptr(qp))
+    return qm, qp
+
+
+def plm_line(q, chi=None):
+    """PLM edge values (qm, qp) for cells 2..m-3 of a line; NaN elsewhere."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    m = q.shape[0]
+    chi = np.ones(m) if chi is None else np.ascontiguousarray(chi, dtype=np.float64)
+    qm = np.full(m, np.nan)
+    qp = np.full(m, np.nan)
+    lib().nyxo_plm_line(m, _ptr(q), _ptr(chi), _ptr(qm), _ptr(qp))
     return qm, qp
 
 

@@ -35,6 +35,10 @@
 #define FLAT_OMEGA2 10.0
 
 static double dmax(double a, double b) { return a > b ? a : b; }
+/* kinetic energy |m|^2 / (2 rho) of a momentum m in the stored variables */
+static double kinetic(const double* m, double rho) {
+  return (0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2])) / rho;
+}
 static double dmin(double a, double b) { return a < b ? a : b; }
 
 /* ------------------------------------------------------------------ */
@@ -74,8 +78,45 @@ static long eid(const Box* b, int i, int j, int k) {
  * approximation replaces both waves by shocks; the star pressure solves
  * u*_R(p) = u*_L(p) with the shock Lagrangian wave speeds W_K and is found by
  * Newton iteration (Z_K = 1/|du*_K/dp|). */
+static void sample_star(double gam, const double* qL, const double* qR, double pstar,
+                        double ustar, double rsL, double rsR, double WL, double WR,
+                        double* qg);
+
+/* Linearised approximate solver (the simpler alternative Sec. 3.2 compares
+ * the two-shock solver against): the acoustic star state, with impedances
+ * W_K = sqrt(gamma p_K rho_K),
+ *   p* = (W_R p_L + W_L p_R + W_L W_R (u_L - u_R)) / (W_L + W_R),
+ *   u* = (W_L u_L + W_R u_R + p_L - p_R) / (W_L + W_R),
+ *   rho*_K = rho_K + (p* - p_K) / c_K^2,
+ * sampled with the same wave structure as the two-shock solver.  With p*
+ * at least the pressure floor, rho*_K >= (1 - 1/gamma) rho_K > 0, so the
+ * star densities need no floor. */
+static void linear_solve(const nyxo_params* prm, const double* qL, const double* qR,
+                         double* qg, double* star) {
+  const double gam = prm->gamma;
+  const double g2 = 0.5 * (gam + 1.0);
+  double rl = qL[0], ul = qL[1], pl = qL[4];
+  double rr = qR[0], ur = qR[1], pr = qR[4];
+  double CL = (gam * pl) * rl;
+  double CR = (gam * pr) * rr;
+  double W0L = sqrt(CL), W0R = sqrt(CR);
+  double p = ((W0R * pl + W0L * pr) + (W0L * W0R) * (ul - ur)) / (W0L + W0R);
+  p = dmax(p, prm->small_pres);
+  double ustar = ((W0L * ul + W0R * ur) + (pl - pr)) / (W0L + W0R);
+  double rsL = rl + (p - pl) / ((gam * pl) / rl);
+  double rsR = rr + (p - pr) / ((gam * pr) / rr);
+  double WL = sqrt(CL + (g2 * rl) * (p - pl));
+  double WR = sqrt(CR + (g2 * rr) * (p - pr));
+  sample_star(gam, qL, qR, p, ustar, rsL, rsR, WL, WR, qg);
+  if (star) { star[0] = p; star[1] = ustar; star[2] = rsL; star[3] = rsR; }
+}
+
 static int riemann_solve(const nyxo_params* prm, const double* qL,
                          const double* qR, double* qg, double* star) {
+  if (prm->riemann == NYXO_RIEMANN_LINEAR) {
+    linear_solve(prm, qL, qR, qg, star);
+    return 0;
+  }
   const double gam = prm->gamma;
   const double g2 = 0.5 * (gam + 1.0);
   const double sp = prm->small_pres;
@@ -115,6 +156,20 @@ static int riemann_solve(const nyxo_params* prm, const double* qL,
   /* star densities from the shock (Hugoniot) relation on both sides */
   double rsL = 1.0 / (1.0 / rl - (pstar - pl) / (WL * WL));
   double rsR = 1.0 / (1.0 / rr - (pstar - pr) / (WR * WR));
+  sample_star(gam, qL, qR, pstar, ustar, rsL, rsR, WL, WR, qg);
+  if (star) { star[0] = pstar; star[1] = ustar; star[2] = rsL; star[3] = rsR; }
+  return it;
+}
+
+/* Wave structure of the star state and the sample at x/t = 0: a shock
+ * (p* >= p_K) is one front at u_K -/+ W_K / rho_K; a rarefaction has its
+ * head at u_K -/+ c_K and its tail at u* -/+ c*_K with linear interpolation
+ * between them; at u* = 0 the mean of both sides. */
+static void sample_star(double gam, const double* qL, const double* qR, double pstar,
+                        double ustar, double rsL, double rsR, double WL, double WR,
+                        double* qg) {
+  double rl = qL[0], ul = qL[1], pl = qL[4];
+  double rr = qR[0], ur = qR[1], pr = qR[4];
   double cL = sqrt((gam * pl) / rl), cR = sqrt((gam * pr) / rr);
   double csL = sqrt((gam * pstar) / rsL), csR = sqrt((gam * pstar) / rsR);
   double shdL, stlL, shdR, stlR;
@@ -151,8 +206,6 @@ static int riemann_solve(const nyxo_params* prm, const double* qL,
     qg[2] = 0.5 * (qL[2] + qR[2]);
     qg[3] = 0.5 * (qL[3] + qR[3]);
   }
-  if (star) { star[0] = pstar; star[1] = ustar; star[2] = rsL; star[3] = rsR; }
-  return it;
 }
 
 void nyxo_riemann(const nyxo_params* prm, const double* qL, const double* qR,
@@ -240,6 +293,21 @@ static void ppm_cell(const double* q5, double chi, double* qm_out,
   }
   *qm_out = qm;
   *qp_out = qp;
+}
+
+/* PLM (unsplit piecewise linear, Sec. 3.2): the limited centred slope of
+ * cell j, flattened by chi, gives the edge values q_j -/+ (chi s)/2; the
+ * tracing below then averages this linear profile over each wave's domain
+ * of dependence (the parabola's q6 term vanishes). */
+static void plm_cell(const double* q5, double chi, double* qm_out, double* qp_out) {
+  double qj = q5[2];
+  double ds = chi * limited_slope(q5[1], q5[2], q5[3]);
+  *qm_out = qj - 0.5 * ds;
+  *qp_out = qj + 0.5 * ds;
+}
+
+void nyxo_plm_line(int m, const double* q, const double* chi, double* qm, double* qp) {
+  for (int j = 2; j <= m - 3; ++j) plm_cell(q + j - 2, chi[j], &qm[j], &qp[j]);
 }
 
 void nyxo_ppm_line(int m, const double* q, const double* chi, double* qm,
@@ -450,6 +518,10 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
   if (!prm || !Uin || !grav || !Uout || nx < 1 || ny < 1 || nz < 1 || ng < 4 ||
       !(dt > 0.0) || !(a_old > 0.0) || !(a_new > 0.0) || !(dx > 0.0))
     return -1;
+  if ((prm->recon != NYXO_RECON_PPM && prm->recon != NYXO_RECON_PLM) ||
+      (prm->riemann != NYXO_RIEMANN_TWOSHOCK && prm->riemann != NYXO_RIEMANN_LINEAR) ||
+      (prm->grav_form != 1 && prm->grav_form != 2))
+    return -1;
   nyxo_stats stl;
   memset(&stl, 0, sizeof stl);
   nyxo_stats* st = &stl;
@@ -545,7 +617,8 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
               c3[d] += s;
               q5[s + 2] = PRIM(v, c3[0], c3[1], c3[2]);
             }
-            ppm_cell(q5, chi[e], &qmv[v], &qpv[v]);
+            if (prm->recon == NYXO_RECON_PLM) plm_cell(q5, chi[e], &qmv[v], &qpv[v]);
+            else ppm_cell(q5, chi[e], &qmv[v], &qpv[v]);
           }
           double lo[5], hi[5];
           st->floor_hits += nyxo_trace_cell(prm, d, qc, cc, qmv, qpv, g, kh,
@@ -690,15 +763,30 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
         double g[3] = {grav[id], grav[P + id], grav[2 * P + id]};
         /* predictor (Step 2) */
         double s0 = U0 - k * D[0];
-        double sm[3];
-        for (int d = 0; d < 3; ++d) sm[d] = (Um[d] - k * D[1 + d]) + (dt * U0) * g[d];
-        double sE = (UE - k * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+        double mh[3], sm[3];
+        for (int d = 0; d < 3; ++d) {
+          mh[d] = Um[d] - k * D[1 + d];
+          sm[d] = mh[d] + (dt * U0) * g[d];
+        }
+        double sE;
+        if (prm->grav_form == 2) {
+          /* form 2: E changes by the change of the kinetic energy that the
+           * gravity momentum update causes (at the new density) */
+          sE = (UE - k * D[4]) + (kinetic(sm, s0) - kinetic(mh, s0));
+        } else {
+          sE = (UE - k * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+        }
         double se = (Ue - k * D[5]) - (k * a_h) * Pi;
         /* corrector (Step 6) with the same g */
         double nm[3];
         for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
-        double nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
-                                       (sm[2] - Um[2]) * g[2]);
+        double nE;
+        if (prm->grav_form == 2) {
+          nE = sE + (kinetic(nm, s0) - kinetic(sm, s0));
+        } else {
+          nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
+                                  (sm[2] - Um[2]) * g[2]);
+        }
         double ne = se;
         /* dual-energy sync (Step 6) */
         double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;

@@ -25,6 +25,12 @@
 extern "C" {
 #endif
 
+/* Scheme variants that Sec. 3.2 describes. */
+#define NYXO_RECON_PPM 0        /* unsplit piecewise parabolic reconstruction */
+#define NYXO_RECON_PLM 1        /* unsplit piecewise linear reconstruction */
+#define NYXO_RIEMANN_TWOSHOCK 0 /* iterative two-shock solver (Colella & Glaz) */
+#define NYXO_RIEMANN_LINEAR 1   /* linearised (acoustic) approximate solver */
+
 typedef struct {
   double gamma;        /* gamma-law EOS exponent (Sec. 2.2: 5/3) */
   double eta;          /* dual-energy threshold (Sec. 3.6, Step 6: 1e-4) */
@@ -32,7 +38,11 @@ typedef struct {
   double small_pres;   /* pressure floor, primitives, edge states, Riemann */
   double riemann_tol;  /* relative stopping tolerance of the two-shock iteration */
   int32_t riemann_maxiter;
-  int32_t pad_;
+  int32_t recon;       /* NYXO_RECON_* */
+  int32_t riemann;     /* NYXO_RIEMANN_* */
+  int32_t grav_form;   /* energy gravity term (Sec. 3.2): 1 = (rho U).g at cell
+                        * centres, 2 = the update of E is the update of the
+                        * kinetic energy from the gravity momentum update */
 } nyxo_params;
 
 typedef struct {
@@ -74,6 +84,9 @@ void nyxo_riemann(const nyxo_params* prm, const double* qL, const double* qR,
  * flattening coefficient of cell j.  Other entries are left untouched. */
 void nyxo_ppm_line(int m, const double* q, const double* chi, double* qm,
                    double* qp);
+/* O3 variant: PLM edge values (q_j -/+ chi s_j / 2, s_j the limited centred
+ * slope) of cells 2..m-3 of a line, same layout as nyxo_ppm_line. */
+void nyxo_plm_line(int m, const double* q, const double* chi, double* qm, double* qp);
 
 /* Unflattened fourth-order interface value between cells j and j+1 from
  * q[j-1..j+2] with van Leer-limited slopes (q points at q[j-1]). */
