@@ -18,6 +18,10 @@ Batched-level leg (level4096): 4096 boxes with edges drawn from {16, 24, 32,
 48, 64} per axis, self-periodic ghosts, per-box dt: one batched plan per
 step (also replayed as a captured HIP graph) against per-box launches.
 
+Variants leg: PLM reconstruction, the linearised Riemann solver and the
+second form of the energy gravity term (Sec. 3.2) on the same box, each in
+FP32-mixed against its own plain FP64 run.
+
 Stress leg (box512_stress): a 512^3 domain with density contrast up to 10^4
 and flows up to Mach 30, plain FP64 as one box against FP32-mixed (and the
 learned flux, trained on smooth flows or on stress faces) on an 8^3 grid of
@@ -390,6 +394,27 @@ def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
     return out
 
 
+def variants_leg(nyx, torch, w, steps, warmup, log):
+    """The scheme variants of Sec. 3.2 on the benchmark box (FP32-mixed, each
+    against its own plain FP64 run): PLM reconstruction, the linearised
+    Riemann solver, the second form of the energy gravity term."""
+    import numpy as np
+    out = {}
+    for name, kw in (("plm", dict(recon=nyx.NYX_RECON_PLM)),
+                     ("linearized_riemann", dict(riemann=nyx.NYX_RIEMANN_LINEARIZED)),
+                     ("gravity_energy_form2", dict(grav_energy_form=2))):
+        m = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_MIXED, **kw), steps, warmup)
+        f = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_FP64, **kw), steps, warmup)
+        l1 = float(np.abs(m["rho"] - f["rho"]).sum() / np.abs(f["rho"]).sum())
+        out[name] = {"mixed_zone_updates_per_s": m["zone_updates_per_s"],
+                     "fp64_zone_updates_per_s": f["zone_updates_per_s"],
+                     "mixed_rho_l1_vs_fp64": l1, "finite": m["finite"] and f["finite"],
+                     "mean_riemann_iters": m["mean_riemann_iters"]}
+        log("variant %s: mixed %.3e, fp64 %.3e zone-updates/s, rho L1 %.2e"
+            % (name, m["zone_updates_per_s"], f["zone_updates_per_s"], l1))
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
     import oracle
@@ -421,6 +446,8 @@ def main():
     ap.add_argument("--no-level", action="store_true", help="skip the 4096-box batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stress", action="store_true", help="skip the 512^3 stress leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the PLM / linearised-solver / gravity-form-2 leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -537,6 +564,8 @@ def main():
             out["learned_training"] = extra["learned_training"]
     if not args.no_level:
         out["level4096"] = level_leg(nyx, torch, synth, max(args.steps // 2 * 2, 2), log)
+    if not args.no_variants:
+        out["variants"] = variants_leg(nyx, torch, w, args.steps, args.warmup, log)
     if not args.no_stress:
         out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
                                           flux, 10, log)

@@ -60,7 +60,22 @@ typedef enum {
 } nyx_status;
 
 typedef enum { NYX_FP64 = 0, NYX_MIXED = 1 } nyx_precision;
-typedef enum { NYX_RIEMANN_TWOSHOCK = 0, NYX_RIEMANN_LEARNED = 1 } nyx_riemann;
+/* Riemann solver of the faces (Sec. 3.2): the iterative two-shock solver;
+ * the learned flux (this library's addition, with the two-shock solver as
+ * fallback); or the simpler linearised approximate solver Sec. 3.2 compares
+ * against: acoustic star state p* = (W_R p_L + W_L p_R + W_L W_R (u_L -
+ * u_R))/(W_L + W_R), u* = (W_L u_L + W_R u_R + p_L - p_R)/(W_L + W_R) with
+ * W_K = sqrt(gamma p_K rho_K), rho*_K = rho_K + (p* - p_K)/c_K^2, sampled
+ * with the two-shock wave structure, no iteration. */
+typedef enum {
+  NYX_RIEMANN_TWOSHOCK = 0,
+  NYX_RIEMANN_LEARNED = 1,
+  NYX_RIEMANN_LINEARIZED = 2
+} nyx_riemann;
+/* Reconstruction of the time-centred edge states (Sec. 3.2): unsplit PPM, or
+ * unsplit piecewise linear (limited centred slopes times the flattening
+ * coefficient); both are traced with the reference state of Sec. 3.2. */
+typedef enum { NYX_RECON_PPM = 0, NYX_RECON_PLM = 1 } nyx_recon;
 
 typedef struct {
   double gamma;          /* gamma-law exponent, > 1 (Sec. 2.2: 5/3) */
@@ -77,6 +92,11 @@ typedef struct {
   int32_t precision;           /* nyx_precision */
   int32_t riemann;             /* nyx_riemann */
   int32_t learned_stages_mask; /* bit s set: stage s (0, 1, 2) uses the MLP */
+  int32_t recon;               /* nyx_recon */
+  int32_t grav_energy_form;    /* energy gravity term (Sec. 3.2): 1 = (aρU).g at
+                                * cell centres; 2 = the update of a^2 rho E is
+                                * the update of the kinetic energy the gravity
+                                * momentum terms cause */
   const void* mlp_weights;     /* (device) packed learned-flux weights, or NULL */
 } nyx_params;
 

@@ -10,11 +10,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (NYX_FP64, NYX_MIXED, NYX_RIEMANN_LEARNED, NYX_RIEMANN_TWOSHOCK, STATS_FIELDS,
-                   Box, NyxError, Params, Stats, check, lib)
+from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMANN_LEARNED,
+                   NYX_RIEMANN_LINEARIZED, NYX_RIEMANN_TWOSHOCK, STATS_FIELDS, Box, NyxError,
+                   Params, Stats, check, lib)
 
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
-           "NYX_RIEMANN_LEARNED", "default_params", "make_box", "workspace_bytes", "estimate_dt",
+           "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
+           "default_params", "make_box", "workspace_bytes", "estimate_dt",
            "hydro_step", "fill_ghosts_periodic", "Batch", "stats_dict"]
 
 

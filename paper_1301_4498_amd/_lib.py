@@ -14,6 +14,9 @@ NYX_FP64 = 0
 NYX_MIXED = 1
 NYX_RIEMANN_TWOSHOCK = 0
 NYX_RIEMANN_LEARNED = 1
+NYX_RIEMANN_LINEARIZED = 2
+NYX_RECON_PPM = 0
+NYX_RECON_PLM = 1
 
 STATUS = {0: "NYX_OK", -1: "NYX_E_NULL", -2: "NYX_E_SHAPE", -3: "NYX_E_PARAM",
           -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE"}
@@ -32,6 +35,8 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("riemann", ctypes.c_int32),
         ("learned_stages_mask", ctypes.c_int32),
+        ("recon", ctypes.c_int32),
+        ("grav_energy_form", ctypes.c_int32),
         ("mlp_weights", ctypes.c_void_p),
     ]
 

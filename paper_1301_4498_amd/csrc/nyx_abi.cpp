@@ -39,7 +39,11 @@ int check_params(const nyx_params* p) {
   if (!finite_pos(p->cfl)) return NYX_E_PARAM;
   if (p->riemann_maxiter < 1 || p->riemann_maxiter > 64) return NYX_E_PARAM;
   if (p->precision != NYX_FP64 && p->precision != NYX_MIXED) return NYX_E_PARAM;
-  if (p->riemann != NYX_RIEMANN_TWOSHOCK && p->riemann != NYX_RIEMANN_LEARNED) return NYX_E_PARAM;
+  if (p->riemann != NYX_RIEMANN_TWOSHOCK && p->riemann != NYX_RIEMANN_LEARNED &&
+      p->riemann != NYX_RIEMANN_LINEARIZED)
+    return NYX_E_PARAM;
+  if (p->recon != NYX_RECON_PPM && p->recon != NYX_RECON_PLM) return NYX_E_PARAM;
+  if (p->grav_energy_form != 1 && p->grav_energy_form != 2) return NYX_E_PARAM;
   if (p->riemann == NYX_RIEMANN_LEARNED) {
     if (p->precision != NYX_MIXED) return NYX_E_UNSUPPORTED;
     if (!p->mlp_weights) return NYX_E_NULL;
@@ -101,6 +105,9 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   a.mlp = learned ? p->mlp_weights : nullptr;
   a.learned_mask = learned ? p->learned_stages_mask : 0;
   a.mlp_tol = p->mlp_resid_tol;
+  a.recon = p->recon;
+  a.grav_form = p->grav_energy_form;
+  a.linear_riemann = p->riemann == NYX_RIEMANN_LINEARIZED ? 1 : 0;
 }
 
 // ---- stage timing ----
@@ -157,6 +164,8 @@ void nyx_default_params(nyx_params* p) {
   p->precision = NYX_FP64;
   p->riemann = NYX_RIEMANN_TWOSHOCK;
   p->learned_stages_mask = 0;
+  p->recon = NYX_RECON_PPM;
+  p->grav_energy_form = 1;
   p->mlp_weights = nullptr;
 }
 

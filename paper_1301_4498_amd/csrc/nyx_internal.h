@@ -251,6 +251,10 @@ struct StepArgs {
   unsigned harvest_keep;   // keep a face when its 32-bit hash < harvest_keep
   unsigned long long harvest_seed;
   int tune[kStages];       // launch-order candidate per stage (kTune* bits)
+  // scheme variants (Sec. 3.2)
+  int recon;               // NYX_RECON_PPM or NYX_RECON_PLM
+  int grav_form;           // energy gravity term, 1 or 2
+  int linear_riemann;      // 1: linearised solver instead of the two-shock one
 };
 
 

@@ -256,6 +256,15 @@ __device__ __forceinline__ void ppm_edges(const real* q5, real chi, real& qm_o, 
   qm_o = qm;
   qp_o = qp;
 }
+// PLM variant (Sec. 3.2): the limited centred slope times the flattening
+// coefficient gives the edge values q_j -/+ ds/2 (the tracing below then
+// averages the linear profile: the parabola's q6 term vanishes)
+__device__ __forceinline__ void plm_edges(const real* q5, real chi, real& qm_o, real& qp_o) {
+  const real qj = q5[2];
+  const real ds = chi * lim_slope(q5[1], q5[2], q5[3]);
+  qm_o = qj - (real)0.5 * ds;
+  qp_o = qj + (real)0.5 * ds;
+}
 __device__ __forceinline__ real avg_hi(real qp, real dq, real q6, real sig) {
   return qp - (real)0.5 * sig * (dq - ((real)1 - ((real)2 / (real)3) * sig) * q6);
 }
@@ -337,7 +346,8 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
       real q5[5];
       for (int o = -2; o <= 2; ++o) q5[o + 2] = ldu(Q + (long long)o * s, c0);
       qc[v] = q5[2];
-      ppm_edges(q5, chi, qm[v], qp[v]);
+      if (A.recon == NYX_RECON_PLM) plm_edges(q5, chi, qm[v], qp[v]);
+      else ppm_edges(q5, chi, qm[v], qp[v]);
       dq[v] = qp[v] - qm[v];
       q6[v] = (real)6 * qc[v] - (real)3 * (qm[v] + qp[v]);
     }
@@ -394,6 +404,84 @@ struct RiemannOut {
   double pstar, ustar, rsL, rsR;  // star pressure, velocity and densities
   int iters;
 };
+
+// Wave structure of a star state and its sample at x/t = 0 (O5, exact
+// divisions and square roots): a shock (p* >= p_K) is one front at
+// u_K -/+ W_K / rho_K; a rarefaction has its head at u_K -/+ c_K and its tail
+// at u* -/+ c*_K with linear interpolation between them; u* = 0 takes the
+// mean of both sides.
+__device__ __forceinline__ void sample_star(double gam, const double* qL, const double* qR,
+                                            double pstar, double ustar, double rsL, double rsR,
+                                            double WL, double WR, RiemannOut& o) {
+  const double rl = qL[0], ul = qL[1], pl = qL[4];
+  const double rr = qR[0], ur = qR[1], pr = qR[4];
+  const double cL = sqrt((gam * pl) / rl), cR = sqrt((gam * pr) / rr);
+  const double csL = sqrt((gam * pstar) / rsL), csR = sqrt((gam * pstar) / rsR);
+  double shdL, stlL, shdR, stlR;
+  if (pstar >= pl) { shdL = ul - WL / rl; stlL = shdL; }
+  else { shdL = ul - cL; stlL = ustar - csL; }
+  if (pstar >= pr) { shdR = ur + WR / rr; stlR = shdR; }
+  else { shdR = ur + cR; stlR = ustar + csR; }
+  double sL0, sL1, sL2, sR0, sR1, sR2;
+  if (shdL >= 0.0) { sL0 = rl; sL1 = ul; sL2 = pl; }
+  else if (stlL <= 0.0) { sL0 = rsL; sL1 = ustar; sL2 = pstar; }
+  else {
+    double f = (0.0 - shdL) / (stlL - shdL);
+    sL0 = rl + f * (rsL - rl);
+    sL1 = ul + f * (ustar - ul);
+    sL2 = pl + f * (pstar - pl);
+  }
+  if (shdR <= 0.0) { sR0 = rr; sR1 = ur; sR2 = pr; }
+  else if (stlR >= 0.0) { sR0 = rsR; sR1 = ustar; sR2 = pstar; }
+  else {
+    double f = (0.0 - shdR) / (stlR - shdR);
+    sR0 = rr + f * (rsR - rr);
+    sR1 = ur + f * (ustar - ur);
+    sR2 = pr + f * (pstar - pr);
+  }
+  if (ustar > 0.0) {
+    o.r = sL0; o.u = sL1; o.p = sL2; o.v = qL[2]; o.w = qL[3];
+  } else if (ustar < 0.0) {
+    o.r = sR0; o.u = sR1; o.p = sR2; o.v = qR[2]; o.w = qR[3];
+  } else {
+    o.r = 0.5 * (sL0 + sR0);
+    o.u = 0.5 * (sL1 + sR1);
+    o.p = 0.5 * (sL2 + sR2);
+    o.v = 0.5 * (qL[2] + qR[2]);
+    o.w = 0.5 * (qL[3] + qR[3]);
+  }
+  o.pstar = pstar;
+  o.ustar = ustar;
+  o.rsL = rsL;
+  o.rsR = rsR;
+}
+
+// Linearised approximate solver (the alternative Sec. 3.2 compares the
+// two-shock solver against): acoustic star state with impedances
+// W_K = sqrt(gamma p_K rho_K), rho*_K = rho_K + (p* - p_K)/c_K^2
+// (>= (1 - 1/gamma) rho_K once p* is floored), sampled with the two-shock
+// wave structure; no iteration.
+__device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double* qL,
+                                                const double* qR) {
+  const double gam = A.gamma;
+  const double g2 = 0.5 * (gam + 1.0);
+  const double rl = qL[0], ul = qL[1], pl = qL[4];
+  const double rr = qR[0], ur = qR[1], pr = qR[4];
+  const double CL = (gam * pl) * rl;
+  const double CR = (gam * pr) * rr;
+  const double W0L = sqrt(CL), W0R = sqrt(CR);
+  double p = ((W0R * pl + W0L * pr) + (W0L * W0R) * (ul - ur)) / (W0L + W0R);
+  p = vmax(p, A.small_pres);
+  const double ustar = ((W0L * ul + W0R * ur) + (pl - pr)) / (W0L + W0R);
+  const double rsL = rl + (p - pl) / ((gam * pl) / rl);
+  const double rsR = rr + (p - pr) / ((gam * pr) / rr);
+  const double WL = sqrt(CL + (g2 * rl) * (p - pl));
+  const double WR = sqrt(CR + (g2 * rr) * (p - pr));
+  RiemannOut o;
+  sample_star(gam, qL, qR, p, ustar, rsL, rsR, WL, WR, o);
+  o.iters = 0;
+  return o;
+}
 
 #if defined(NYX_PREC_MIXED)
 // FP64 reciprocal and reciprocal square root from the hardware estimates
@@ -640,46 +728,8 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
   const double pstar = p;
   const double rsL = 1.0 / (1.0 / rl - (pstar - pl) / (WL * WL));
   const double rsR = 1.0 / (1.0 / rr - (pstar - pr) / (WR * WR));
-  const double cL = sqrt((gam * pl) / rl), cR = sqrt((gam * pr) / rr);
-  const double csL = sqrt((gam * pstar) / rsL), csR = sqrt((gam * pstar) / rsR);
-  double shdL, stlL, shdR, stlR;
-  if (pstar >= pl) { shdL = ul - WL / rl; stlL = shdL; }
-  else { shdL = ul - cL; stlL = ustar - csL; }
-  if (pstar >= pr) { shdR = ur + WR / rr; stlR = shdR; }
-  else { shdR = ur + cR; stlR = ustar + csR; }
-  double sL0, sL1, sL2, sR0, sR1, sR2;
-  if (shdL >= 0.0) { sL0 = rl; sL1 = ul; sL2 = pl; }
-  else if (stlL <= 0.0) { sL0 = rsL; sL1 = ustar; sL2 = pstar; }
-  else {
-    double f = (0.0 - shdL) / (stlL - shdL);
-    sL0 = rl + f * (rsL - rl);
-    sL1 = ul + f * (ustar - ul);
-    sL2 = pl + f * (pstar - pl);
-  }
-  if (shdR <= 0.0) { sR0 = rr; sR1 = ur; sR2 = pr; }
-  else if (stlR >= 0.0) { sR0 = rsR; sR1 = ustar; sR2 = pstar; }
-  else {
-    double f = (0.0 - shdR) / (stlR - shdR);
-    sR0 = rr + f * (rsR - rr);
-    sR1 = ur + f * (ustar - ur);
-    sR2 = pr + f * (pstar - pr);
-  }
   RiemannOut o;
-  if (ustar > 0.0) {
-    o.r = sL0; o.u = sL1; o.p = sL2; o.v = qL[2]; o.w = qL[3];
-  } else if (ustar < 0.0) {
-    o.r = sR0; o.u = sR1; o.p = sR2; o.v = qR[2]; o.w = qR[3];
-  } else {
-    o.r = 0.5 * (sL0 + sR0);
-    o.u = 0.5 * (sL1 + sR1);
-    o.p = 0.5 * (sL2 + sR2);
-    o.v = 0.5 * (qL[2] + qR[2]);
-    o.w = 0.5 * (qL[3] + qR[3]);
-  }
-  o.pstar = pstar;
-  o.ustar = ustar;
-  o.rsL = rsL;
-  o.rsR = rsR;
+  sample_star(gam, qL, qR, pstar, ustar, rsL, rsR, WL, WR, o);
   o.iters = it;
   return o;
 }
@@ -860,7 +910,7 @@ __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, cons
     return g;
   }
 #endif
-  if (active) g = two_shock(A, qL, qR);
+  if (active) g = A.linear_riemann ? lin_solve(A, qL, qR) : two_shock(A, qL, qR);
   return g;
 }
 
@@ -1135,6 +1185,15 @@ __device__ __forceinline__ double cell_speed(const StepArgs& A, double U0, doubl
   return s;
 }
 
+// kinetic energy |m|^2 / (2 rho) of a momentum in the stored variables
+__device__ __forceinline__ double kinetic(const double* m, double rho) {
+#if defined(NYX_PREC_MIXED)
+  return (0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2])) * rcp64(rho);
+#else
+  return (0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2])) / rho;
+#endif
+}
+
 __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* dst) {
   __shared__ double red[kBlock / 64];
   for (int o = 32; o > 0; o >>= 1) s = vmax(s, __shfl_xor(s, o, 64));
@@ -1191,15 +1250,30 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     const double dt = C.dt, kk = C.k;
     // predictor (Step 2)
     const double s0 = U0 - kk * D[0];
-    double sm[3];
-    for (int d = 0; d < 3; ++d) sm[d] = (Um[d] - kk * D[1 + d]) + (dt * U0) * g[d];
-    const double sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+    double mh[3], sm[3];
+    for (int d = 0; d < 3; ++d) {
+      mh[d] = Um[d] - kk * D[1 + d];
+      sm[d] = mh[d] + (dt * U0) * g[d];
+    }
+    double sE;
+    if (A.grav_form == 2) {
+      // form 2 (Sec. 3.2): E changes by the kinetic energy the gravity
+      // momentum update causes, at the new density
+      sE = (UE - kk * D[4]) + (kinetic(sm, s0) - kinetic(mh, s0));
+    } else {
+      sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+    }
     const double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
     // corrector (Step 6), same g
     double nm[3];
     for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
-    double nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
-                                   (sm[2] - Um[2]) * g[2]);
+    double nE;
+    if (A.grav_form == 2) {
+      nE = sE + (kinetic(nm, s0) - kinetic(sm, s0));
+    } else {
+      nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
+                              (sm[2] - Um[2]) * g[2]);
+    }
     double ne = se;
     // dual-energy sync (Step 6)
 #if defined(NYX_PREC_MIXED)

@@ -36,6 +36,8 @@ def test_defaults_and_status_strings(nyx):
     p = nyx.default_params()
     assert p.gamma == 5.0 / 3.0 and p.eta_dual == 1e-4 and p.riemann_maxiter == 20
     assert p.cfl == 0.5 and p.precision == nyx.NYX_FP64
+    assert p.recon == nyx.NYX_RECON_PPM and p.grav_energy_form == 1
+    assert p.riemann == nyx.NYX_RIEMANN_TWOSHOCK
     L = nyx.lib()
     assert L.nyx_status_string(0) == b"ok"
     assert b"overlap" in L.nyx_status_string(-4)
@@ -93,7 +95,8 @@ def test_argument_errors(nyx):
     b2.comp_stride = 10
     assert _step(nyx, p, b2) == -2
     for field, val in (("gamma", 1.0), ("riemann_maxiter", 0), ("precision", 7), ("cfl", 0.0),
-                       ("small_pres", 0.0), ("riemann", 5)):
+                       ("small_pres", 0.0), ("riemann", 5), ("recon", 2),
+                       ("grav_energy_form", 0), ("grav_energy_form", 3)):
         q = nyx.default_params(**{field: val})
         assert _step(nyx, q, b) == -3, field
 
