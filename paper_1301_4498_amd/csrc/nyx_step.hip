@@ -456,6 +456,7 @@ __device__ __forceinline__ void sample_star(double gam, const double* qL, const 
   o.rsR = rsR;
 }
 
+#if !defined(NYX_PREC_MIXED)
 // Linearised approximate solver (the alternative Sec. 3.2 compares the
 // two-shock solver against): acoustic star state with impedances
 // W_K = sqrt(gamma p_K rho_K), rho*_K = rho_K + (p* - p_K)/c_K^2
@@ -482,6 +483,7 @@ __device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double*
   o.iters = 0;
   return o;
 }
+#endif
 
 #if defined(NYX_PREC_MIXED)
 // FP64 reciprocal and reciprocal square root from the hardware estimates
@@ -596,21 +598,21 @@ __device__ __forceinline__ void sample_side(double gam, double r, double ir, dou
 // star densities from the estimates) and the sample at x/t = 0: only the
 // side the contact moves away from is sampled, both sides (and their mean)
 // when u* = 0.
-__device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShockEval& e,
-                                                double p, const double* qL, const double* qR) {
-  const double ustar = (e.usL * e.zR + e.usR * e.zL) * rcp64(e.zL + e.zR);
-  const double pstar = p;
-  const double irl = rcp_est(t.rl), irr = rcp_est(t.rr);
-  const double DL = irl - (pstar - t.pl) * (e.wL * e.wL);
-  const double DR = irr - (pstar - t.pr) * (e.wR * e.wR);
-  const double rsL = rcp_est(DL), rsR = rcp_est(DR);
+// Sample of a star state (p*, u*, 1/rho*_K = D_K) with the wave data X_K,
+// w_K = X_K^-1/2 of each side: only the side the contact moves away from,
+// both sides (and their mean) when u* = 0.
+__device__ __forceinline__ RiemannOut sample_upwind(const TwoShock& t, double XL, double XR,
+                                                   double wL, double wR, double irl,
+                                                   double irr, double DL, double DR,
+                                                   double rsL, double rsR, double ustar,
+                                                   double pstar, const double* qL,
+                                                   const double* qR) {
   const bool left = !(ustar < 0.0);  // u* > 0 samples the left wave, u* = 0 both
   const double sg = left ? 1.0 : -1.0;
   double s1[3];
   sample_side(t.gam, left ? t.rl : t.rr, left ? irl : irr, sg * (left ? t.ul : t.ur),
-              left ? t.pl : t.pr,
-              left ? e.XL : e.XR, left ? e.wL : e.wR, left ? DL : DR, left ? rsL : rsR,
-              sg * ustar, pstar, s1);
+              left ? t.pl : t.pr, left ? XL : XR, left ? wL : wR, left ? DL : DR,
+              left ? rsL : rsR, sg * ustar, pstar, s1);
   RiemannOut o;
   if (ustar != 0.0) {
     o.r = s1[0]; o.u = sg * s1[1]; o.p = s1[2];
@@ -618,7 +620,7 @@ __device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShoc
     o.w = left ? qL[3] : qR[3];
   } else {
     double s2[3];
-    sample_side(t.gam, t.rr, irr, -t.ur, t.pr, e.XR, e.wR, DR, rsR, -ustar, pstar, s2);
+    sample_side(t.gam, t.rr, irr, -t.ur, t.pr, XR, wR, DR, rsR, -ustar, pstar, s2);
     o.r = 0.5 * (s1[0] + s2[0]);
     o.u = 0.5 * (s1[1] - s2[1]);
     o.p = 0.5 * (s1[2] + s2[2]);
@@ -629,6 +631,39 @@ __device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShoc
   o.ustar = ustar;
   o.rsL = rsL;
   o.rsR = rsR;
+  o.iters = 0;
+  return o;
+}
+
+// star state from the converged pressure p (u* with a refined reciprocal,
+// star densities from the Hugoniot relation with the estimates) and its sample
+__device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShockEval& e,
+                                                double p, const double* qL, const double* qR) {
+  const double ustar = (e.usL * e.zR + e.usR * e.zL) * rcp64(e.zL + e.zR);
+  const double irl = rcp_est(t.rl), irr = rcp_est(t.rr);
+  const double DL = irl - (p - t.pl) * (e.wL * e.wL);
+  const double DR = irr - (p - t.pr) * (e.wR * e.wR);
+  return sample_upwind(t, e.XL, e.XR, e.wL, e.wR, irl, irr, DL, DR, rcp_est(DL), rcp_est(DR),
+                       ustar, p, qL, qR);
+}
+
+// Linearised solver of this build: the acoustic star state (refined
+// reciprocals), linearised star densities rho*_K = rho_K + (p* - p_K) rho_K^2
+// / C_K, and the same upwind sample as the two-shock solver.
+__device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double* qL,
+                                                const double* qR) {
+  const TwoShock t = ts_setup(A, qL, qR);
+  const double W0L = t.CL * rsq64(t.CL), W0R = t.CR * rsq64(t.CR);
+  const double iW = rcp64(W0L + W0R);
+  double p = ((W0R * t.pl + W0L * t.pr) + (W0L * W0R) * (t.ul - t.ur)) * iW;
+  p = vmax(p, t.sp);
+  const double ustar = ((W0L * t.ul + W0R * t.ur) + (t.pl - t.pr)) * iW;
+  const double rsL = t.rl + (p - t.pl) * ((t.rl * t.rl) * rcp_est(t.CL));
+  const double rsR = t.rr + (p - t.pr) * ((t.rr * t.rr) * rcp_est(t.CR));
+  const double XL = t.CL + t.gl * (p - t.pl), XR = t.CR + t.gr * (p - t.pr);
+  RiemannOut o = sample_upwind(t, XL, XR, rsq_est(XL), rsq_est(XR), rcp_est(t.rl),
+                               rcp_est(t.rr), rcp_est(rsL), rcp_est(rsR), rsL, rsR, ustar, p,
+                               qL, qR);
   o.iters = 0;
   return o;
 }
