@@ -26,6 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libnyxoracle.so")
 _SRC = os.path.join(_HERE, "nyx_oracle.c")
 _MLP_SRC = os.path.join(_HERE, "mlp_oracle.c")
+_FILL_SRC = os.path.join(_HERE, "fill_oracle.c")
 
 # Compiler line: plain IEEE FP64, no contraction, no fast-math.
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle shared library with gcc; returns its path."""
     if not force and os.path.exists(_SO):
         return _SO
-    srcs = [_SRC] + ([_MLP_SRC] if os.path.exists(_MLP_SRC) else [])
+    srcs = [_SRC, _MLP_SRC, _FILL_SRC]
     tmp = _SO + ".tmp%d" % os.getpid()
     cmd = ["gcc"] + CFLAGS + ["-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
@@ -113,6 +114,11 @@ def lib():
         L.nyxo_ppm_line.restype = None
         L.nyxo_plm_line.argtypes = [i, _D, _D, _D, _D]
         L.nyxo_plm_line.restype = None
+        _I32 = ctypes.POINTER(ctypes.c_int32)
+        _I64 = ctypes.POINTER(ctypes.c_int64)
+        L.nyxo_fill_level.argtypes = [i, _I32, _I32, _I64, i, _I32, i, _D, i, _I32, _I32, _I64, i,
+                                      _D, _I64, _I64]
+        L.nyxo_fill_level.restype = i
         L.nyxo_ppm_interface.argtypes = [_D]
         L.nyxo_ppm_interface.restype = d
         L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
@@ -281,3 +287,44 @@ def mlp_loss_grad(params, x, y):
     g = np.zeros(params.shape[0])
     loss = lib().nyxo_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _ptr(g))
     return loss, g
+
+
+def fill_level(boxes, ng, dom, datas, coarse=None, ncomp=6):
+    """Ghost fill of one level (fill_oracle.c).  boxes: list of (n, lo) with
+    n = (nx, ny, nz) and lo the global index of valid cell (0, 0, 0); datas:
+    the boxes' padded arrays (ncomp, nz+2ng, ny+2ng, nx+2ng), filled in place
+    (valid cells untouched); dom: the periodic domain (cells).  coarse: None
+    or (cboxes, cng, cdatas) of the level below (ratio 2, ghosts filled).
+    Returns (copied, interpolated) ghost-cell counts; raises if a ghost cell
+    is covered by neither level."""
+    def pack(bxs, arrs):
+        n3 = np.ascontiguousarray([list(n) for n, _ in bxs], dtype=np.int32).ravel()
+        lo3 = np.ascontiguousarray([list(lo) for _, lo in bxs], dtype=np.int32).ravel()
+        sizes = [a.size for a in arrs]
+        off = np.ascontiguousarray(np.cumsum([0] + sizes[:-1]), dtype=np.int64)
+        flat = np.ascontiguousarray(np.concatenate([np.ascontiguousarray(a, np.float64).ravel()
+                                                    for a in arrs]))
+        return n3, lo3, off, flat, sizes
+    n3, lo3, off, flat, sizes = pack(boxes, datas)
+    dom = np.ascontiguousarray(dom, dtype=np.int32)
+    I32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    I64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    ncp, nip = ctypes.c_int64(0), ctypes.c_int64(0)
+    if coarse is not None:
+        cb, cng, cd = coarse
+        cn3, clo3, coff, cflat, _ = pack(cb, cd)
+        args = (len(cb), I32(cn3), I32(clo3), I64(coff), cng, _ptr(cflat))
+    else:
+        args = (0, None, None, None, 1, None)
+    rc = lib().nyxo_fill_level(len(boxes), I32(n3), I32(lo3), I64(off), ng, I32(dom), ncomp,
+                               _ptr(flat), args[0], args[1], args[2], args[3], args[4], args[5],
+                               ctypes.byref(ncp), ctypes.byref(nip))
+    if rc == -2:
+        raise ValueError("a ghost cell is covered by neither level (improper nesting)")
+    if rc != 0:
+        raise ValueError("nyxo_fill_level: bad arguments")
+    pos = 0
+    for a, sz in zip(datas, sizes):
+        a[...] = flat[pos:pos + sz].reshape(a.shape)
+        pos += sz
+    return ncp.value, nip.value

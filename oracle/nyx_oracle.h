@@ -109,6 +109,20 @@ int nyxo_trace_cell(const nyxo_params* prm, int d, const double* qc, double cc,
                     double kh, double hdt_a, double hda_a, double pexp,
                     double* lo, double* hi);
 
+/* Ghost fill of one AMR level (fill_oracle.c; Sec. 4.1, Sec. 4.2): ghost
+ * cells covered by a valid cell of the level are copied; the others take the
+ * limited linear profile of the coarse level (ratio 2) at the fine cell
+ * centre.  n3/lo3: 3 ints per box (valid extents, global index of valid cell
+ * (0,0,0)); off: element offset of each box's padded data (component stride
+ * = its padded cell count); dom: periodic domain in fine cells (even).  The
+ * coarse arrays follow the same conventions (ncoarse = 0: none; the coarse
+ * ghosts must be filled).  Returns 0, -1 (bad arguments), or -2 (a ghost
+ * cell covered by neither level); counts the copied and interpolated cells. */
+int nyxo_fill_level(int nbox, const int32_t* n3, const int32_t* lo3, const int64_t* off, int ng,
+                    const int32_t* dom, int ncomp, double* data, int ncoarse,
+                    const int32_t* cn3, const int32_t* clo3, const int64_t* coff, int cng,
+                    const double* cdata, int64_t* n_copied, int64_t* n_interp);
+
 #ifdef __cplusplus
 }
 #endif
