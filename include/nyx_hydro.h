@@ -239,6 +239,41 @@ int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void*
 int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
                           void* stream);
 
+/* ---------------- ghost fill of an AMR level (Sec. 4.1, Sec. 4.2) ----------------
+ * A level is nbox boxes of one cell size in a periodic domain of dom[3]
+ * cells (host, 3 ints, each even and at least the ghost width).  lo (host,
+ * 3*nbox ints) gives the global index of each box's valid cell (0,0,0); the
+ * boxes' valid regions must not overlap, and all boxes share one ghost
+ * width.  Every ghost cell of every box is filled:
+ *   - from the valid cell of the level that covers it (periodic images
+ *     included), copied bit for bit;
+ *   - otherwise from the level below (refinement ratio 2, domain dom/2;
+ *     cboxes/clo, ncoarse >= 1, its own ghost cells already filled) by the
+ *     limited linear profile of the coarse cell X = floor(x/2) at the fine
+ *     cell centre: per direction the MC-limited centred difference of X and
+ *     its two neighbours, all three slopes scaled by the largest factor in
+ *     [0, 1] that keeps the eight children of X within the minimum and
+ *     maximum over X and its six face neighbours, and the child value
+ *     U(X) + sum_d (-/+ s_d / 4).  The children average to U(X) (the
+ *     interpolation conserves), and create no new extrema.
+ * A ghost cell covered by neither level (improper nesting, or ncoarse = 0)
+ * is a NYX_E_SHAPE error of the plan.  The host plans once per box layout
+ * (nyx_fill_plan_bytes, nyx_fill_plan_create: the plan's tables live in the
+ * caller's device workspace, 256-byte aligned; create synchronises the
+ * stream); nyx_fill_level then enqueues the fill of ncomp components of
+ * the FP64 state (device; each box at its state_off with its comp_stride)
+ * from coarse_state (device, or NULL without a coarse level). */
+typedef struct nyx_fill_plan nyx_fill_plan;
+int nyx_fill_plan_bytes(int nbox, const nyx_box* boxes, const int32_t* lo, const int32_t* dom,
+                        int ncoarse, const nyx_box* cboxes, const int32_t* clo, size_t* bytes);
+int nyx_fill_plan_create(int nbox, const nyx_box* boxes, const int32_t* lo, const int32_t* dom,
+                         int ncoarse, const nyx_box* cboxes, const int32_t* clo, void* workspace,
+                         size_t ws_bytes, void* stream, nyx_fill_plan** plan);
+int nyx_fill_plan_counts(const nyx_fill_plan* plan, long long* copied, long long* interpolated);
+int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_state, int ncomp,
+                   void* stream);
+int nyx_fill_plan_destroy(nyx_fill_plan* plan);
+
 /* ---------------- learned Riemann flux ----------------
  * A small network 10 -> 64 -> 64 -> 64 -> 5 (ReLU) stands in for the
  * iteration of the two-shock Riemann solver (Sec. 3.2 names the solver; the

@@ -17,7 +17,7 @@ from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMAN
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
-           "hydro_step", "fill_ghosts_periodic", "Batch", "stats_dict"]
+           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "stats_dict"]
 
 
 def _ptr(t):
@@ -202,6 +202,59 @@ class Batch:
     def close(self):
         if self.handle is not None and self.handle.value:
             lib().nyx_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FillPlan:
+    """Ghost fill of an AMR level (nyx_fill_plan_*, nyx_fill_level).  boxes:
+    nyx_box list of the level (state offsets and strides into one FP64
+    buffer); lo: per box the global index of valid cell (0, 0, 0); dom: the
+    periodic domain; coarse: None or (cboxes, clo) of the level below."""
+
+    def __init__(self, boxes, lo, dom, coarse=None, stream=None):
+        import torch
+        n = len(boxes)
+        self._boxes = (Box * n)(*boxes)
+        self._lo = (ctypes.c_int * (3 * n))(*[int(v) for b in lo for v in b])
+        self._dom = (ctypes.c_int * 3)(*[int(v) for v in dom])
+        if coarse is not None:
+            cb, clo = coarse
+            self._cb = (Box * len(cb))(*cb)
+            self._clo = (ctypes.c_int * (3 * len(cb)))(*[int(v) for b in clo for v in b])
+            nc = len(cb)
+        else:
+            self._cb, self._clo, nc = None, None, 0
+        nbytes = ctypes.c_size_t(0)
+        check("nyx_fill_plan_bytes", lib().nyx_fill_plan_bytes(
+            n, self._boxes, self._lo, self._dom, nc, self._cb, self._clo, ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nbytes.value]
+        h = ctypes.c_void_p(0)
+        check("nyx_fill_plan_create", lib().nyx_fill_plan_create(
+            n, self._boxes, self._lo, self._dom, nc, self._cb, self._clo,
+            _ptr(self.workspace), nbytes.value, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def counts(self):
+        c, i = ctypes.c_longlong(0), ctypes.c_longlong(0)
+        check("nyx_fill_plan_counts", lib().nyx_fill_plan_counts(self.handle, ctypes.byref(c),
+                                                                 ctypes.byref(i)))
+        return c.value, i.value
+
+    def fill(self, state, coarse_state=None, ncomp=6, stream=None):
+        check("nyx_fill_level", lib().nyx_fill_level(self.handle, _ptr(state), _ptr(coarse_state),
+                                                     int(ncomp), _stream(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().nyx_fill_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
 
     def __del__(self):

@@ -106,6 +106,14 @@ def lib():
             "nyx_batch_autotune": (i, [vp, vp, vp, vp, d, d, vp, vp, i, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i), vp]),
             "nyx_batch_set_tuning": (i, [vp, ctypes.POINTER(i)]),
+            "nyx_fill_plan_bytes": (i, [i, B, ctypes.POINTER(i), ctypes.POINTER(i), i, B,
+                                        ctypes.POINTER(i), ctypes.POINTER(sz)]),
+            "nyx_fill_plan_create": (i, [i, B, ctypes.POINTER(i), ctypes.POINTER(i), i, B,
+                                         ctypes.POINTER(i), vp, sz, vp, ctypes.POINTER(vp)]),
+            "nyx_fill_plan_counts": (i, [vp, ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_longlong)]),
+            "nyx_fill_level": (i, [vp, vp, vp, i, vp]),
+            "nyx_fill_plan_destroy": (i, [vp]),
             "nyx_batch_get_tuning": (i, [vp, ctypes.POINTER(i)]),
         }
         for name, (res, args) in sig.items():
@@ -129,7 +137,8 @@ def exported_symbols():
             "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read",
             "nyx_batch_set_harvest", "nyx_mlp_init", "nyx_mlp_loss_grad", "nyx_mlp_adam",
             "nyx_mlp_pack", "nyx_mlp_predict", "nyx_batch_autotune", "nyx_batch_set_tuning",
-            "nyx_batch_get_tuning"]
+            "nyx_batch_get_tuning", "nyx_fill_plan_bytes", "nyx_fill_plan_create",
+            "nyx_fill_plan_counts", "nyx_fill_level", "nyx_fill_plan_destroy"]
 
 TUNE_CANDIDATES = 16
 MLP_NPARAM = 9349

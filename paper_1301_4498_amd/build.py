@@ -3,6 +3,8 @@
 Translation units:
   nyx_step.hip  twice: FP64 stages (no contraction) and FP32-mixed stages;
   nyx_util.hip  CFL reduction, dt finalisation, ghost fills (no contraction);
+  nyx_fill.hip  ghost fill of an AMR level: planning, copies, coarse-fine
+                interpolation (no contraction);
   nyx_abi.cpp   the C ABI (validation, plans, dispatch).
 """
 from __future__ import annotations
@@ -28,6 +30,7 @@ UNITS = [
                                           "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
     ("nyx_mlp.hip", "nyx_mlp.o", ["-ffp-contract=on"]),
     ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
+    ("nyx_fill.hip", "nyx_fill.o", ["-ffp-contract=off"]),
     ("nyx_abi.cpp", "nyx_abi.o", ["-ffp-contract=off", "-x", "hip"]),
 ]
 
@@ -43,7 +46,7 @@ def _compile(unit):
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=6) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \

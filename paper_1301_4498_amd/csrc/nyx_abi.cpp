@@ -148,6 +148,9 @@ hipError_t run_stages(const nyx_params* p, StepArgs a, hipStream_t s) {
 
 }  // namespace
 
+// shape check of one box, shared with the level-fill planner (nyx_fill.hip)
+int nyx::validate_box(const nyx_box* b) { return check_box(b); }
+
 extern "C" {
 
 void nyx_default_params(nyx_params* p) {

@@ -258,6 +258,9 @@ struct StepArgs {
 };
 
 
+// Shape check of one box (NYX_OK or a negative nyx_status).
+int validate_box(const nyx_box* b);
+
 // The two precision builds of the stage kernels.
 namespace fp64 {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);

@@ -144,3 +144,35 @@ def test_batch_argument_errors(nyx):
     # a workspace smaller than the largest box is rejected before any upload
     assert L.nyx_batch_create(ctypes.byref(p), 2, good, 0x40000000, 4096, None, ctypes.byref(h)) == -7
     assert L.nyx_hydro_step_batched(None, 1, 1, 1, 0.5, 0.5, 2, None, None, None) == -1
+
+
+def test_level_fill_planning_errors(nyx):
+    # planning is host work: valid layouts plan, bad ones are refused
+    L = nyx.lib()
+    I = ctypes.c_int
+    def plan(layout, dom, coarse=None):
+        boxes = (nyx.Box * len(layout))(*[nyx.make_box(n, 4, 1.0) for n, _ in layout])
+        lo = (I * (3 * len(layout)))(*[v for _, l in layout for v in l])
+        d = (I * 3)(*dom)
+        nb = ctypes.c_size_t(0)
+        if coarse:
+            cb = (nyx.Box * len(coarse))(*[nyx.make_box(n, 4, 2.0) for n, _ in coarse])
+            clo = (I * (3 * len(coarse)))(*[v for _, l in coarse for v in l])
+            return L.nyx_fill_plan_bytes(len(layout), boxes, lo, d, len(coarse), cb, clo,
+                                         ctypes.byref(nb)), nb.value
+        return L.nyx_fill_plan_bytes(len(layout), boxes, lo, d, 0, None, None, ctypes.byref(nb)), nb.value
+    rc, nb = plan([((8, 8, 8), (0, 0, 0)), ((8, 8, 8), (8, 0, 0))], (16, 8, 8))
+    assert rc == 0 and nb > 0
+    # overlapping valid regions
+    assert plan([((8, 8, 8), (0, 0, 0)), ((8, 8, 8), (4, 0, 0))], (16, 8, 8))[0] == -2
+    # a box outside the domain
+    assert plan([((8, 8, 8), (12, 0, 0))], (16, 8, 8))[0] == -2
+    # open ghost cells without a coarse level (improper nesting)
+    assert plan([((8, 8, 8), (4, 4, 4))], (24, 24, 24))[0] == -2
+    # with a coarse level covering them it plans
+    assert plan([((8, 8, 8), (4, 4, 4))], (24, 24, 24), coarse=[((12, 12, 12), (0, 0, 0))])[0] == 0
+    # a coarse level with a hole under the fine box's ghost cells
+    assert plan([((8, 8, 8), (4, 4, 4))], (24, 24, 24),
+                coarse=[((6, 12, 12), (6, 0, 0))])[0] == -2
+    # an odd domain
+    assert plan([((8, 8, 8), (0, 0, 0))], (9, 8, 8))[0] == -2
