@@ -22,6 +22,9 @@ Variants leg: PLM reconstruction, the linearised Riemann solver and the
 second form of the energy gravity term (Sec. 3.2) on the same box, each in
 FP32-mixed against its own plain FP64 run.
 
+Level-fill leg: the ghost fill of AMR levels (same-level copies, and
+coarse-fine interpolation from a coarser level), rated in algorithmic GB/s.
+
 Stress leg (box512_stress): a 512^3 domain with density contrast up to 10^4
 and flows up to Mach 30, plain FP64 as one box against FP32-mixed (and the
 learned flux, trained on smooth flows or on stress faces) on an 8^3 grid of
@@ -415,6 +418,71 @@ def variants_leg(nyx, torch, w, steps, warmup, log):
     return out
 
 
+def level_fill_leg(nyx, torch, log, reps=5):
+    """Ghost fill of AMR levels (Sec. 4.1-4.2): (a) 512 patches of 64^3 tiling
+    a periodic 512^3 domain, every ghost cell a copy; (b) a fine level of 8
+    boxes of 64^3 over the central 128^3 of a 512^3 domain above a coarse
+    level of 64 boxes of 64^3 (ratio 2): copies between the fine boxes and
+    limited linear interpolation from the coarse level on the outer faces.
+    Algorithmic bytes: a copied cell reads and writes 6 FP64 components; an
+    interpolated cell writes 6 and reads the coarse cell's 6 once per 8
+    children."""
+    m, ng = 64, 4
+    P = (m + 2 * ng) ** 3
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def grid_boxes(g, dx, lo0=(0, 0, 0)):
+        boxes, lo = [], []
+        for b in range(g[0] * g[1] * g[2]):
+            boxes.append(nyx.make_box((m, m, m), ng, dx, state_off=6 * P * b))
+            ijk = (b % g[0], (b // g[0]) % g[1], b // (g[0] * g[1]))
+            lo.append(tuple(lo0[d] + m * ijk[d] for d in range(3)))
+        return boxes, lo
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # (a) copies only
+    boxes, lo = grid_boxes((8, 8, 8), 1.0 / 512)
+    state = torch.rand(512 * 6 * P, dtype=torch.float64, device="cuda")
+    plan = nyx.FillPlan(boxes, lo, (512, 512, 512))
+    nc, ni = plan.counts()
+    ms = timed(lambda: plan.fill(state))
+    gbs = nc * 96 / (ms * 1e-3) / 1e9
+    out["patch_grid_512"] = {"copied_cells": nc, "ms": ms, "gbs": gbs,
+                             "hbm_frac": gbs / HBM_PEAK_GBS}
+    log("level fill, 512 x 64^3 patches: %.3f ms, %.0f GB/s" % (ms, gbs))
+    plan.close()
+    del state, plan
+    torch.cuda.empty_cache()
+    # (b) two levels
+    cboxes, clo = grid_boxes((4, 4, 4), 1.0 / 256)
+    cstate = torch.rand(64 * 6 * P, dtype=torch.float64, device="cuda")
+    cplan = nyx.FillPlan(cboxes, clo, (256, 256, 256))
+    cplan.fill(cstate)
+    fboxes, flo = grid_boxes((2, 2, 2), 1.0 / 512, lo0=(192, 192, 192))
+    fstate = torch.rand(8 * 6 * P, dtype=torch.float64, device="cuda")
+    fplan = nyx.FillPlan(fboxes, flo, (512, 512, 512), coarse=(cboxes, clo))
+    nc, ni = fplan.counts()
+    ms = timed(lambda: fplan.fill(fstate, cstate))
+    gbs = (nc * 96 + ni * (48 + 6)) / (ms * 1e-3) / 1e9
+    out["two_level"] = {"copied_cells": nc, "interpolated_cells": ni, "ms": ms, "gbs": gbs,
+                        "hbm_frac": gbs / HBM_PEAK_GBS}
+    log("level fill, 8 fine boxes over 64 coarse boxes: %d copied, %d interpolated, %.3f ms, "
+        "%.0f GB/s" % (nc, ni, ms, gbs))
+    cplan.close()
+    fplan.close()
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
     import oracle
@@ -448,6 +516,7 @@ def main():
     ap.add_argument("--no-stress", action="store_true", help="skip the 512^3 stress leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the PLM / linearised-solver / gravity-form-2 leg")
+    ap.add_argument("--no-fill", action="store_true", help="skip the level ghost-fill leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -566,6 +635,8 @@ def main():
         out["level4096"] = level_leg(nyx, torch, synth, max(args.steps // 2 * 2, 2), log)
     if not args.no_variants:
         out["variants"] = variants_leg(nyx, torch, w, args.steps, args.warmup, log)
+    if not args.no_fill:
+        out["level_fill"] = level_fill_leg(nyx, torch, log)
     if not args.no_stress:
         out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
                                           flux, 10, log)

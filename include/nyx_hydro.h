@@ -262,7 +262,8 @@ int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, dou
  * caller's device workspace, 256-byte aligned; create synchronises the
  * stream); nyx_fill_level then enqueues the fill of ncomp components of
  * the FP64 state (device; each box at its state_off with its comp_stride)
- * from coarse_state (device, or NULL without a coarse level). */
+ * from coarse_state (device, or NULL without a coarse level; it must not
+ * overlap the fine state). */
 typedef struct nyx_fill_plan nyx_fill_plan;
 int nyx_fill_plan_bytes(int nbox, const nyx_box* boxes, const int32_t* lo, const int32_t* dom,
                         int ncoarse, const nyx_box* cboxes, const int32_t* clo, size_t* bytes);

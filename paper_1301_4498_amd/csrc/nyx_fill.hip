@@ -116,8 +116,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_interp(FillArgs A) {
   const unsigned di = fill_pidx(D, loc[0], loc[1], loc[2]);
   const unsigned c0 = fill_pidx(C, X[0], X[1], X[2]);
   const unsigned st[3] = {1u, (unsigned)C.px, (unsigned)C.px * (unsigned)C.py};
+  // the coarse level is read-only here and lives apart from the fine state
+  const double* __restrict__ cs = A.cstate;
+  double* __restrict__ fs = A.state;
   for (int c = 0; c < A.ncomp; ++c) {
-    const double* u = A.cstate + C.soff + (long long)c * C.sstride;
+    const double* u = cs + C.soff + (long long)c * C.sstride;
     const double u0 = ldu(u, c0);
     double s[3], lo = u0, hi = u0;
     for (int d = 0; d < 3; ++d) {
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_interp(FillArgs A) {
     }
     double v = 0.0;
     for (int d = 0; d < 3; ++d) v = v + (par[d] ? 0.25 : -0.25) * s[d];
-    stu(A.state + D.soff + (long long)c * D.sstride, di, u0 + alpha * v);
+    stu(fs + D.soff + (long long)c * D.sstride, di, u0 + alpha * v);
   }
 }
 
