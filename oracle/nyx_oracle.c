@@ -7,8 +7,9 @@
  * What it computes (Almgren et al., "Nyx"):
  *   - state U = (rho, a rho U, a^2 rho E, a^2 rho e) and the flux, S_e and S_g
  *     terms of Sec. 3.2 Gas Dynamics (eqs. for U, F, S_e, S_g);
- *   - the comoving Euler equations of Sec. 2.2 with gamma = 5/3, so the
- *     a*adot*(2 - 3(gamma-1)) rho e expansion term vanishes;
+ *   - the comoving Euler equations of Sec. 2.2; the a*adot*(2 - 3(gamma-1))
+ *     rho e expansion term of the two energy equations vanishes at gamma = 5/3
+ *     and is applied, predictor-corrector like S_g, for any other gamma;
  *   - an unsplit Godunov method with characteristic tracing and full corner
  *     coupling, PPM edge states, a reference state built from the fastest
  *     wave moving toward the interface, and an iterative two-shock Riemann
@@ -541,6 +542,13 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
   const double kap1 = kh / 3.0;
   const double kap2 = kh / 2.0;
   const double k = dt / dx;
+  /* expansion source of both energy equations (Sec. 2.2): a adot (2 - 3(gamma-1))
+   * rho e = (adot / a) cgam U_e in the stored variables; with adot dt = da the
+   * step's integral is cgam (da / a) U_e evaluated at a_old (predictor) and at
+   * a_new (corrector) */
+  const double cgam = 2.0 - 3.0 * gm1;
+  const double xo = cgam * (da / a_old);
+  const double xn = cgam * (da / a_new);
 
   double* prim = (double*)malloc(sizeof(double) * 6 * P);
   double* chi = (double*)malloc(sizeof(double) * E);
@@ -777,6 +785,10 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
           sE = (UE - k * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
         }
         double se = (Ue - k * D[5]) - (k * a_h) * Pi;
+        if (cgam != 0.0) {
+          sE = sE + xo * Ue;
+          se = se + xo * Ue;
+        }
         /* corrector (Step 6) with the same g */
         double nm[3];
         for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
@@ -788,6 +800,12 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
                                   (sm[2] - Um[2]) * g[2]);
         }
         double ne = se;
+        if (cgam != 0.0) {
+          /* time-centre the expansion source: + (S* - S^n) dt / 2 */
+          const double cx = 0.5 * (xn * se - xo * Ue);
+          nE = nE + cx;
+          ne = ne + cx;
+        }
         /* dual-energy sync (Step 6) */
         double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;
         if (nE - ke > prm->eta * nE) {

@@ -32,7 +32,8 @@ extern "C" {
 #define NYXO_RIEMANN_LINEAR 1   /* linearised (acoustic) approximate solver */
 
 typedef struct {
-  double gamma;        /* gamma-law EOS exponent (Sec. 2.2: 5/3) */
+  double gamma;        /* gamma-law EOS exponent (Sec. 2.2: 5/3); any other value
+                        * turns on the expansion term of the energy equations */
   double eta;          /* dual-energy threshold (Sec. 3.6, Step 6: 1e-4) */
   double small_dens;   /* density floor, primitives and edge states only */
   double small_pres;   /* pressure floor, primitives, edge states, Riemann */
