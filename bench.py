@@ -400,12 +400,14 @@ def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
 def variants_leg(nyx, torch, w, steps, warmup, log):
     """The scheme variants of Sec. 3.2 on the benchmark box (FP32-mixed, each
     against its own plain FP64 run): PLM reconstruction, the linearised
-    Riemann solver, the second form of the energy gravity term."""
+    Riemann solver, the second form of the energy gravity term, and gamma =
+    1.4, where the expansion term of the energy equations is applied."""
     import numpy as np
     out = {}
     for name, kw in (("plm", dict(recon=nyx.NYX_RECON_PLM)),
                      ("linearized_riemann", dict(riemann=nyx.NYX_RIEMANN_LINEARIZED)),
-                     ("gravity_energy_form2", dict(grav_energy_form=2))):
+                     ("gravity_energy_form2", dict(grav_energy_form=2)),
+                     ("gamma14_expansion", dict(gamma=1.4))):
         m = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_MIXED, **kw), steps, warmup)
         f = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_FP64, **kw), steps, warmup)
         l1 = float(np.abs(m["rho"] - f["rho"]).sum() / np.abs(f["rho"]).sum())

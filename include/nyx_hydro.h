@@ -78,7 +78,10 @@ typedef enum {
 typedef enum { NYX_RECON_PPM = 0, NYX_RECON_PLM = 1 } nyx_recon;
 
 typedef struct {
-  double gamma;          /* gamma-law exponent, > 1 (Sec. 2.2: 5/3) */
+  double gamma;          /* gamma-law exponent, > 1 (Sec. 2.2: 5/3).  For any
+                          * other value the a adot (2 - 3(gamma-1)) rho e term of
+                          * both energy equations (Sec. 2.2) is applied, at a_old
+                          * in the predictor and time-centred by the corrector */
   double eta_dual;       /* dual-energy threshold (Sec. 3.6 Step 6: 1e-4) */
   double small_dens;     /* density floor of primitives and edge states */
   double small_pres;     /* pressure floor of primitives, edge states, Riemann */

@@ -108,6 +108,9 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   a.recon = p->recon;
   a.grav_form = p->grav_energy_form;
   a.linear_riemann = p->riemann == NYX_RIEMANN_LINEARIZED ? 1 : 0;
+  // the expansion term's coefficient 2 - 3(gamma-1) is exactly 0.0 in FP64
+  // for gamma = 5/3; the term is then skipped
+  a.expansion = (2.0 - 3.0 * (p->gamma - 1.0)) != 0.0 ? 1 : 0;
 }
 
 // ---- stage timing ----

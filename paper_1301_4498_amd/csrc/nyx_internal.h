@@ -103,6 +103,7 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
 // kernel (the same expressions the oracle evaluates on the host).
 struct StepC {
   double dt, a_h, da, kh, hdt_a, hda_a, pexp, kap1, kap2, k, gm1;
+  double xo, xn;  // expansion source of the energy equations at a_old / a_new
   double pad_;
 };
 
@@ -255,6 +256,7 @@ struct StepArgs {
   int recon;               // NYX_RECON_PPM or NYX_RECON_PLM
   int grav_form;           // energy gravity term, 1 or 2
   int linear_riemann;      // 1: linearised solver instead of the two-shock one
+  int expansion;           // 1: gamma != 5/3, apply the a adot (2 - 3(gamma-1)) rho e term
 };
 
 

@@ -1298,7 +1298,12 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     } else {
       sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
     }
-    const double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
+    double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
+    if (A.expansion) {
+      // expansion source of both energy equations (Sec. 2.2), predictor part
+      sE = sE + C.xo * Ue;
+      se = se + C.xo * Ue;
+    }
     // corrector (Step 6), same g
     double nm[3];
     for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
@@ -1310,6 +1315,12 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
                               (sm[2] - Um[2]) * g[2]);
     }
     double ne = se;
+    if (A.expansion) {
+      // time-centred expansion source: + (S* - S^n) dt / 2
+      const double cx = 0.5 * (C.xn * se - C.xo * Ue);
+      nE = nE + cx;
+      ne = ne + cx;
+    }
     // dual-energy sync (Step 6)
 #if defined(NYX_PREC_MIXED)
     const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) * rcp64(s0);

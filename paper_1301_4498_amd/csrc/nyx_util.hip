@@ -115,6 +115,11 @@ __global__ void k_prologue(StepArgs A, int nbox, StepC* consts, BoxDev* single_d
   c.kap1 = c.kh / 3.0;
   c.kap2 = c.kh / 2.0;
   c.k = c.dt / b.dx;
+  // a adot (2 - 3(gamma-1)) rho e = (adot / a) cgam U_e; integrated over the
+  // step at a_old (predictor) and a_new (corrector)
+  const double cgam = 2.0 - 3.0 * c.gm1;
+  c.xo = cgam * (c.da / A.a_old);
+  c.xn = cgam * (c.da / A.a_new);
   c.pad_ = 0.0;
   consts[b.gidx] = c;
 }

@@ -1,6 +1,7 @@
 """The scheme variants of Sec. 3.2 through the C ABI against the oracle:
 PLM reconstruction, the linearised approximate Riemann solver, the second
-form of the energy gravity term, and all three together.  FP64: bitwise
+form of the energy gravity term, all three together, and gamma = 1.4 with the
+expansion term of the energy equations (Sec. 2.2).  FP64: bitwise
 equal to the oracle (same expression trees, no contraction), with equal
 counters and next dt; FP32-mixed: within 1e-5 relative L1; batched plans
 give the same bits as the single-box path."""
@@ -19,6 +20,7 @@ VARIANTS = {
     "gravity_form2": (dict(grav_form=2), dict(grav_energy_form=2)),
     "all_three": (dict(recon=oracle.RECON_PLM, riemann=oracle.RIEMANN_LINEAR, grav_form=2),
                   dict(recon=1, riemann=2, grav_energy_form=2)),
+    "gamma14_expansion": (dict(gamma=1.4), dict(gamma=1.4)),
 }
 
 
