@@ -27,6 +27,7 @@ _SO = os.path.join(_HERE, "libnyxoracle.so")
 _SRC = os.path.join(_HERE, "nyx_oracle.c")
 _MLP_SRC = os.path.join(_HERE, "mlp_oracle.c")
 _FILL_SRC = os.path.join(_HERE, "fill_oracle.c")
+_SYNC_SRC = os.path.join(_HERE, "sync_oracle.c")
 
 # Compiler line: plain IEEE FP64, no contraction, no fast-math.
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
@@ -36,7 +37,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle shared library with gcc; returns its path."""
     if not force and os.path.exists(_SO):
         return _SO
-    srcs = [_SRC, _MLP_SRC, _FILL_SRC]
+    srcs = [_SRC, _MLP_SRC, _FILL_SRC, _SYNC_SRC]
     tmp = _SO + ".tmp%d" % os.getpid()
     cmd = ["gcc"] + CFLAGS + ["-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
@@ -119,6 +120,13 @@ def lib():
         L.nyxo_fill_level.argtypes = [i, _I32, _I32, _I64, i, _I32, i, _D, i, _I32, _I32, _I64, i,
                                       _D, _I64, _I64]
         L.nyxo_fill_level.restype = i
+        L.nyxo_hydro_step_faces.argtypes = [P, i, i, i, i, _D, _D, d, d, d, d, _D,
+                                            ctypes.POINTER(_Stats), _D]
+        L.nyxo_hydro_step_faces.restype = i
+        L.nyxo_reflux_average_down.argtypes = [i, _I32, _I32, _I64, i, d, _D, _D, _I64, d,
+                                               i, _I32, _I32, _I64, i, _I32, _D, i, _D, _I64,
+                                               ctypes.c_int64, _D, i, _I64, _I64]
+        L.nyxo_reflux_average_down.restype = i
         L.nyxo_ppm_interface.argtypes = [_D]
         L.nyxo_ppm_interface.restype = d
         L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
@@ -164,11 +172,31 @@ def estimate_dt(state: np.ndarray, ng: int, a: float, dx: float, cfl: float,
     return out.value
 
 
+def face_flux_size(n) -> int:
+    """Doubles in one box's face-flux block (layout of nyxo_hydro_step_faces)."""
+    nx, ny, nz = n
+    return 6 * ((nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1))
+
+
+def face_flux_views(flux: np.ndarray, n):
+    """Split a face-flux block into three arrays (6, nz', ny', nx') per direction."""
+    nx, ny, nz = n
+    out, pos = [], 0
+    for d in range(3):
+        shp = (6, nz + (d == 2), ny + (d == 1), nx + (d == 0))
+        sz = int(np.prod(shp))
+        out.append(flux[pos:pos + sz].reshape(shp))
+        pos += sz
+    return out
+
+
 def hydro_step(state: np.ndarray, grav: np.ndarray, ng: int, dt: float,
                dx: float, a_old: float, a_new: float,
-               params: Params | None = None):
-    """One gas step.  Returns (new_state, stats dict).  Ghost cells of the
-    returned array are copies of the input's (stale); refill before reuse."""
+               params: Params | None = None, faces: bool = False):
+    """One gas step.  Returns (new_state, stats dict), plus the final face
+    fluxes (flat block, see face_flux_views) when faces is set.  Ghost cells
+    of the returned array are copies of the input's (stale); refill before
+    reuse."""
     params = params or Params()
     state = np.ascontiguousarray(state, dtype=np.float64)
     grav = np.ascontiguousarray(grav, dtype=np.float64)
@@ -176,12 +204,15 @@ def hydro_step(state: np.ndarray, grav: np.ndarray, ng: int, dt: float,
     nx, ny, nz = _dims(state, ng)
     out = state.copy()
     st = _Stats()
-    rc = lib().nyxo_hydro_step(ctypes.byref(params.c()), nx, ny, nz, ng,
-                               _ptr(state), _ptr(grav), dt, dx, a_old, a_new,
-                               _ptr(out), ctypes.byref(st))
+    flux = np.zeros(face_flux_size((nx, ny, nz))) if faces else None
+    rc = lib().nyxo_hydro_step_faces(ctypes.byref(params.c()), nx, ny, nz, ng,
+                                     _ptr(state), _ptr(grav), dt, dx, a_old, a_new,
+                                     _ptr(out), ctypes.byref(st),
+                                     _ptr(flux) if faces else None)
     if rc != 0:
         raise ValueError("nyxo_hydro_step: bad arguments")
-    return out, {k: int(getattr(st, k)) for k in STATS_FIELDS}
+    stats = {k: int(getattr(st, k)) for k in STATS_FIELDS}
+    return (out, stats, flux) if faces else (out, stats)
 
 
 def riemann(qL, qR, params: Params | None = None):
@@ -328,3 +359,56 @@ def fill_level(boxes, ng, dom, datas, coarse=None, ncomp=6):
         a[...] = flat[pos:pos + sz].reshape(a.shape)
         pos += sz
     return ncp.value, nip.value
+
+
+def reflux_average_down(cboxes, cng, cdx, cdatas, cfluxes, dt_c, fboxes, fng, dom, fdatas,
+                        ffluxes, dt_f, ncomp=6):
+    """Reflux and average-down of two levels (sync_oracle.c).  cboxes/fboxes:
+    lists of (n, lo); cdatas: the coarse boxes' padded arrays, updated in
+    place; cfluxes: per coarse box its step's face-flux block over dt_c;
+    fdatas: the fine boxes' padded arrays after their substeps; ffluxes[s][b]:
+    face-flux block of fine box b in substep s, over dt_f[s]; dom: the fine
+    level's periodic domain.  Returns (interface faces, covered cells);
+    raises on improper nesting."""
+    I32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    I64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def geom(bxs, arrs):
+        n3 = np.ascontiguousarray([list(n) for n, _ in bxs], dtype=np.int32).ravel()
+        lo3 = np.ascontiguousarray([list(lo) for _, lo in bxs], dtype=np.int32).ravel()
+        sizes = [a.size for a in arrs]
+        off = np.ascontiguousarray(np.cumsum([0] + sizes[:-1]), dtype=np.int64)
+        flat = np.ascontiguousarray(np.concatenate([np.ascontiguousarray(a, np.float64).ravel()
+                                                    for a in arrs]))
+        return n3, lo3, off, flat, sizes
+
+    def fluxcat(blocks):
+        off = np.ascontiguousarray(np.cumsum([0] + [b.size for b in blocks[:-1]]), dtype=np.int64)
+        return np.ascontiguousarray(np.concatenate(blocks), dtype=np.float64), off
+
+    cn3, clo3, coff, cflat, csizes = geom(cboxes, cdatas)
+    fn3, flo3, foff, fflat, _ = geom(fboxes, fdatas)
+    cfl, cfl_off = fluxcat(list(cfluxes))
+    subs = [fluxcat(list(f)) for f in ffluxes]
+    stride = subs[0][0].size
+    assert all(x[0].size == stride for x in subs)
+    ffl = np.ascontiguousarray(np.concatenate([x[0] for x in subs]))
+    ffl_off = subs[0][1]
+    dtf = np.ascontiguousarray(dt_f, dtype=np.float64)
+    dom = np.ascontiguousarray(dom, dtype=np.int32)
+    nf, nc = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib().nyxo_reflux_average_down(
+        len(cboxes), I32(cn3), I32(clo3), I64(coff), cng, cdx, _ptr(cflat), _ptr(cfl),
+        I64(cfl_off), dt_c, len(fboxes), I32(fn3), I32(flo3), I64(foff), fng, I32(dom),
+        _ptr(fflat), len(subs), _ptr(ffl), I64(ffl_off), stride, _ptr(dtf), ncomp,
+        ctypes.byref(nf), ctypes.byref(nc))
+    if rc == -2:
+        raise ValueError("improper nesting: a covered cell or its uncovered neighbour has no "
+                         "coarse box")
+    if rc != 0:
+        raise ValueError("nyxo_reflux_average_down: bad arguments")
+    pos = 0
+    for a, sz in zip(cdatas, csizes):
+        a[...] = cflat[pos:pos + sz].reshape(a.shape)
+        pos += sz
+    return nf.value, nc.value

@@ -1,7 +1,7 @@
 /*
  * fill_oracle.c -- FP64 CPU reference of the ghost-cell fill of one AMR
  * level (Sec. 4.1 Mesh Hierarchy: each grid carries ghost cells that hold
- * data for the update of its valid cells; Sec. 4.2 regridding: data in newly
+ * data for the update of its valid cells; its regrid procedure: data in newly
  * refined regions are interpolated from the coarser level with limited
  * piecewise linear profiles whose values at the fine cell centres conserve
  * the coarse averages).  TEST INFRASTRUCTURE ONLY; shares no code with the

@@ -516,6 +516,14 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
                     const double* Uin, const double* grav, double dt,
                     double dx, double a_old, double a_new, double* Uout,
                     nyxo_stats* stats) {
+  return nyxo_hydro_step_faces(prm, nx, ny, nz, ng, Uin, grav, dt, dx, a_old, a_new, Uout,
+                               stats, NULL);
+}
+
+int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                          const double* Uin, const double* grav, double dt,
+                          double dx, double a_old, double a_new, double* Uout,
+                          nyxo_stats* stats, double* face_flux) {
   if (!prm || !Uin || !grav || !Uout || nx < 1 || ny < 1 || nz < 1 || ng < 4 ||
       !(dt > 0.0) || !(a_old > 0.0) || !(a_new > 0.0) || !(dx > 0.0))
     return -1;
@@ -744,6 +752,18 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
           long eR = eid(&b, cR[0], cR[1], cR[2]);
           for (int v = 0; v < NF; ++v) FL2(d, v, eR) = f[v];
         }
+  }
+
+  /* the final comoving fluxes of every face, for flux registers */
+  if (face_flux) {
+    double* o = face_flux;
+    for (int d = 0; d < 3; ++d) {
+      const int fe[3] = {n[0] + (d == 0), n[1] + (d == 1), n[2] + (d == 2)};
+      for (int c = 0; c < 6; ++c)
+        for (int kk = 0; kk < fe[2]; ++kk)
+          for (int j = 0; j < fe[1]; ++j)
+            for (int i = 0; i < fe[0]; ++i) *o++ = FL2(d, c, eid(&b, i, j, kk));
+    }
   }
 
   /* ---- O10-O12: update, gravity corrector, dual-energy sync ---- */

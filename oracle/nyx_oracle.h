@@ -72,6 +72,45 @@ int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
                     double dx, double a_old, double a_new, double* state_out,
                     nyxo_stats* stats);
 
+/* The same step; face_flux (or NULL) also receives the final comoving fluxes
+ * F = (f_rho / a_h, f_m, a_h f_E, a_h f_e) of every face of the box (Sec. 3.2
+ * flux vector), the values the update differences: for d = 0, 1, 2 in turn a
+ * block of 6 components, each (nz + [d==2]) x (ny + [d==1]) x (nx + [d==0])
+ * faces, x fastest; face index f along d is the low face of cell f. */
+int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                          const double* state_in, const double* grav, double dt,
+                          double dx, double a_old, double a_new, double* state_out,
+                          nyxo_stats* stats, double* face_flux);
+
+/* Synchronisation of two levels after the fine level's substeps (Sec. 4.3,
+ * Steps 2 and 8): explicit reflux of the coarse cells next to the fine
+ * level's boundary, then average-down of the covered coarse cells.
+ * Coarse level: ncoarse boxes (cn3, clo3, coff, cng as in nyxo_fill_level),
+ * cell size cdx, its step's face fluxes cflux (per box at cflux_off[b], the
+ * layout of nyxo_hydro_step_faces) over dt_c.  Fine level (ratio 2, domain
+ * dom, coarse domain dom/2): nfine boxes whose lo and n are even, data fdata
+ * after its nsub substeps, whose face fluxes are fflux + s * fflux_sub_stride
+ * (per box at fflux_off[b]) over dt_f[s].
+ * A coarse cell is covered when its eight children lie in a fine box.  For
+ * every valid coarse cell A that is not covered and each of its faces (x-,
+ * x+, y-, y+, z-, z+ in that order) whose other side B is covered (periodic
+ * images included):
+ *   R = -dt_c F_c + sum_s (dt_f[s] / 4) (sum of the four fine faces' F)
+ * with F_c the face's flux in A's own box; then A += (sum over its faces of
+ * -/+ R) / cdx, the sign + when the face is A's low face.  Then every
+ * covered coarse cell becomes the mean of its eight children.  ncomp
+ * components.  Returns 0, -1 on bad arguments, -2 when a covered cell or an
+ * uncovered neighbour of one lies in no coarse box. */
+int nyxo_reflux_average_down(int ncoarse, const int32_t* cn3, const int32_t* clo3,
+                             const int64_t* coff, int cng, double cdx, double* cdata,
+                             const double* cflux, const int64_t* cflux_off, double dt_c,
+                             int nfine, const int32_t* fn3, const int32_t* flo3,
+                             const int64_t* foff, int fng, const int32_t* dom,
+                             const double* fdata, int nsub, const double* fflux,
+                             const int64_t* fflux_off, int64_t fflux_sub_stride,
+                             const double* dt_f, int ncomp, int64_t* n_faces,
+                             int64_t* n_covered);
+
 /* ---- unit-level entry points used by the oracle's own pins ---- */
 
 /* Two-shock Riemann solve on rotated primitive states (rho, u_n, u_t1, u_t2, p).
@@ -110,7 +149,7 @@ int nyxo_trace_cell(const nyxo_params* prm, int d, const double* qc, double cc,
                     double kh, double hdt_a, double hda_a, double pexp,
                     double* lo, double* hi);
 
-/* Ghost fill of one AMR level (fill_oracle.c; Sec. 4.1, Sec. 4.2): ghost
+/* Ghost fill of one AMR level (fill_oracle.c; Sec. 4.1, ghost cells and regridding): ghost
  * cells covered by a valid cell of the level are copied; the others take the
  * limited linear profile of the coarse level (ratio 2) at the fine cell
  * centre.  n3/lo3: 3 ints per box (valid extents, global index of valid cell

@@ -1,4 +1,4 @@
-"""Pins of the oracle's level ghost fill (Sec. 4.1 ghost cells, Sec. 4.2
+"""Pins of the oracle's level ghost fill (Sec. 4.1: ghost cells, and the
 conservative limited piecewise-linear interpolation from the coarser level),
 no GPU: same-level copies reproduce the periodic padding of the domain; the
 interpolation is exact for linear data, conserves every coarse cell's
