@@ -421,7 +421,7 @@ def variants_leg(nyx, torch, w, steps, warmup, log):
 
 
 def level_fill_leg(nyx, torch, log, reps=5):
-    """Ghost fill of AMR levels (Sec. 4.1-4.2): (a) 512 patches of 64^3 tiling
+    """Ghost fill of AMR levels (Sec. 4.1): (a) 512 patches of 64^3 tiling
     a periodic 512^3 domain, every ghost cell a copy; (b) a fine level of 8
     boxes of 64^3 over the central 128^3 of a 512^3 domain above a coarse
     level of 64 boxes of 64^3 (ratio 2): copies between the fine boxes and

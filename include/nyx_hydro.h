@@ -242,7 +242,7 @@ int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void*
 int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
                           void* stream);
 
-/* ---------------- ghost fill of an AMR level (Sec. 4.1, Sec. 4.2) ----------------
+/* ---------------- ghost fill of an AMR level (Sec. 4.1) ----------------
  * A level is nbox boxes of one cell size in a periodic domain of dom[3]
  * cells (host, 3 ints, each even and at least the ghost width).  lo (host,
  * 3*nbox ints) gives the global index of each box's valid cell (0,0,0); the

@@ -1,6 +1,6 @@
 // nyx_fill.hip -- ghost fill of one AMR level (Sec. 4.1 Mesh Hierarchy:
-// ghost cells hold data for the update of a grid's valid cells; Sec. 4.2
-// regridding: data not covered by the level come from the coarser level
+// ghost cells hold data for the update of a grid's valid cells; the regrid
+// procedure of the same section: data not covered by the level come from the coarser level
 // through limited piecewise linear profiles whose values at the fine cell
 // centres conserve the coarse averages).
 //
