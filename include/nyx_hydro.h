@@ -278,6 +278,59 @@ int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_stat
                    void* stream);
 int nyx_fill_plan_destroy(nyx_fill_plan* plan);
 
+/* ---------------- two-level synchronisation (Sec. 4.3) ----------------
+ * After a coarse level has taken a step and the fine level above it
+ * (refinement ratio 2) its substeps, the multilevel algorithm (Sec. 4.3,
+ * Steps 2 and 8) refluxes the coarse cells next to the fine level, so that
+ * the composite solution conserves what the fine fluxes moved, and then
+ * averages the fine solution down onto the coarse cells it covers.
+ *
+ * Geometry: the fine level is nfine boxes (lo: global index of valid cell
+ * (0,0,0), 3 ints per box; lo and n even) in a periodic domain of dom
+ * cells (even); the coarse level is ncoarse boxes in the domain dom / 2.
+ * Boxes lie inside their domain and do not overlap within a level.  A coarse
+ * cell is covered when its eight children lie in a fine box.  Every
+ * uncovered face neighbour of a covered cell must lie in a coarse box
+ * (proper nesting), else NYX_E_SHAPE.
+ *
+ * Flux register: one slot per interface face (a coarse face with exactly
+ * one covered side, periodic images included), 6 FP64 components stored
+ * component-major: reg[c * faces + slot] (device, caller-zeroed before the
+ * coarse step).  nyx_batch_set_flux_register attaches it to a batch plan
+ * whose boxes are the sync plan's coarse boxes (level 0) or fine boxes
+ * (level 1), in the same order and shapes; every later
+ * nyx_hydro_step_batched of that plan then adds, per interface face, its
+ * final comoving flux F (Sec. 3.2 flux vector) times -dt (level 0: the
+ * face's flux in the box of the uncovered cell) or times dt / 4 summed over
+ * the four fine faces (level 1), so that after one coarse step and the fine
+ * substeps reg = sum_s dt_s <F_fine> - dt_c F_coarse.  reg = NULL detaches
+ * it.  nyx_batch_autotune does not feed the register.
+ *
+ * nyx_reflux adds to each uncovered coarse cell next to the fine level the
+ * sum over its interface faces (in the order x-, x+, y-, y+, z-, z+) of
+ * +reg (the cell's low face) or -reg (its high face), divided by the coarse
+ * box's dx, for the first ncomp components.  nyx_average_down sets each
+ * covered coarse cell to the mean of its eight children (ncomp components;
+ * fine and coarse states must not overlap).  Plans, like fill plans, keep
+ * their tables in the caller's device workspace (256-byte aligned;
+ * nyx_sync_plan_create synchronises the stream); a batch plan that feeds a
+ * register reads the sync plan's tables, so both must outlive that use. */
+typedef struct nyx_sync_plan nyx_sync_plan;
+int nyx_sync_plan_bytes(int nfine, const nyx_box* fboxes, const int32_t* flo, const int32_t* dom,
+                        int ncoarse, const nyx_box* cboxes, const int32_t* clo, size_t* bytes);
+int nyx_sync_plan_create(int nfine, const nyx_box* fboxes, const int32_t* flo, const int32_t* dom,
+                         int ncoarse, const nyx_box* cboxes, const int32_t* clo, void* workspace,
+                         size_t ws_bytes, void* stream, nyx_sync_plan** plan);
+int nyx_sync_plan_counts(const nyx_sync_plan* plan, long long* faces, long long* reflux_cells,
+                         long long* covered_cells);
+int nyx_sync_plan_destroy(nyx_sync_plan* plan);
+int nyx_batch_set_flux_register(nyx_batch* plan, const nyx_sync_plan* sync, int level,
+                                double* reg);
+int nyx_reflux(nyx_sync_plan* plan, double* coarse_state, const double* reg, int ncomp,
+               void* stream);
+int nyx_average_down(nyx_sync_plan* plan, double* coarse_state, const double* fine_state,
+                     int ncomp, void* stream);
+
 /* ---------------- learned Riemann flux ----------------
  * A small network 10 -> 64 -> 64 -> 64 -> 5 (ReLU) stands in for the
  * iteration of the two-shock Riemann solver (Sec. 3.2 names the solver; the

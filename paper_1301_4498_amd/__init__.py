@@ -17,7 +17,7 @@ from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMAN
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
-           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "stats_dict"]
+           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "stats_dict"]
 
 
 def _ptr(t):
@@ -195,6 +195,14 @@ class Batch:
             os.replace(tmp, cache)
         return tune, table
 
+    def set_flux_register(self, sync, level, reg):
+        """Feed a two-level sync plan's register (device FP64, 6 x faces) from
+        every later step: level 0 for the coarse boxes, 1 for the fine boxes;
+        reg None detaches it."""
+        check("nyx_batch_set_flux_register", lib().nyx_batch_set_flux_register(
+            self.handle, sync.handle if sync is not None else None, int(level), _ptr(reg)))
+        self._sync = sync  # keep the sync plan's tables alive
+
     def fill_ghosts(self, state, mode=0, grid=(1, 1, 1), stream=None):
         check("nyx_batch_fill_ghosts", lib().nyx_batch_fill_ghosts(
             self.handle, mode, grid[0], grid[1], grid[2], _ptr(state), _stream(stream)))
@@ -255,6 +263,65 @@ class FillPlan:
     def close(self):
         if self.handle is not None and self.handle.value:
             lib().nyx_fill_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SyncPlan:
+    """Two-level synchronisation (nyx_sync_plan_*, nyx_reflux,
+    nyx_average_down).  fine = (boxes, lo) of the fine level in the periodic
+    domain dom; coarse = (cboxes, clo) of the level below (domain dom / 2)."""
+
+    def __init__(self, fine, coarse, dom, stream=None):
+        import torch
+        fb, flo = fine
+        cb, clo = coarse
+        nf, nc = len(fb), len(cb)
+        self._fb = (Box * nf)(*fb)
+        self._flo = (ctypes.c_int * (3 * nf))(*[int(v) for b in flo for v in b])
+        self._cb = (Box * nc)(*cb)
+        self._clo = (ctypes.c_int * (3 * nc))(*[int(v) for b in clo for v in b])
+        self._dom = (ctypes.c_int * 3)(*[int(v) for v in dom])
+        nbytes = ctypes.c_size_t(0)
+        check("nyx_sync_plan_bytes", lib().nyx_sync_plan_bytes(
+            nf, self._fb, self._flo, self._dom, nc, self._cb, self._clo, ctypes.byref(nbytes)))
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nbytes.value]
+        h = ctypes.c_void_p(0)
+        check("nyx_sync_plan_create", lib().nyx_sync_plan_create(
+            nf, self._fb, self._flo, self._dom, nc, self._cb, self._clo,
+            _ptr(self.workspace), nbytes.value, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def counts(self):
+        """(interface faces, reflux cells, covered coarse cells)."""
+        f, r, c = ctypes.c_longlong(0), ctypes.c_longlong(0), ctypes.c_longlong(0)
+        check("nyx_sync_plan_counts", lib().nyx_sync_plan_counts(
+            self.handle, ctypes.byref(f), ctypes.byref(r), ctypes.byref(c)))
+        return f.value, r.value, c.value
+
+    def register(self):
+        """A zeroed flux register (6 x faces FP64 on the device)."""
+        import torch
+        return torch.zeros(6 * max(self.counts()[0], 1), dtype=torch.float64, device="cuda")
+
+    def reflux(self, coarse_state, reg, ncomp=6, stream=None):
+        check("nyx_reflux", lib().nyx_reflux(self.handle, _ptr(coarse_state), _ptr(reg),
+                                             int(ncomp), _stream(stream)))
+
+    def average_down(self, coarse_state, fine_state, ncomp=6, stream=None):
+        check("nyx_average_down", lib().nyx_average_down(
+            self.handle, _ptr(coarse_state), _ptr(fine_state), int(ncomp), _stream(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().nyx_sync_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
 
     def __del__(self):

@@ -5,6 +5,8 @@ Translation units:
   nyx_util.hip  CFL reduction, dt finalisation, ghost fills (no contraction);
   nyx_fill.hip  ghost fill of an AMR level: planning, copies, coarse-fine
                 interpolation (no contraction);
+  nyx_sync.hip  two-level synchronisation: planning, reflux, average-down
+                (no contraction);
   nyx_abi.cpp   the C ABI (validation, plans, dispatch).
 """
 from __future__ import annotations
@@ -31,6 +33,7 @@ UNITS = [
     ("nyx_mlp.hip", "nyx_mlp.o", ["-ffp-contract=on"]),
     ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
     ("nyx_fill.hip", "nyx_fill.o", ["-ffp-contract=off"]),
+    ("nyx_sync.hip", "nyx_sync.o", ["-ffp-contract=off"]),
     ("nyx_abi.cpp", "nyx_abi.o", ["-ffp-contract=off", "-x", "hip"]),
 ]
 
@@ -46,7 +49,7 @@ def _compile(unit):
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=6) as ex:
+    with ThreadPoolExecutor(max_workers=7) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \

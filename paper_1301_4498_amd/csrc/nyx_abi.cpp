@@ -294,6 +294,11 @@ struct nyx_batch {
   unsigned harvest_keep = 0;
   unsigned long long harvest_seed = 0;
   int tune[kStages] = {0};        // launch-order candidate per stage
+  // flux register fed after every group's update (two-level sync)
+  const FluxRec* reg_recs = nullptr;  // device, sorted by box
+  std::vector<long long> reg_prefix;  // per box, host
+  double* reg = nullptr;
+  long long reg_slots = 0;
 };
 
 namespace {
@@ -488,7 +493,8 @@ namespace {
 // record around its stages (autotuning), or nullptr for the profiler's.
 int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, const double* dt,
                     double a_old, double a_new, double* state_out, double* dt_next,
-                    nyx_stats* stats, hipStream_t s, hipEvent_t* const* group_ev) {
+                    nyx_stats* stats, hipStream_t s, hipEvent_t* const* group_ev,
+                    bool record = true) {
   if (dt_next && launch_zero_u64(plan->smax, plan->nbox, s) != hipSuccess) return NYX_E_HIP;
   if (stats && launch_zero_u64(plan->slots, kStatSlots * kStatFields, s) != hipSuccess)
     return NYX_E_HIP;
@@ -518,6 +524,17 @@ int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, c
       e = run_stages(&plan->prm, A, s);
     }
     if (e != hipSuccess) return NYX_E_HIP;
+    if (record && plan->reg) {
+      // the group's final-stage states are in the stage region until the
+      // next group runs
+      const long long r0 = plan->reg_prefix[g.b0], r1 = plan->reg_prefix[g.b1];
+      e = plan->prm.precision == NYX_MIXED
+              ? mixed::launch_flux_record(A, plan->table, plan->reg_recs + r0, r1 - r0, plan->reg,
+                                          plan->reg_slots, s)
+              : fp64::launch_flux_record(A, plan->table, plan->reg_recs + r0, r1 - r0, plan->reg,
+                                         plan->reg_slots, s);
+      if (e != hipSuccess) return NYX_E_HIP;
+    }
   }
   if (stats && launch_stats_reduce(plan->slots, stats, s) != hipSuccess) return NYX_E_HIP;
   if (dt_next &&
@@ -591,7 +608,7 @@ int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav
     for (int i = 0; i < kStages; ++i) plan->tune[i] = c;
     for (int r = 0; r <= reps && rc == NYX_OK; ++r) {  // r = 0 warms up
       rc = enqueue_batched(plan, state_in, grav, dt, a_old, a_new, state_out, dt_next, nullptr, s,
-                           gev.data());
+                           gev.data(), false);
       if (rc == NYX_OK && hipStreamSynchronize(s) != hipSuccess) rc = NYX_E_HIP;
       double step_ms[kStages] = {};
       for (size_t g = 0; g < ng && rc == NYX_OK && r > 0; ++g)
@@ -652,6 +669,30 @@ int nyx_batch_set_harvest(nyx_batch* plan, float* records, unsigned long long* c
   const double k = keep_fraction * 4294967296.0;
   plan->harvest_keep = k >= 4294967295.0 ? 4294967295u : (unsigned)k;
   plan->harvest_seed = seed;
+  return NYX_OK;
+}
+
+int nyx_batch_set_flux_register(nyx_batch* plan, const nyx_sync_plan* sync, int level,
+                                double* reg) {
+  if (!plan) return NYX_E_NULL;
+  if (!reg) {
+    plan->reg = nullptr;
+    plan->reg_recs = nullptr;
+    plan->reg_prefix.clear();
+    return NYX_OK;
+  }
+  if (!sync) return NYX_E_NULL;
+  SyncLevelView v{};
+  int rc = sync_level_view(sync, level, &v);
+  if (rc) return rc;
+  if (v.nbox != plan->nbox) return NYX_E_SHAPE;
+  for (int b = 0; b < plan->nbox; ++b)
+    for (int d = 0; d < 3; ++d)
+      if (v.shapes[3 * b + d] != plan->boxes[b].n[d]) return NYX_E_SHAPE;
+  plan->reg_recs = v.recs;
+  plan->reg_prefix.assign(v.prefix, v.prefix + plan->nbox + 1);
+  plan->reg = reg;
+  plan->reg_slots = v.nslots;
   return NYX_OK;
 }
 

@@ -263,12 +263,39 @@ struct StepArgs {
 // Shape check of one box (NYX_OK or a negative nyx_status).
 int validate_box(const nyx_box* b);
 
+// One face of a flux register fed by a batched step (Sec. 4.3 reflux): the
+// final flux of face f (box-local; f[d] in [0, n_d] along the normal d, a
+// valid cell index across it) of box `box` is added, times scale * dt, to
+// register slot `slot`.  nsub = 2 sums the 2 x 2 faces f, f + e_t1,
+// f + e_t2, f + e_t1 + e_t2 (t1 < t2 the transverse axes) in that order.
+struct FluxRec {
+  int box, d, nsub, pad_;
+  int f[3], pad2_;
+  double scale;
+  long long slot;
+};
+
+// The records of one level of a two-level sync plan (nyx_sync.hip), sorted
+// by box, with the per-box prefix (host, nbox + 1 entries) and box shapes
+// (host, 3 ints per box) for matching a batch plan.
+struct SyncLevelView {
+  const FluxRec* recs;
+  const long long* prefix;
+  const int* shapes;
+  int nbox;
+  long long nslots;
+};
+
 // The two precision builds of the stage kernels.
 namespace fp64 {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_flux_record(const StepArgs& a, const BoxDev* table, const FluxRec* recs,
+                              long long nrec, double* reg, long long nslots, hipStream_t s);
 }
 namespace mixed {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_flux_record(const StepArgs& a, const BoxDev* table, const FluxRec* recs,
+                              long long nrec, double* reg, long long nslots, hipStream_t s);
 }
 // Precision-independent kernels (in nyx_abi.cpp's companion nyx_util.hip).
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
@@ -293,5 +320,7 @@ hipError_t launch_mlp_predict(const void* packed, const float* rec, long long n,
                               float* out, hipStream_t st);
 hipError_t launch_fill_periodic(const StepArgs& a, const BoxDev* full, double* state, int ncomp,
                                 int mode, int gx, int gy, int gz, hipStream_t s);
+
+int sync_level_view(const nyx_sync_plan* p, int level, SyncLevelView* out);
 
 }  // namespace nyx

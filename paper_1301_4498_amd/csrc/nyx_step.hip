@@ -1356,6 +1356,53 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
   if (A.dt_next) block_max_atomic(smax, A.smax + b.gidx);
 }
 
+// ---------------------------------------------------------------------------
+// flux registers (Sec. 4.3 reflux): after a group's update, each record
+// adds scale * dt times the final flux of its face (or the sum of its 2 x 2
+// fine faces) to its register slot.  One lane per record; a slot belongs to
+// one record, so no two lanes write the same slot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_flux_record(StepArgs A, const BoxDev* table,
+                                                        const FluxRec* recs, long long nrec,
+                                                        double* reg, long long nslots) {
+  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nrec) return;
+  const FluxRec R = recs[r];
+  const BoxDev& b = table[R.box];
+  const StepC& C = step_consts(A, b);
+  const int d = R.d;
+  const unsigned e = ((unsigned)(R.f[2] + 1) * (unsigned)b.ey + (unsigned)(R.f[1] + 1)) *
+                         (unsigned)b.ex + (unsigned)(R.f[0] + 1);
+  const real* G = (const real*)A.work + b.w_f2 + (long long)d * kGod * b.E;
+  const real ah = (real)C.a_h;
+  double acc[6];
+  real f[8];
+  final_flux(A.gamma, d, G, b.E, e, ah, f);
+  for (int c = 0; c < 6; ++c) acc[c] = (double)f[c];
+  if (R.nsub == 2) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const unsigned o1 = e_stride(b, t1), o2 = e_stride(b, t2);
+    const unsigned sub[3] = {e + o1, e + o2, e + o1 + o2};
+    for (int q = 0; q < 3; ++q) {
+      final_flux(A.gamma, d, G, b.E, sub[q], ah, f);
+      for (int c = 0; c < 6; ++c) acc[c] = acc[c] + (double)f[c];
+    }
+  }
+  const double w = R.scale * C.dt;
+  for (int c = 0; c < 6; ++c) {
+    double* g = reg + (long long)c * nslots + R.slot;
+    *g = *g + w * acc[c];
+  }
+}
+
+hipError_t launch_flux_record(const StepArgs& a, const BoxDev* table, const FluxRec* recs,
+                              long long nrec, double* reg, long long nslots, hipStream_t s) {
+  if (nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flux_record, dim3((unsigned)((nrec + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, a, table, recs, nrec, reg, nslots);
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   const dim3 blk(kBlock);
   auto mark = [&](int i) {

@@ -176,3 +176,32 @@ def test_level_fill_planning_errors(nyx):
                 coarse=[((6, 12, 12), (6, 0, 0))])[0] == -2
     # an odd domain
     assert plan([((8, 8, 8), (0, 0, 0))], (9, 8, 8))[0] == -2
+
+
+def test_two_level_sync_planning_errors(nyx):
+    # planning is host work: nested even layouts plan, bad ones are refused
+    L = nyx.lib()
+    I = ctypes.c_int
+
+    def plan(fine, coarse, dom):
+        fb = (nyx.Box * len(fine))(*[nyx.make_box(n, 4, 1.0) for n, _ in fine])
+        flo = (I * (3 * len(fine)))(*[v for _, l in fine for v in l])
+        cb = (nyx.Box * len(coarse))(*[nyx.make_box(n, 4, 2.0) for n, _ in coarse])
+        clo = (I * (3 * len(coarse)))(*[v for _, l in coarse for v in l])
+        d = (I * 3)(*dom)
+        nb = ctypes.c_size_t(0)
+        return L.nyx_sync_plan_bytes(len(fine), fb, flo, d, len(coarse), cb, clo, ctypes.byref(nb))
+
+    whole = [((8, 8, 8), (0, 0, 0))]
+    assert plan([((8, 8, 8), (4, 4, 4))], whole, (16, 16, 16)) == 0
+    # an odd fine corner or extent
+    assert plan([((8, 8, 8), (3, 4, 4))], whole, (16, 16, 16)) == -2
+    assert plan([((8, 6, 7), (4, 4, 4))], whole, (16, 16, 16)) == -2
+    # the coarse level does not hold the fine level's uncovered neighbours
+    assert plan([((8, 8, 8), (4, 4, 4))], [((4, 8, 8), (2, 0, 0))], (16, 16, 16)) == -2
+    # overlapping fine boxes
+    assert plan([((8, 8, 8), (2, 2, 2)), ((8, 8, 8), (4, 4, 4))], whole, (16, 16, 16)) == -2
+    # a fine box outside the domain
+    assert plan([((8, 8, 8), (12, 4, 4))], whole, (16, 16, 16)) == -2
+    assert L.nyx_batch_set_flux_register(None, None, 0, None) == -1
+    assert L.nyx_reflux(None, None, None, 6, None) == -1
