@@ -485,6 +485,122 @@ def level_fill_leg(nyx, torch, log, reps=5):
     return out
 
 
+def two_level_leg(nyx, torch, synth, w, log, steps=4):
+    """One coarse step and two fine substeps with reflux and average-down
+    (Sec. 4.3, Steps 2 and 8), FP32-mixed: the benchmark fields on a coarse
+    level of 64 boxes of 64^3 (periodic 256^3), and a fine level of 8 boxes
+    of 64^3 over the central 128^3 of the 512^3 fine domain (the coarse data
+    injected).  Per two-level step: coarse ghost fill, coarse step feeding
+    the flux register, fine ghost fill from the coarse level, two fine
+    substeps feeding the register (the second fine fill also from the old
+    coarse data: no time interpolation), reflux, average-down.  Reports
+    composite zone-updates/s (coarse cells + 2 x fine cells per step), the
+    time of the sync kernels, and the composite mass change."""
+    import numpy as np
+    m, ng = 64, 4
+    P = (m + 2 * ng) ** 3
+    prm = nyx.default_params(precision=nyx.NYX_MIXED)
+    cpad = synth.split_patches(w.state, (4, 4, 4))
+    gpad = synth.split_patches(w.grav, (4, 4, 4))
+
+    def boxes_of(g, dx, lo0=(0, 0, 0)):
+        bx, lo = [], []
+        for b in range(g[0] * g[1] * g[2]):
+            bx.append(nyx.make_box((m, m, m), ng, dx, state_off=6 * P * b, grav_off=3 * P * b))
+            ijk = (b % g[0], (b // g[0]) % g[1], b // (g[0] * g[1]))
+            lo.append(tuple(lo0[d] + m * ijk[d] for d in range(3)))
+        return bx, lo
+
+    cb, clo = boxes_of((4, 4, 4), 1.0 / 256)
+    fb, flo = boxes_of((2, 2, 2), 1.0 / 512, lo0=(192, 192, 192))
+    c = torch.from_numpy(np.concatenate([np.ascontiguousarray(x).ravel() for x in cpad])).cuda()
+    cg = torch.from_numpy(np.concatenate([np.ascontiguousarray(x).ravel() for x in gpad])).to(
+        torch.float32).cuda()
+    # fine data: the coarse cells under each fine box, injected (children = parent)
+    fs, fgs = [], []
+    for lo in flo:
+        C0 = [x // 2 for x in lo]
+        sl = (slice(None),) + tuple(slice(C0[2 - a] + ng - ng // 2, C0[2 - a] + ng + m // 2 + ng // 2)
+                                    for a in range(3))
+        for src, dst in ((w.state, fs), (w.grav, fgs)):
+            blk = src[sl]
+            dst.append(np.ascontiguousarray(blk.repeat(2, 1).repeat(2, 2).repeat(2, 3)).ravel())
+    f = torch.from_numpy(np.concatenate(fs)).cuda()
+    fg = torch.from_numpy(np.concatenate(fgs)).to(torch.float32).cuda()
+    c2, f2 = c.clone(), f.clone()
+    cfill = nyx.FillPlan(cb, clo, (256, 256, 256))
+    ffill = nyx.FillPlan(fb, flo, (512, 512, 512), coarse=(cb, clo))
+    sync = nyx.SyncPlan((fb, flo), (cb, clo), (512, 512, 512))
+    nfaces, ncells, ncov = sync.counts()
+    reg = sync.register()
+    cbat = nyx.Batch(prm, cb, aligned(torch, nyx.Batch.workspace_bytes(prm, cb)[1]))
+    fbat = nyx.Batch(prm, fb, aligned(torch, nyx.Batch.workspace_bytes(prm, fb)[1]))
+    dtc = torch.zeros(64, dtype=torch.float64, device="cuda")
+    cfill.fill(c)
+    cbat.estimate_dt(c, w.a0, 0.5, dtc)
+    cbat.min_dt(dtc)
+    dt_c = float(dtc[0])
+    dtf = torch.full((8,), 0.5 * dt_c, dtype=torch.float64, device="cuda")
+    ffill.fill(f, c)
+    a = [w.a0 + (w.a1 - w.a0) * k / (2 * steps + 2) for k in range(2 * steps + 3)]
+    cbat.autotune(c, cg, dtc, a[0], a[2], c2, reps=2)
+    fbat.autotune(f, fg, dtf, a[0], a[1], f2, reps=2)
+    cbat.set_flux_register(sync, 0, reg)
+    fbat.set_flux_register(sync, 1, reg)
+
+    def composite_mass(cs, fst):
+        cv = synth.join_valid(cs.view(-1), (4, 4, 4), (m, m, m))[0].cpu().numpy()
+        fv = synth.join_valid(fst.view(-1), (2, 2, 2), (m, m, m))[0].cpu().numpy()
+        return 8.0 * (cv.sum() - cv[96:160, 96:160, 96:160].sum()) + fv.sum()
+
+    def two_level_step(k):
+        reg.zero_()
+        cfill.fill(c)
+        cbat.step(c, cg, dtc, a[2 * k], a[2 * k + 2], c2)
+        ffill.fill(f, c)
+        fbat.step(f, fg, dtf, a[2 * k], a[2 * k + 1], f2)
+        ffill.fill(f2, c)
+        fbat.step(f2, fg, dtf, a[2 * k + 1], a[2 * k + 2], f)
+        sync.reflux(c2, reg)
+        sync.average_down(c2, f)
+        c.copy_(c2)
+
+    two_level_step(0)
+    torch.cuda.synchronize()
+    mass0 = composite_mass(c, f)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(1, steps + 1):
+        two_level_step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    mass1 = composite_mass(c, f)
+    cells = 64 * m ** 3 + 2 * 8 * m ** 3
+    # the sync kernels alone
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        sync.reflux(c2, reg)
+        sync.average_down(c2, f)
+    e1.record()
+    torch.cuda.synchronize()
+    sync_ms = e0.elapsed_time(e1) / reps
+    out = {"coarse": "64 x 64^3 (256^3 periodic)", "fine": "8 x 64^3 over the central 128^3",
+           "interface_faces": nfaces, "reflux_cells": ncells, "covered_cells": ncov,
+           "ms_per_two_level_step": ms, "zone_updates_per_s": cells / (ms * 1e-3),
+           "sync_ms": sync_ms, "sync_frac": sync_ms / ms,
+           "composite_mass_rel_change": abs(mass1 - mass0) / abs(mass0)}
+    log("two-level step: %.3f ms, %.3e zone-updates/s, reflux + average-down %.4f ms, composite "
+        "mass change %.1e" % (ms, out["zone_updates_per_s"], sync_ms,
+                              out["composite_mass_rel_change"]))
+    fbat.set_flux_register(None, 1, None)
+    cbat.set_flux_register(None, 0, None)
+    for x in (cfill, ffill, cbat, fbat, sync):
+        x.close()
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
     import oracle
@@ -519,6 +635,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the PLM / linearised-solver / gravity-form-2 leg")
     ap.add_argument("--no-fill", action="store_true", help="skip the level ghost-fill leg")
+    ap.add_argument("--no-two-level", action="store_true",
+                    help="skip the two-level step (reflux, average-down) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -639,6 +757,8 @@ def main():
         out["variants"] = variants_leg(nyx, torch, w, args.steps, args.warmup, log)
     if not args.no_fill:
         out["level_fill"] = level_fill_leg(nyx, torch, log)
+    if not args.no_two_level:
+        out["two_level"] = two_level_leg(nyx, torch, synth, w, log)
     if not args.no_stress:
         out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
                                           flux, 10, log)
