@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "nyx_oracle.c")
 _MLP_SRC = os.path.join(_HERE, "mlp_oracle.c")
 _FILL_SRC = os.path.join(_HERE, "fill_oracle.c")
 _SYNC_SRC = os.path.join(_HERE, "sync_oracle.c")
+_GRAV_SRC = os.path.join(_HERE, "gravity_oracle.c")
 
 # Compiler line: plain IEEE FP64, no contraction, no fast-math.
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11"]
@@ -37,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle shared library with gcc; returns its path."""
     if not force and os.path.exists(_SO):
         return _SO
-    srcs = [_SRC, _MLP_SRC, _FILL_SRC, _SYNC_SRC]
+    srcs = [_SRC, _MLP_SRC, _FILL_SRC, _SYNC_SRC, _GRAV_SRC]
     tmp = _SO + ".tmp%d" % os.getpid()
     cmd = ["gcc"] + CFLAGS + ["-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
@@ -127,6 +128,12 @@ def lib():
                                                i, _I32, _I32, _I64, i, _I32, _D, i, _D, _I64,
                                                ctypes.c_int64, _D, i, _I64, _I64]
         L.nyxo_reflux_average_down.restype = i
+        L.nyxo_cic_deposit.argtypes = [ctypes.c_long, _D, _D, _I32, d, _D]
+        L.nyxo_cic_deposit.restype = i
+        L.nyxo_cic_interp.argtypes = [ctypes.c_long, _D, _I32, d, _D, _D]
+        L.nyxo_cic_interp.restype = i
+        L.nyxo_gradient.argtypes = [_I32, d, _D, _D]
+        L.nyxo_gradient.restype = i
         L.nyxo_ppm_interface.argtypes = [_D]
         L.nyxo_ppm_interface.restype = d
         L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
@@ -412,3 +419,82 @@ def reflux_average_down(cboxes, cng, cdx, cdatas, cfluxes, dt_c, fboxes, fng, do
         a[...] = cflat[pos:pos + sz].reshape(a.shape)
         pos += sz
     return nf.value, nc.value
+
+
+# ---- gravity input path (gravity_oracle.c; Sec. 2.4, Sec. 3.4) ----
+# Mesh fields of the periodic domain: arrays of shape (nz, ny, nx), no ghosts.
+
+def _dom_of(shape):
+    return np.ascontiguousarray([shape[2], shape[1], shape[0]], dtype=np.int32)
+
+
+def cic_deposit(pos, mass, shape, dx, rho=None):
+    """Cloud-in-cell comoving density of particles (pos: (3, np) x, y, z;
+    mass: (np,)) on a periodic mesh of `shape` (nz, ny, nx); added to rho
+    when given."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    out = np.zeros(shape) if rho is None else np.ascontiguousarray(rho, dtype=np.float64).copy()
+    dom = _dom_of(shape)
+    rc = lib().nyxo_cic_deposit(mass.size, _ptr(pos), _ptr(mass),
+                                dom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), dx, _ptr(out))
+    if rc != 0:
+        raise ValueError("nyxo_cic_deposit: bad arguments")
+    return out
+
+
+def cic_interp(pos, field, dx):
+    """Cloud-in-cell value of a mesh field at particle positions (pins only)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    field = np.ascontiguousarray(field, dtype=np.float64)
+    out = np.zeros(pos.shape[1])
+    dom = _dom_of(field.shape)
+    rc = lib().nyxo_cic_interp(pos.shape[1], _ptr(pos),
+                               dom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), dx,
+                               _ptr(field), _ptr(out))
+    if rc != 0:
+        raise ValueError("nyxo_cic_interp: bad arguments")
+    return out
+
+
+def gradient(phi, dx):
+    """g = -(centred difference of phi) / (2 dx) per axis: (3, nz, ny, nx),
+    components x, y, z."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    g = np.zeros((3,) + phi.shape)
+    dom = _dom_of(phi.shape)
+    rc = lib().nyxo_gradient(dom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), dx, _ptr(phi),
+                             _ptr(g))
+    if rc != 0:
+        raise ValueError("nyxo_gradient: bad arguments")
+    return g
+
+
+def laplacian7(phi, dx):
+    """The standard 7-point Laplacian on the periodic mesh (Sec. 3.4)."""
+    out = -6.0 * phi
+    for ax in range(3):
+        out = out + (np.roll(phi, 1, axis=ax) + np.roll(phi, -1, axis=ax))
+    return out / (dx * dx)
+
+
+def poisson_solve(rho, dx, coef):
+    """The solution of the discrete periodic Poisson problem of Sec. 2.4 /
+    Sec. 3.4: laplacian7(phi) = coef (rho - mean(rho)), phi of zero mean
+    (the gauge of the periodic problem).  Exact up to rounding: the 7-point
+    operator is diagonal in the discrete Fourier basis with eigenvalues
+    sum_d (2 cos(2 pi k_d / n_d) - 2) / dx^2; the k = 0 mode is removed."""
+    rho = np.asarray(rho, dtype=np.float64)
+    f = coef * (rho - rho.mean())
+    lam = np.zeros(rho.shape)
+    for ax, n in enumerate(rho.shape):
+        k = np.arange(n)
+        e = (2.0 * np.cos(2.0 * np.pi * k / n) - 2.0) / (dx * dx)
+        shp = [1, 1, 1]
+        shp[ax] = n
+        lam = lam + e.reshape(shp)
+    fh = np.fft.fftn(f)
+    lam[0, 0, 0] = 1.0
+    ph = fh / lam
+    ph[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(ph))
