@@ -331,6 +331,56 @@ int nyx_reflux(nyx_sync_plan* plan, double* coarse_state, const double* reg, int
 int nyx_average_down(nyx_sync_plan* plan, double* coarse_state, const double* fine_state,
                      int ncomp, void* stream);
 
+/* ---------------- gravity input of the step (Sec. 2.4, Sec. 3.4) ----------------
+ * The mesh side of self-gravity on a periodic domain of dom[3] cells (each
+ * even, at most 2^16, product below 2^31) of size dx.  Mesh fields (rho,
+ * phi) are FP64 device arrays of the domain, x fastest, no ghost cells;
+ * cell (i, j, k) is centred at ((i + 1/2) dx, ...).
+ *
+ * nyx_cic_deposit adds the cloud-in-cell comoving density of np particles
+ * to rho: a particle's mass is spread uniformly over a cube of side dx
+ * centred at it, each cell receives the mass times the volume of its
+ * intersection with the cube, divided by dx^6 (dx^3 for the fraction, dx^3
+ * for a density).  pos: device, three arrays of np positions (x, then y,
+ * then z; taken periodically; a particle with a non-finite coordinate, or
+ * one beyond 1e15 cells, is skipped); mass: device, np values.
+ * The additions use FP64 atomics: the result is exact up to their order.
+ *
+ * nyx_poisson_solve solves lap7(phi) = coef (rho_t - mean(rho_t)), lap7 the
+ * 7-point Laplacian, rho_t = rho plus, when state is not NULL, the gas
+ * density (component 0) of the state of box `box` (host; a box of dom
+ * cells: the whole domain as one padded box).  coef is 4 pi G / a
+ * (Sec. 2.4).  Geometric multigrid: V-cycles with two red-black
+ * Gauss-Seidel sweeps before and after the coarse correction, averaging
+ * restriction of the residual, trilinear cell-centred prolongation, levels
+ * halved while every extent is a multiple of 4, 32 sweeps on the coarsest.
+ * phi (device) is the initial guess on entry (the previous solution serves,
+ * Sec. 3.4) and the zero-mean solution on return.  The cycles stop once
+ * max|rhs - lap7 phi| <= tol max|rhs| (the paper's typical tol is 1e-12;
+ * FP64 rounding of the residual limits what large meshes can reach) or
+ * after max_vcycles.  With tol > 0 or rel_resid given, the call
+ * synchronises the stream once per V-cycle; with tol = 0 and rel_resid NULL
+ * it runs exactly max_vcycles cycles and only enqueues kernels.  vcycles
+ * and rel_resid (host, or NULL) receive the cycles run and the final
+ * relative residual.  workspace: device, nyx_poisson_workspace_bytes
+ * bytes, 256-byte aligned.  Every reduction has a fixed order: the same
+ * inputs give the same bits.
+ *
+ * nyx_gravity_from_phi writes g = -(phi(c + e_d) - phi(c - e_d)) / (2 dx)
+ * into every padded cell of box `box` (host; dom cells; ghosts are the
+ * periodic images) of grav (device), at box->grav_off with box->grav_stride,
+ * in FP64 (precision NYX_FP64) or FP32 (NYX_MIXED): the gravity input of a
+ * step of that box. */
+int nyx_cic_deposit(const double* pos, const double* mass, long long np, const int32_t* dom,
+                    double dx, double* rho, void* stream);
+int nyx_poisson_workspace_bytes(const int32_t* dom, size_t* bytes);
+int nyx_poisson_solve(const int32_t* dom, double dx, double coef, const double* rho,
+                      const double* state, const nyx_box* box, double* phi, double tol,
+                      int max_vcycles, void* workspace, size_t ws_bytes, void* stream,
+                      int* vcycles, double* rel_resid);
+int nyx_gravity_from_phi(const int32_t* dom, double dx, const double* phi, const nyx_box* box,
+                         void* grav, int precision, void* stream);
+
 /* ---------------- learned Riemann flux ----------------
  * A small network 10 -> 64 -> 64 -> 64 -> 5 (ReLU) stands in for the
  * iteration of the two-shock Riemann solver (Sec. 3.2 names the solver; the

@@ -17,7 +17,8 @@ from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMAN
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
-           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "stats_dict"]
+           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "cic_deposit", "PoissonSolver",
+           "gravity_from_phi", "stats_dict"]
 
 
 def _ptr(t):
@@ -329,3 +330,57 @@ class SyncPlan:
             self.close()
         except Exception:
             pass
+
+
+def _dom(dom):
+    return (ctypes.c_int * 3)(*[int(v) for v in dom])
+
+
+def cic_deposit(pos, mass, dom, dx, rho, stream=None):
+    """Add the cloud-in-cell density of particles (pos: device (3, np) FP64,
+    mass: device (np,)) to rho (device, the domain's cells, x fastest);
+    dom = (nx, ny, nz)."""
+    np_ = int(mass.numel())
+    check("nyx_cic_deposit", lib().nyx_cic_deposit(_ptr(pos), _ptr(mass), np_, _dom(dom),
+                                                   float(dx), _ptr(rho), _stream(stream)))
+
+
+class PoissonSolver:
+    """Multigrid solve of the periodic 7-point Poisson problem on a domain of
+    dom = (nx, ny, nz) cells (nyx_poisson_solve), with its own workspace."""
+
+    def __init__(self, dom):
+        import torch
+        self.dom = tuple(int(v) for v in dom)
+        nb = ctypes.c_size_t(0)
+        check("nyx_poisson_workspace_bytes",
+              lib().nyx_poisson_workspace_bytes(_dom(self.dom), ctypes.byref(nb)))
+        raw = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw[off:off + nb.value]
+
+    def solve(self, rho, phi, dx, coef, tol=1e-10, max_vcycles=50, state=None, box=None,
+              stream=None):
+        """phi (device) in: initial guess, out: solution.  Returns (V-cycles,
+        relative residual)."""
+        cyc, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+        check("nyx_poisson_solve", lib().nyx_poisson_solve(
+            _dom(self.dom), float(dx), float(coef), _ptr(rho), _ptr(state),
+            ctypes.byref(box) if box is not None else None, _ptr(phi), float(tol),
+            int(max_vcycles), _ptr(self.workspace), self.workspace.numel(), _stream(stream),
+            ctypes.byref(cyc), ctypes.byref(rel)))
+        return cyc.value, rel.value
+
+    def enqueue(self, rho, phi, dx, coef, vcycles, state=None, box=None, stream=None):
+        """Exactly `vcycles` V-cycles, kernels only (no synchronisation)."""
+        check("nyx_poisson_solve", lib().nyx_poisson_solve(
+            _dom(self.dom), float(dx), float(coef), _ptr(rho), _ptr(state),
+            ctypes.byref(box) if box is not None else None, _ptr(phi), 0.0, int(vcycles),
+            _ptr(self.workspace), self.workspace.numel(), _stream(stream), None, None))
+
+
+def gravity_from_phi(phi, dom, dx, box, grav, precision, stream=None):
+    """g = -grad(phi) (centred) into every padded cell of `box` in grav."""
+    check("nyx_gravity_from_phi", lib().nyx_gravity_from_phi(
+        _dom(dom), float(dx), _ptr(phi), ctypes.byref(box), _ptr(grav), int(precision),
+        _stream(stream)))

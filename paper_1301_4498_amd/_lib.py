@@ -126,6 +126,13 @@ def lib():
             "nyx_batch_set_flux_register": (i, [vp, vp, i, vp]),
             "nyx_reflux": (i, [vp, vp, vp, i, vp]),
             "nyx_average_down": (i, [vp, vp, vp, i, vp]),
+            "nyx_cic_deposit": (i, [vp, vp, ctypes.c_longlong, ctypes.POINTER(i), d, vp, vp]),
+            "nyx_poisson_workspace_bytes": (i, [ctypes.POINTER(i), ctypes.POINTER(sz)]),
+            "nyx_poisson_solve": (i, [ctypes.POINTER(i), d, d, vp, vp, ctypes.POINTER(Box), vp, d,
+                                      i, vp, sz, vp, ctypes.POINTER(i),
+                                      ctypes.POINTER(ctypes.c_double)]),
+            "nyx_gravity_from_phi": (i, [ctypes.POINTER(i), d, vp, ctypes.POINTER(Box), vp, i,
+                                         vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -152,7 +159,8 @@ def exported_symbols():
             "nyx_fill_plan_counts", "nyx_fill_level", "nyx_fill_plan_destroy",
             "nyx_sync_plan_bytes", "nyx_sync_plan_create", "nyx_sync_plan_counts",
             "nyx_sync_plan_destroy", "nyx_batch_set_flux_register", "nyx_reflux",
-            "nyx_average_down"]
+            "nyx_average_down", "nyx_cic_deposit", "nyx_poisson_workspace_bytes",
+            "nyx_poisson_solve", "nyx_gravity_from_phi"]
 
 TUNE_CANDIDATES = 16
 MLP_NPARAM = 9349

@@ -7,6 +7,8 @@ Translation units:
                 interpolation (no contraction);
   nyx_sync.hip  two-level synchronisation: planning, reflux, average-down
                 (no contraction);
+  nyx_gravity.hip  gravity input: cloud-in-cell deposit, multigrid Poisson
+                solve, centred gradient (no contraction);
   nyx_abi.cpp   the C ABI (validation, plans, dispatch).
 """
 from __future__ import annotations
@@ -34,6 +36,7 @@ UNITS = [
     ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
     ("nyx_fill.hip", "nyx_fill.o", ["-ffp-contract=off"]),
     ("nyx_sync.hip", "nyx_sync.o", ["-ffp-contract=off"]),
+    ("nyx_gravity.hip", "nyx_gravity.o", ["-ffp-contract=off"]),
     ("nyx_abi.cpp", "nyx_abi.o", ["-ffp-contract=off", "-x", "hip"]),
 ]
 
@@ -49,7 +52,7 @@ def _compile(unit):
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=7) as ex:
+    with ThreadPoolExecutor(max_workers=8) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
