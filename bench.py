@@ -601,6 +601,83 @@ def two_level_leg(nyx, torch, synth, w, log, steps=4):
     return out
 
 
+def gravity_leg(nyx, torch, synth, w, log, reps=3):
+    """The gravity input of the step on the benchmark box (Sec. 2.4, 3.4):
+    256^3 dark-matter particles (one per cell, displaced from the cell
+    centres by N(0, 0.3 dx) per axis, equal masses of the mean gas density)
+    deposited by cloud-in-cell, the periodic Poisson solve of the total
+    density (deposit + the state's gas density) to a relative residual of
+    1e-10 from zero and from the previous solution, and g = -grad(phi) into
+    the FP32 padded gravity array of the step.  Algorithmic bytes: deposit
+    32 B per particle read + 8 x 8 B of atomic adds; a red-black sweep of the
+    finest level reads phi and f and writes phi, 24 B per cell; the gradient
+    reads phi (8 B per cell) and writes 3 FP32 per padded cell."""
+    import numpy as np
+    n = w.n[0]
+    dx = w.dx
+    dom = (n, n, n)
+    rng = np.random.default_rng(21)
+    c = (np.arange(n) + 0.5) * dx
+    zz, yy, xx = np.meshgrid(c, c, c, indexing="ij")
+    pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()])
+    pos += rng.normal(0.0, 0.3 * dx, pos.shape)
+    npart = pos.shape[1]
+    mass = np.full(npart, float(w.state[0].mean()) * dx ** 3)
+    pos_d = torch.from_numpy(pos).cuda()
+    mass_d = torch.from_numpy(mass).cuda()
+    del pos, zz, yy, xx
+    box = nyx.make_box(w.n, 4, dx)
+    state = torch.from_numpy(w.state).cuda()
+    rho = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    phi = torch.zeros_like(rho)
+    grav = torch.zeros((3,) + w.state.shape[1:], dtype=torch.float32, device="cuda")
+    solver = nyx.PoissonSolver(dom)
+    coef = 4 * np.pi * 1.0 / w.a0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k=reps):
+        e0.record()
+        for _ in range(k):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k, out
+
+    def deposit():
+        rho.zero_()
+        nyx.cic_deposit(pos_d, mass_d, dom, dx, rho)
+
+    deposit()
+    torch.cuda.synchronize()
+    dep_ms, _ = timed(deposit)
+
+    def cold():
+        phi.zero_()
+        return solver.solve(rho, phi, dx, coef, tol=1e-10, max_vcycles=40, state=state, box=box)
+
+    cold()
+    cold_ms, (cyc, rel) = timed(cold)
+    # a warm start: the previous solution for a slightly moved density
+    pos_d.add_(0.05 * dx)
+    deposit()
+    warm_ms, (wcyc, wrel) = timed(lambda: solver.solve(rho, phi, dx, coef, tol=1e-10,
+                                                       max_vcycles=40, state=state, box=box), 1)
+    grad_ms, _ = timed(lambda: nyx.gravity_from_phi(phi, dom, dx, box, grav, nyx.NYX_MIXED))
+    # fixed-cycle form: kernels only, the V-cycle rate
+    vc_ms, _ = timed(lambda: solver.enqueue(rho, phi, dx, coef, cyc, state=state, box=box))
+    P = (n + 8) ** 3
+    out = {"particles": npart, "deposit_ms": dep_ms,
+           "deposit_gbs": npart * (32 + 64) / (dep_ms * 1e-3) / 1e9,
+           "solve_cold_ms": cold_ms, "vcycles_cold": cyc, "rel_resid_cold": rel,
+           "solve_warm_ms": warm_ms, "vcycles_warm": wcyc, "rel_resid_warm": wrel,
+           "ms_per_vcycle_no_sync": vc_ms / cyc, "gradient_ms": grad_ms,
+           "gradient_gbs": (n ** 3 * 8 + P * 12) / (grad_ms * 1e-3) / 1e9}
+    log("gravity: deposit %d particles %.3f ms; solve %d V-cycles %.2f ms (rel resid %.1e), warm "
+        "%d V-cycles %.2f ms; %.3f ms per V-cycle; gradient %.3f ms"
+        % (npart, dep_ms, cyc, cold_ms, rel, wcyc, warm_ms, vc_ms / cyc, grad_ms))
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
     import oracle
@@ -637,6 +714,8 @@ def main():
     ap.add_argument("--no-fill", action="store_true", help="skip the level ghost-fill leg")
     ap.add_argument("--no-two-level", action="store_true",
                     help="skip the two-level step (reflux, average-down) leg")
+    ap.add_argument("--no-gravity", action="store_true",
+                    help="skip the gravity input leg (deposit, Poisson solve, gradient)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -759,6 +838,8 @@ def main():
         out["level_fill"] = level_fill_leg(nyx, torch, log)
     if not args.no_two_level:
         out["two_level"] = two_level_leg(nyx, torch, synth, w, log)
+    if not args.no_gravity:
+        out["gravity"] = gravity_leg(nyx, torch, synth, w, log)
     if not args.no_stress:
         out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
                                           flux, 10, log)

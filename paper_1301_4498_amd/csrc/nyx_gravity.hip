@@ -20,9 +20,9 @@
 #include "nyx_internal.h"
 
 namespace nyx {
-namespace {
+namespace grav {
 
-constexpr int kRedBlocks = 1024;  // block partials of a reduction
+constexpr int kRedBlocks = 4096;  // block partials of a reduction
 
 __device__ __forceinline__ unsigned wrap_dec(unsigned i, unsigned n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ unsigned wrap_inc(unsigned i, unsigned n) { return i + 1 == n ? 0 : i + 1; }
@@ -31,8 +31,25 @@ struct Grid {
   unsigned nx, ny, nz;
 };
 
-__device__ __forceinline__ unsigned at(const Grid& g, unsigned i, unsigned j, unsigned k) {
+// natural order (the caller's mesh fields): x fastest
+__device__ __forceinline__ unsigned nat(const Grid& g, unsigned i, unsigned j, unsigned k) {
   return (k * g.ny + j) * g.nx + i;
+}
+
+// the solver's own arrays keep the two colours of the red-black ordering
+// apart: colour (i + j + k) & 1 holds its cells x fastest with half-length
+// rows, so a half sweep reads the other colour's neighbours, its own rhs
+// and writes its own cells, each contiguous across the lanes of a row
+__device__ __forceinline__ unsigned at(const Grid& g, unsigned i, unsigned j, unsigned k) {
+  const unsigned half = g.nx >> 1;
+  return ((i + j + k) & 1) * (half * g.ny * g.nz) + (k * g.ny + j) * half + (i >> 1);
+}
+
+__device__ __forceinline__ void coords(const Grid& g, unsigned c, unsigned* i, unsigned* j,
+                                       unsigned* k) {
+  *i = c % g.nx;
+  *j = (c / g.nx) % g.ny;
+  *k = c / (g.nx * g.ny);
 }
 
 // the six-neighbour sum of the 7-point stencil, (x pair + y pair) + z pair
@@ -71,7 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_cic(const double* __restrict__ pos,
     w = w * (b0 ? f[0] : 1.0 - f[0]);
     w = w * (b1 ? f[1] : 1.0 - f[1]);
     w = w * (b2 ? f[2] : 1.0 - f[2]);
-    unsafeAtomicAdd(rho + at(g, b0 ? hi[0] : lo[0], b1 ? hi[1] : lo[1], b2 ? hi[2] : lo[2]), m * w);
+    unsafeAtomicAdd(rho + nat(g, b0 ? hi[0] : lo[0], b1 ? hi[1] : lo[1], b2 ? hi[2] : lo[2]),
+                    m * w);
   }
 }
 
@@ -111,7 +129,8 @@ __device__ double block_reduce(double v) {
   return sh[0];
 }
 
-// MODE 0: sum of rho_total; 1: max |f - L phi|; 2: max |f|; 3: sum of phi
+// MODE 0: sum of rho_total (natural order); 1: max |f - L phi|; 2: max |f|;
+// 3: sum of phi (solver order)
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_partial(RhoSrc R, const double* __restrict__ phi,
                                                     const double* __restrict__ f, Grid g,
@@ -124,7 +143,12 @@ __global__ __launch_bounds__(kBlock) void k_partial(RhoSrc R, const double* __re
     if (MODE == 0) {
       v = rho_total(R, g, c);
     } else if (MODE == 1) {
-      const unsigned i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
+      // c walks the solver's order: the cell's colour, row and half index
+      const unsigned half = g.nx >> 1, hn = n >> 1;
+      const unsigned color = c / hn, r = c - color * hn;
+      const unsigned ih = r % half, row = r / half;
+      const unsigned j = row % g.ny, k = row / g.ny;
+      const unsigned i = 2 * ih + ((j + k + color) & 1);
       const double lap = (nb_sum(phi, g, i, j, k) - 6.0 * phi[c]) * inv_h2;
       v = fabs(f[c] - lap);
     } else if (MODE == 2) {
@@ -147,24 +171,34 @@ __global__ __launch_bounds__(kBlock) void k_final(const double* __restrict__ par
   if (threadIdx.x == 0) *out = b;
 }
 
-// f = coef (rho_total - sum / n)
+// f = coef (rho_total - sum / n) in the solver's order; the initial guess
+// copied into it
 __global__ __launch_bounds__(kBlock) void k_rhs(RhoSrc R, Grid g, double coef,
                                                 const double* __restrict__ sum,
-                                                double* __restrict__ f) {
+                                                double* __restrict__ f,
+                                                const double* __restrict__ phi_in,
+                                                double* __restrict__ phi) {
   const unsigned n = g.nx * g.ny * g.nz;
   const unsigned c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= n) return;
+  unsigned i, j, k;
+  coords(g, c, &i, &j, &k);
+  const unsigned a = at(g, i, j, k);
   const double mean = *sum / (double)n;
-  f[c] = coef * (rho_total(R, g, c) - mean);
+  f[a] = coef * (rho_total(R, g, c) - mean);
+  phi[a] = phi_in[c];
 }
 
-// phi -= sum / n
-__global__ __launch_bounds__(kBlock) void k_sub_mean(double* __restrict__ phi, Grid g,
-                                                     const double* __restrict__ sum) {
+// the caller's phi (natural order) = the solution minus sum / n
+__global__ __launch_bounds__(kBlock) void k_sub_mean(const double* __restrict__ phi, Grid g,
+                                                     const double* __restrict__ sum,
+                                                     double* __restrict__ out) {
   const unsigned n = g.nx * g.ny * g.nz;
   const unsigned c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= n) return;
-  phi[c] = phi[c] - *sum / (double)n;
+  unsigned i, j, k;
+  coords(g, c, &i, &j, &k);
+  out[c] = phi[at(g, i, j, k)] - *sum / (double)n;
 }
 
 // ---- multigrid kernels ----
@@ -180,6 +214,25 @@ __global__ __launch_bounds__(kBlock) void k_rbgs(double* __restrict__ phi,
   const unsigned i = 2 * ih + ((j + k + color) & 1);
   const unsigned c = at(g, i, j, k);
   phi[c] = (nb_sum(phi, g, i, j, k) - h2 * f[c]) / 6.0;
+}
+
+// All sweeps of a small level in one workgroup (the half sweeps separated
+// by barriers): the same updates, in the same order, as k_rbgs launches.
+__global__ __launch_bounds__(kBlock) void k_rbgs_small(double* __restrict__ phi,
+                                                       const double* __restrict__ f, Grid g,
+                                                       double h2, int sweeps) {
+  const unsigned half = g.nx >> 1, n = half * g.ny * g.nz;
+  for (int it = 0; it < sweeps; ++it)
+    for (unsigned color = 0; color < 2; ++color) {
+      for (unsigned t = threadIdx.x; t < n; t += kBlock) {
+        const unsigned ih = t % half, r = t / half;
+        const unsigned j = r % g.ny, k = r / g.ny;
+        const unsigned i = 2 * ih + ((j + k + color) & 1);
+        const unsigned c = at(g, i, j, k);
+        phi[c] = (nb_sum(phi, g, i, j, k) - h2 * f[c]) / 6.0;
+      }
+      __syncthreads();
+    }
 }
 
 // coarse f = mean of the eight children's residuals f - L phi; coarse phi = 0
@@ -198,30 +251,42 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const double* __restrict__ 
     const double r = f[c] - (nb_sum(phi, g, i, j, k) - 6.0 * phi[c]) * inv_h2;
     s = q == 0 ? r : s + r;
   }
-  fc[C] = 0.125 * s;
-  phic[C] = 0.0;
+  const unsigned a = at(gc, I, J, K);
+  fc[a] = 0.125 * s;
+  phic[a] = 0.0;
 }
 
-// fine phi += trilinear (cell-centred) interpolation of the coarse correction
+// fine phi += trilinear (cell-centred) interpolation of the coarse
+// correction: one lane per coarse cell reads its 3 x 3 x 3 neighbourhood
+// once and corrects its eight children; child (a, b, c) takes the parent
+// with weight 27/64, the three face neighbours on its side 9/64, the three
+// edge neighbours 3/64 and the corner 1/64
 __global__ __launch_bounds__(kBlock) void k_prolong(double* __restrict__ phi, Grid g,
                                                     const double* __restrict__ ec, Grid gc) {
-  const unsigned c = blockIdx.x * kBlock + threadIdx.x;
-  if (c >= g.nx * g.ny * g.nz) return;
-  const unsigned i = c % g.nx, j = (c / g.nx) % g.ny, k = c / (g.nx * g.ny);
-  const unsigned I = i >> 1, J = j >> 1, K = k >> 1;
-  // the coarse neighbour on the child's side, per axis
-  const unsigned I1 = (i & 1) ? wrap_inc(I, gc.nx) : wrap_dec(I, gc.nx);
-  const unsigned J1 = (j & 1) ? wrap_inc(J, gc.ny) : wrap_dec(J, gc.ny);
-  const unsigned K1 = (k & 1) ? wrap_inc(K, gc.nz) : wrap_dec(K, gc.nz);
-  const double c000 = ec[at(gc, I, J, K)];
-  const double c100 = ec[at(gc, I1, J, K)], c010 = ec[at(gc, I, J1, K)], c001 = ec[at(gc, I, J, K1)];
-  const double c110 = ec[at(gc, I1, J1, K)], c101 = ec[at(gc, I1, J, K1)],
-               c011 = ec[at(gc, I, J1, K1)];
-  const double c111 = ec[at(gc, I1, J1, K1)];
-  const double e = (27.0 * c000 + 9.0 * ((c100 + c010) + c001) + 3.0 * ((c110 + c101) + c011) +
-                    c111) *
-                   (1.0 / 64.0);
-  phi[c] = phi[c] + e;
+  const unsigned C = blockIdx.x * kBlock + threadIdx.x;
+  if (C >= gc.nx * gc.ny * gc.nz) return;
+  unsigned I, J, K;
+  coords(gc, C, &I, &J, &K);
+  const unsigned xs[3] = {wrap_dec(I, gc.nx), I, wrap_inc(I, gc.nx)};
+  const unsigned ys[3] = {wrap_dec(J, gc.ny), J, wrap_inc(J, gc.ny)};
+  const unsigned zs[3] = {wrap_dec(K, gc.nz), K, wrap_inc(K, gc.nz)};
+  double e[3][3][3];
+  for (int z = 0; z < 3; ++z)
+    for (int y = 0; y < 3; ++y)
+      for (int x = 0; x < 3; ++x) e[z][y][x] = ec[at(gc, xs[x], ys[y], zs[z])];
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+    const int X = a ? 2 : 0, Y = b ? 2 : 0, Z = c ? 2 : 0;  // the neighbour on the child's side
+    const double c000 = e[1][1][1];
+    const double c100 = e[1][1][X], c010 = e[1][Y][1], c001 = e[Z][1][1];
+    const double c110 = e[1][Y][X], c101 = e[Z][1][X], c011 = e[Z][Y][1];
+    const double c111 = e[Z][Y][X];
+    const double v = (27.0 * c000 + 9.0 * ((c100 + c010) + c001) + 3.0 * ((c110 + c101) + c011) +
+                      c111) *
+                     (1.0 / 64.0);
+    const unsigned f = at(g, 2 * I + a, 2 * J + b, 2 * K + c);
+    phi[f] = phi[f] + v;
+  }
 }
 
 // ---- g = -grad(phi) into the padded layout of a box covering the domain ----
@@ -236,16 +301,16 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ 
   // the periodic image of the padded cell in the domain
   auto wrapc = [](int x, unsigned n) { return (unsigned)(((x % (int)n) + (int)n) % (int)n); };
   const unsigned i = wrapc(pi - b.ng, g.nx), j = wrapc(pj - b.ng, g.ny), k = wrapc(pk - b.ng, g.nz);
-  const double gx = -(phi[at(g, wrap_inc(i, g.nx), j, k)] - phi[at(g, wrap_dec(i, g.nx), j, k)]) / two_dx;
-  const double gy = -(phi[at(g, i, wrap_inc(j, g.ny), k)] - phi[at(g, i, wrap_dec(j, g.ny), k)]) / two_dx;
-  const double gz = -(phi[at(g, i, j, wrap_inc(k, g.nz))] - phi[at(g, i, j, wrap_dec(k, g.nz))]) / two_dx;
+  const double gx = -(phi[nat(g, wrap_inc(i, g.nx), j, k)] - phi[nat(g, wrap_dec(i, g.nx), j, k)]) / two_dx;
+  const double gy = -(phi[nat(g, i, wrap_inc(j, g.ny), k)] - phi[nat(g, i, wrap_dec(j, g.ny), k)]) / two_dx;
+  const double gz = -(phi[nat(g, i, j, wrap_inc(k, g.nz))] - phi[nat(g, i, j, wrap_dec(k, g.nz))]) / two_dx;
   T* out = grav + b.goff;
   out[c] = (T)gx;
   out[b.gstride + c] = (T)gy;
   out[2 * b.gstride + c] = (T)gz;
 }
 
-unsigned blocks_for(unsigned long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+static unsigned blocks_for(unsigned long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 struct Level {
   Grid g;
@@ -254,7 +319,7 @@ struct Level {
   double* f;
 };
 
-int check_dom(const int32_t* dom) {
+static int check_dom(const int32_t* dom) {
   if (!dom) return NYX_E_NULL;
   unsigned long long n = 1;
   for (int d = 0; d < 3; ++d) {
@@ -267,7 +332,7 @@ int check_dom(const int32_t* dom) {
 
 // level sizes: halve while every extent stays even (red-black sweeps pair
 // the cells of a row), down to extents of 2
-std::vector<Grid> levels_of(const int32_t* dom) {
+static std::vector<Grid> levels_of(const int32_t* dom) {
   std::vector<Grid> L;
   Grid g{(unsigned)dom[0], (unsigned)dom[1], (unsigned)dom[2]};
   L.push_back(g);
@@ -278,23 +343,23 @@ std::vector<Grid> levels_of(const int32_t* dom) {
   return L;
 }
 
-size_t cells(const Grid& g) { return (size_t)g.nx * g.ny * g.nz; }
-size_t r256(size_t x) { return (x + 255) / 256 * 256; }
+static size_t cells(const Grid& g) { return (size_t)g.nx * g.ny * g.nz; }
+static size_t r256(size_t x) { return (x + 255) / 256 * 256; }
 
-// workspace: block partials, 8 scalars, the finest rhs, then phi and f of
-// every coarser level, each 256-byte aligned
+// workspace: block partials, 8 scalars, then phi and f of every level in the
+// solver's colour-split order, each 256-byte aligned
 constexpr size_t kOffScalars = (size_t)kRedBlocks * sizeof(double);
 constexpr size_t kOffLevels = kOffScalars + 256;
 
-size_t mg_bytes(const int32_t* dom) {
+static size_t mg_bytes(const int32_t* dom) {
   const auto L = levels_of(dom);
-  size_t b = kOffLevels + r256(cells(L[0]) * sizeof(double));
-  for (size_t l = 1; l < L.size(); ++l) b += 2 * r256(cells(L[l]) * sizeof(double));
+  size_t b = kOffLevels;
+  for (size_t l = 0; l < L.size(); ++l) b += 2 * r256(cells(L[l]) * sizeof(double));
   return b;
 }
 
 template <int MODE, int OP>
-void reduce(const RhoSrc& R, const double* phi, const double* f, const Grid& g, double inv_h2,
+static void reduce(const RhoSrc& R, const double* phi, const double* f, const Grid& g, double inv_h2,
             unsigned nb, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_partial<MODE>, dim3(nb), dim3(kBlock), 0, s, R, phi, f, g, inv_h2, part);
   hipLaunchKernelGGL(k_final<OP>, dim3(1), dim3(kBlock), 0, s, part, (int)nb, out);
@@ -302,7 +367,14 @@ void reduce(const RhoSrc& R, const double* phi, const double* f, const Grid& g, 
 
 constexpr int kPre = 2, kPost = 2, kCoarseSweeps = 32;
 
-hipError_t smooth(const Level& v, int iters, hipStream_t s) {
+// levels up to this many cells are smoothed by one workgroup
+constexpr size_t kSmallCells = 4096;
+
+static hipError_t smooth(const Level& v, int iters, hipStream_t s) {
+  if (cells(v.g) <= kSmallCells) {
+    hipLaunchKernelGGL(k_rbgs_small, dim3(1), dim3(kBlock), 0, s, v.phi, v.f, v.g, v.h2, iters);
+    return hipGetLastError();
+  }
   const unsigned nb = blocks_for((unsigned long long)(v.g.nx / 2) * v.g.ny * v.g.nz);
   for (int it = 0; it < iters; ++it)
     for (unsigned color = 0; color < 2; ++color)
@@ -310,7 +382,7 @@ hipError_t smooth(const Level& v, int iters, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t vcycle(std::vector<Level>& L, size_t l, hipStream_t s) {
+static hipError_t vcycle(std::vector<Level>& L, size_t l, hipStream_t s) {
   if (l + 1 == L.size()) return smooth(L[l], kCoarseSweeps, s);
   hipError_t e = smooth(L[l], kPre, s);
   if (e != hipSuccess) return e;
@@ -319,15 +391,16 @@ hipError_t vcycle(std::vector<Level>& L, size_t l, hipStream_t s) {
   hipLaunchKernelGGL(k_restrict, dim3(blocks_for(cells(c.g))), dim3(kBlock), 0, s, f.phi, f.f,
                      f.g, f.inv_h2, c.g, c.f, c.phi);
   if ((e = vcycle(L, l + 1, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(cells(f.g))), dim3(kBlock), 0, s, f.phi, f.g,
+  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(cells(c.g))), dim3(kBlock), 0, s, f.phi, f.g,
                      c.phi, c.g);
   return smooth(f, kPost, s);
 }
 
-}  // namespace
+}  // namespace grav
 }  // namespace nyx
 
 using namespace nyx;
+using namespace nyx::grav;
 
 extern "C" {
 
@@ -388,12 +461,8 @@ int nyx_poisson_solve(const int32_t* dom, double dx, double coef, const double* 
     L[l].g = G[l];
     L[l].h2 = h * h;
     L[l].inv_h2 = 1.0 / (h * h);
-    if (l == 0) {
-      L[l].phi = phi;
-    } else {
-      L[l].phi = (double*)w;
-      w += r256(cells(G[l]) * sizeof(double));
-    }
+    L[l].phi = (double*)w;
+    w += r256(cells(G[l]) * sizeof(double));
     L[l].f = (double*)w;
     w += r256(cells(G[l]) * sizeof(double));
     h *= 2.0;
@@ -403,7 +472,7 @@ int nyx_poisson_solve(const int32_t* dom, double dx, double coef, const double* 
   // right-hand side and its size
   reduce<0, 0>(R, F.phi, F.f, F.g, F.inv_h2, nb, part, scal + 0, s);
   hipLaunchKernelGGL(k_rhs, dim3(blocks_for(cells(F.g))), dim3(kBlock), 0, s, R, F.g, coef,
-                     scal + 0, F.f);
+                     scal + 0, F.f, phi, F.phi);
   if (hipGetLastError() != hipSuccess) return NYX_E_HIP;
   // with tol > 0 or a residual requested the stream is synchronised (once,
   // then once per V-cycle); otherwise only kernels are enqueued
@@ -431,7 +500,7 @@ int nyx_poisson_solve(const int32_t* dom, double dx, double coef, const double* 
   // the periodic problem fixes phi up to a constant: remove its mean
   reduce<3, 0>(R, F.phi, F.f, F.g, F.inv_h2, nb, part, scal + 3, s);
   hipLaunchKernelGGL(k_sub_mean, dim3(blocks_for(cells(F.g))), dim3(kBlock), 0, s, F.phi, F.g,
-                     scal + 3);
+                     scal + 3, phi);
   if (hipGetLastError() != hipSuccess) return NYX_E_HIP;
   if (vcycles) *vcycles = done;
   if (rel_resid) *rel_resid = rel;
