@@ -85,16 +85,20 @@ def bytes_per_launch(stage, n, rb):
 
 
 KERNEL_SOURCES = ("paper_1301_4498_amd/csrc/nyx_step.hip", "paper_1301_4498_amd/csrc/nyx_internal.h",
-                  "paper_1301_4498_amd/csrc/nyx_mlp_dev.h", "paper_1301_4498_amd/build.py")
+                  "paper_1301_4498_amd/csrc/nyx_mlp_dev.h")
 
 
 def kernel_source_hash():
-    """sha256 over the sources and build script of the stage kernels."""
+    """sha256 over the sources of the stage kernels and the compiler flags of
+    their two builds (other translation units of the library do not enter)."""
     import hashlib
+    from paper_1301_4498_amd import build as B
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    flags = [B.COMMON] + [u for u in B.UNITS if u[0] == "nyx_step.hip"]
+    h.update(repr(flags).encode())
     return h.hexdigest()
 
 
