@@ -38,6 +38,7 @@ struct FillTag {
 struct FillArgs {
   const FillTag* tags;
   const int* prefix;     // cells before each tag, ntags + 1 entries
+  const int* btag;       // per workgroup: the tag of its first cell
   int ntags;
   const BoxDev* fine;    // fine boxes
   const BoxDev* coarse;  // coarse boxes (interpolation)
@@ -46,19 +47,16 @@ struct FillArgs {
   int ncomp;
 };
 
-// The tag of this thread's cell (binary search of the cell prefix: every
-// lane takes one ghost cell of the concatenated tags, so small tags do not
-// leave lanes idle) and the cell's box-local coordinates; false for lanes
-// past the last cell.
+// The tag of this thread's cell and the cell's box-local coordinates; false
+// for lanes past the last cell.  Every lane takes one ghost cell of the
+// concatenated tags, so small tags do not leave lanes idle; the host stored
+// the tag of each workgroup's first cell, and a lane walks forward from it
+// (a workgroup's 256 cells span few tags).
 __device__ __forceinline__ bool fill_locate(const FillArgs& A, const FillTag** tag, int* loc) {
   const unsigned q = blockIdx.x * (unsigned)kBlock + threadIdx.x;
   if (q >= (unsigned)A.prefix[A.ntags]) return false;
-  int lo = 0, hi = A.ntags;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((unsigned)A.prefix[mid] <= q) lo = mid;
-    else hi = mid;
-  }
+  int lo = A.btag[blockIdx.x];
+  while ((unsigned)A.prefix[lo + 1] <= q) ++lo;
   const FillTag& t = A.tags[lo];
   *tag = &t;
   const unsigned r = q - (unsigned)A.prefix[lo];
@@ -160,6 +158,8 @@ struct nyx_fill_plan {
   FillTag* interp_tags = nullptr;
   int* copy_prefix = nullptr;
   int* interp_prefix = nullptr;
+  int* copy_btag = nullptr;
+  int* interp_btag = nullptr;
   size_t state_span = 0, cstate_span = 0;
 };
 
@@ -171,6 +171,7 @@ struct HostPlan {
   std::vector<BoxDev> fine, coarse;
   std::vector<FillTag> copy, interp;
   std::vector<int> copy_prefix, interp_prefix;
+  std::vector<int> copy_btag, interp_btag;
   long long copied = 0, interpolated = 0;
   size_t state_span = 0, cstate_span = 0;
 };
@@ -194,6 +195,20 @@ FillTag make_tag(int dst, int src, const int* lo, const int* ext, const int* shi
   t.dx = make_fastdiv((unsigned)ext[0]);
   t.dxy = make_fastdiv((unsigned)ext[0] * (unsigned)ext[1]);
   return t;
+}
+
+// the tag holding the first cell of each workgroup of a launch over the
+// prefix's cells
+void block_tags(const std::vector<int>& pre, std::vector<int>& btag) {
+  const int ntags = (int)pre.size() - 1;
+  const int nblocks = (pre.back() + kBlock - 1) / kBlock;
+  btag.assign(std::max(nblocks, 1), 0);
+  int t = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    const int q = b * kBlock;
+    while (t + 1 < ntags && pre[t + 1] <= q) ++t;
+    btag[b] = t;
+  }
 }
 
 // cells before each tag; the launch covers prefix.back() cells
@@ -396,6 +411,8 @@ int plan_level(int nbox, const nyx_box* boxes, const int32_t* lo, const int32_t*
   merge_rows(H.interp);
   if ((rc = prefix_of(H.copy, H.copy_prefix))) return rc;
   if ((rc = prefix_of(H.interp, H.interp_prefix))) return rc;
+  block_tags(H.copy_prefix, H.copy_btag);
+  block_tags(H.interp_prefix, H.interp_btag);
   return NYX_OK;
 }
 
@@ -403,7 +420,8 @@ size_t plan_bytes(const HostPlan& H) {
   return r256(sizeof(BoxDev) * H.fine.size()) + r256(sizeof(BoxDev) * std::max<size_t>(H.coarse.size(), 1)) +
          r256(sizeof(FillTag) * std::max<size_t>(H.copy.size(), 1)) +
          r256(sizeof(FillTag) * std::max<size_t>(H.interp.size(), 1)) +
-         r256(sizeof(int) * H.copy_prefix.size()) + r256(sizeof(int) * H.interp_prefix.size());
+         r256(sizeof(int) * H.copy_prefix.size()) + r256(sizeof(int) * H.interp_prefix.size()) +
+         r256(sizeof(int) * H.copy_btag.size()) + r256(sizeof(int) * H.interp_btag.size());
 }
 
 }  // namespace
@@ -444,6 +462,10 @@ int nyx_fill_plan_create(int nbox, const nyx_box* boxes, const int32_t* lo, cons
   p->copy_prefix = (int*)w;
   w += r256(sizeof(int) * H.copy_prefix.size());
   p->interp_prefix = (int*)w;
+  w += r256(sizeof(int) * H.interp_prefix.size());
+  p->copy_btag = (int*)w;
+  w += r256(sizeof(int) * H.copy_btag.size());
+  p->interp_btag = (int*)w;
   p->nbox = nbox;
   p->ncoarse = ncoarse;
   p->ncopy = (int)H.copy.size();
@@ -472,6 +494,12 @@ int nyx_fill_plan_create(int nbox, const nyx_box* boxes, const int32_t* lo, cons
   if (ok)
     ok = hipMemcpyAsync(p->interp_prefix, H.interp_prefix.data(),
                         sizeof(int) * H.interp_prefix.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+  if (ok)
+    ok = hipMemcpyAsync(p->copy_btag, H.copy_btag.data(), sizeof(int) * H.copy_btag.size(),
+                        hipMemcpyHostToDevice, s) == hipSuccess;
+  if (ok)
+    ok = hipMemcpyAsync(p->interp_btag, H.interp_btag.data(), sizeof(int) * H.interp_btag.size(),
+                        hipMemcpyHostToDevice, s) == hipSuccess;
   // the host vectors die with this call: the copies must have completed
   if (ok) ok = hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
@@ -509,6 +537,7 @@ int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_stat
   if (plan->ncopy > 0) {
     A.tags = plan->copy_tags;
     A.prefix = plan->copy_prefix;
+    A.btag = plan->copy_btag;
     A.ntags = plan->ncopy;
     hipLaunchKernelGGL(k_fill_copy, dim3(plan->copy_blocks), dim3(kBlock), 0, s, A);
     if (hipGetLastError() != hipSuccess) return NYX_E_HIP;
@@ -516,6 +545,7 @@ int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_stat
   if (plan->ninterp > 0) {
     A.tags = plan->interp_tags;
     A.prefix = plan->interp_prefix;
+    A.btag = plan->interp_btag;
     A.ntags = plan->ninterp;
     hipLaunchKernelGGL(k_fill_interp, dim3(plan->interp_blocks), dim3(kBlock), 0, s, A);
     if (hipGetLastError() != hipSuccess) return NYX_E_HIP;
