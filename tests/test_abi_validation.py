@@ -205,3 +205,56 @@ def test_two_level_sync_planning_errors(nyx):
     assert plan([((8, 8, 8), (12, 4, 4))], whole, (16, 16, 16)) == -2
     assert L.nyx_batch_set_flux_register(None, None, 0, None) == -1
     assert L.nyx_reflux(None, None, None, 6, None) == -1
+
+
+def test_gravity_entry_points_validate_before_launch(nyx):
+    # every refusal below happens on the host, before anything is enqueued
+    L = nyx.lib()
+    I = ctypes.c_int
+    dom = (I * 3)(16, 16, 16)
+    nb = ctypes.c_size_t(0)
+    assert L.nyx_poisson_workspace_bytes(dom, ctypes.byref(nb)) == 0 and nb.value > 16 ** 3 * 8
+    for bad in ((15, 16, 16), (0, 16, 16), (16, 16, 1 << 17)):
+        assert L.nyx_poisson_workspace_bytes((I * 3)(*bad), ctypes.byref(nb)) == -2
+    assert L.nyx_poisson_workspace_bytes(None, ctypes.byref(nb)) == -1
+    cyc, rel = ctypes.c_int(0), ctypes.c_double(0.0)
+    fake = 0x10000000  # never dereferenced: every call below is refused first
+    args = lambda **k: dict(dom=dom, dx=1 / 16, coef=1.0, rho=fake, state=None, box=None,
+                            phi=fake, tol=1e-10, cyc=40, ws=fake, wsb=nb.value, **k)
+
+    def solve(a):
+        return L.nyx_poisson_solve(a["dom"], a["dx"], a["coef"], a["rho"], a["state"], a["box"],
+                                   a["phi"], a["tol"], a["cyc"], a["ws"], a["wsb"], None,
+                                   ctypes.byref(cyc), ctypes.byref(rel))
+    L.nyx_poisson_workspace_bytes(dom, ctypes.byref(nb))
+    a = args()
+    a["dx"] = -1.0
+    assert solve(a) == -3
+    a = args()
+    a["cyc"] = 0
+    assert solve(a) == -3
+    a = args()
+    a["tol"] = float("nan")
+    assert solve(a) == -3
+    a = args()
+    a["wsb"] = nb.value - 8
+    assert solve(a) == -7
+    a = args()
+    a["ws"] = fake + 8  # misaligned
+    assert solve(a) == -7
+    a = args()
+    a["rho"] = None
+    assert solve(a) == -1
+    a = args()
+    a["state"] = fake  # a state without its box
+    assert solve(a) == -1
+    box = nyx.make_box((16, 16, 8), 4, 1 / 16)
+    a = args()
+    a["state"], a["box"] = fake, ctypes.byref(box)  # box does not cover the domain
+    assert solve(a) == -2
+    assert L.nyx_gravity_from_phi(dom, 1 / 16, fake, ctypes.byref(box), fake, 0, None) == -2
+    good = nyx.make_box((16, 16, 16), 4, 1 / 16)
+    assert L.nyx_gravity_from_phi(dom, 1 / 16, fake, ctypes.byref(good), fake, 7, None) == -3
+    assert L.nyx_cic_deposit(fake, fake, -1, dom, 1 / 16, fake, None) == -3
+    assert L.nyx_cic_deposit(fake, fake, 0, dom, 1 / 16, None, None) == -1
+    assert L.nyx_cic_deposit(fake, fake, 0, dom, 1 / 16, fake, None) == 0  # nothing to do
