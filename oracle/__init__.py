@@ -121,6 +121,9 @@ def lib():
         L.nyxo_fill_level.argtypes = [i, _I32, _I32, _I64, i, _I32, i, _D, i, _I32, _I32, _I64, i,
                                       _D, _I64, _I64]
         L.nyxo_fill_level.restype = i
+        L.nyxo_fill_level_time.argtypes = [i, _I32, _I32, _I64, i, _I32, i, _D, i, _I32, _I32,
+                                           _I64, i, _D, _D, d, _I64, _I64]
+        L.nyxo_fill_level_time.restype = i
         L.nyxo_hydro_step_faces.argtypes = [P, i, i, i, i, _D, _D, d, d, d, d, _D,
                                             ctypes.POINTER(_Stats), _D]
         L.nyxo_hydro_step_faces.restype = i
@@ -327,14 +330,16 @@ def mlp_loss_grad(params, x, y):
     return loss, g
 
 
-def fill_level(boxes, ng, dom, datas, coarse=None, ncomp=6):
+def fill_level(boxes, ng, dom, datas, coarse=None, ncomp=6, coarse_new=None, theta=0.0):
     """Ghost fill of one level (fill_oracle.c).  boxes: list of (n, lo) with
     n = (nx, ny, nz) and lo the global index of valid cell (0, 0, 0); datas:
     the boxes' padded arrays (ncomp, nz+2ng, ny+2ng, nx+2ng), filled in place
     (valid cells untouched); dom: the periodic domain (cells).  coarse: None
     or (cboxes, cng, cdatas) of the level below (ratio 2, ghosts filled).
     Returns (copied, interpolated) ghost-cell counts; raises if a ghost cell
-    is covered by neither level."""
+    is covered by neither level.  coarse_new (the coarse boxes' arrays at the
+    end of the coarse step) with theta in [0, 1]: the coarse data are
+    interpolated in time, old + theta (new - old) (subcycling, Sec. 4.2)."""
     def pack(bxs, arrs):
         n3 = np.ascontiguousarray([list(n) for n, _ in bxs], dtype=np.int32).ravel()
         lo3 = np.ascontiguousarray([list(lo) for _, lo in bxs], dtype=np.int32).ravel()
@@ -348,15 +353,19 @@ def fill_level(boxes, ng, dom, datas, coarse=None, ncomp=6):
     I32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     I64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     ncp, nip = ctypes.c_int64(0), ctypes.c_int64(0)
+    cnew = None
     if coarse is not None:
         cb, cng, cd = coarse
         cn3, clo3, coff, cflat, _ = pack(cb, cd)
         args = (len(cb), I32(cn3), I32(clo3), I64(coff), cng, _ptr(cflat))
+        if coarse_new is not None:
+            cnew = pack(cb, coarse_new)[3]
     else:
         args = (0, None, None, None, 1, None)
-    rc = lib().nyxo_fill_level(len(boxes), I32(n3), I32(lo3), I64(off), ng, I32(dom), ncomp,
-                               _ptr(flat), args[0], args[1], args[2], args[3], args[4], args[5],
-                               ctypes.byref(ncp), ctypes.byref(nip))
+    rc = lib().nyxo_fill_level_time(len(boxes), I32(n3), I32(lo3), I64(off), ng, I32(dom), ncomp,
+                                    _ptr(flat), args[0], args[1], args[2], args[3], args[4],
+                                    args[5], _ptr(cnew) if cnew is not None else None,
+                                    float(theta), ctypes.byref(ncp), ctypes.byref(nip))
     if rc == -2:
         raise ValueError("a ghost cell is covered by neither level (improper nesting)")
     if rc != 0:

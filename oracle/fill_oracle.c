@@ -30,10 +30,18 @@
  *   3. no other case exists for properly nested levels; the function then
  *      returns -2.
  * Valid cells are never written.
+ *
+ * Subcycling (Sec. 4.2): when the fine level takes several steps per coarse
+ * step, its ghost cells at an intermediate time take the coarse data
+ * interpolated linearly in time, U_c = U_old + theta (U_new - U_old) for
+ * every coarse value the profile reads (nyxo_fill_level_time; theta in
+ * [0, 1] is the fine time's fraction of the coarse step).
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+
+#include "nyx_oracle.h"
 
 typedef struct {
   int n[3], ng, lo[3];
@@ -85,19 +93,26 @@ static double mc_slope(double um, double u0, double up) {
   return 0.0;
 }
 
+/* coarse value at padded index i: the old data, or the old and new data
+ * interpolated in time */
+static double cval(const double* uo, const double* un, double theta, long i) {
+  return un ? uo[i] + theta * (un[i] - uo[i]) : uo[i];
+}
+
 /* limited linear value of coarse cell (I, J, K) (local to coarse box cb) at
  * the fine child with parities par[3] (0 = low child), component c */
-static double interp(const Lbox* cb, const double* cdata, int c, int I, int J, int K,
-                     const int* par) {
+static double interp(const Lbox* cb, const double* cdata, const double* cnew, double theta,
+                     int c, int I, int J, int K, const int* par) {
   const double* u = cdata + cb->off + (long)c * cb->P;
-  const double u0 = u[padded(cb, I, J, K)];
+  const double* un = cnew ? cnew + cb->off + (long)c * cb->P : NULL;
+  const double u0 = cval(u, un, theta, padded(cb, I, J, K));
   double s[3], lo = u0, hi = u0;
   for (int d = 0; d < 3; ++d) {
     int cm[3] = {I, J, K}, cp[3] = {I, J, K};
     cm[d] -= 1;
     cp[d] += 1;
-    double um = u[padded(cb, cm[0], cm[1], cm[2])];
-    double up = u[padded(cb, cp[0], cp[1], cp[2])];
+    double um = cval(u, un, theta, padded(cb, cm[0], cm[1], cm[2]));
+    double up = cval(u, un, theta, padded(cb, cp[0], cp[1], cp[2]));
     s[d] = mc_slope(um, u0, up);
     lo = fmin(lo, fmin(um, up));
     hi = fmax(hi, fmax(um, up));
@@ -121,6 +136,16 @@ int nyxo_fill_level(int nbox, const int32_t* n3, const int32_t* lo3, const int64
                     const int32_t* dom, int ncomp, double* data, int ncoarse,
                     const int32_t* cn3, const int32_t* clo3, const int64_t* coff, int cng,
                     const double* cdata, int64_t* n_copied, int64_t* n_interp) {
+  return nyxo_fill_level_time(nbox, n3, lo3, off, ng, dom, ncomp, data, ncoarse, cn3, clo3, coff,
+                              cng, cdata, NULL, 0.0, n_copied, n_interp);
+}
+
+int nyxo_fill_level_time(int nbox, const int32_t* n3, const int32_t* lo3, const int64_t* off,
+                         int ng, const int32_t* dom, int ncomp, double* data, int ncoarse,
+                         const int32_t* cn3, const int32_t* clo3, const int64_t* coff, int cng,
+                         const double* cdata, const double* cdata_new, double theta,
+                         int64_t* n_copied, int64_t* n_interp) {
+  if (cdata_new && !(theta >= 0.0 && theta <= 1.0)) return -1;
   if (nbox < 1 || !n3 || !lo3 || !off || !dom || !data || ng < 1 || ncomp < 1) return -1;
   for (int d = 0; d < 3; ++d)
     if (dom[d] < 2 || (dom[d] & 1)) return -1;
@@ -164,7 +189,8 @@ int nyxo_fill_level(int nbox, const int32_t* n3, const int32_t* lo3, const int64
           const Lbox* C = &cbx[cbi];
           for (int c = 0; c < ncomp; ++c)
             data[B->off + (long)c * B->P + dst] =
-                interp(C, cdata, c, G[0] - C->lo[0], G[1] - C->lo[1], G[2] - C->lo[2], par);
+                interp(C, cdata, cdata_new, theta, c, G[0] - C->lo[0], G[1] - C->lo[1],
+                       G[2] - C->lo[2], par);
           ni++;
         }
   }

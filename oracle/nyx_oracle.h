@@ -163,6 +163,15 @@ int nyxo_fill_level(int nbox, const int32_t* n3, const int32_t* lo3, const int64
                     const int32_t* cn3, const int32_t* clo3, const int64_t* coff, int cng,
                     const double* cdata, int64_t* n_copied, int64_t* n_interp);
 
+/* The same fill at an intermediate time of a subcycled fine level (Sec.
+ * 4.2): every coarse value the interpolation reads is cdata + theta
+ * (cdata_new - cdata), theta in [0, 1] (cdata_new = NULL: cdata alone). */
+int nyxo_fill_level_time(int nbox, const int32_t* n3, const int32_t* lo3, const int64_t* off,
+                         int ng, const int32_t* dom, int ncomp, double* data, int ncoarse,
+                         const int32_t* cn3, const int32_t* clo3, const int64_t* coff, int cng,
+                         const double* cdata, const double* cdata_new, double theta,
+                         int64_t* n_copied, int64_t* n_interp);
+
 #ifdef __cplusplus
 }
 #endif

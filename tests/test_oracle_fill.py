@@ -154,3 +154,51 @@ def test_copies_take_precedence_and_improper_nesting_is_an_error():
     # with no coarse level the open faces are covered by nothing
     with pytest.raises(ValueError):
         oracle.fill_level(boxes, NG, (24, 24, 24), [a.copy() for a in fdata], ncomp=1)
+
+
+def test_time_interpolation_of_the_coarse_data():
+    # subcycling (Sec. 4.2): with coarse data linear in space at the start and
+    # at the end of the coarse step, the ghost cells at fraction theta of the
+    # step are the linear field interpolated in time
+    cdom = (16, 16, 16)
+    K, J, I = np.meshgrid(*[np.arange(-NG, 16 + NG)] * 3, indexing="ij")
+    c0 = (0.7 + 0.11 * I - 0.05 * J + 0.031 * K)[None]
+    c1 = (1.3 - 0.02 * I + 0.09 * J + 0.017 * K)[None]
+    fine = [((8, 8, 8), (12, 10, 14))]
+    k, j, i = np.meshgrid(*[np.arange(-NG, 8 + NG)] * 3, indexing="ij")
+    lo = fine[0][1]
+    X = (lo[0] + i + 0.5) / 2 - 0.5
+    Y = (lo[1] + j + 0.5) / 2 - 0.5
+    Z = (lo[2] + k + 0.5) / 2 - 0.5
+    ghost = np.ones((16, 16, 16), bool)
+    ghost[NG:-NG, NG:-NG, NG:-NG] = False
+    for theta in (0.0, 0.25, 0.5, 1.0):
+        d = [np.zeros((1, 16, 16, 16))]
+        oracle.fill_level(fine, NG, (32, 32, 32), d, coarse=([(cdom, (0, 0, 0))], NG, [c0]),
+                          ncomp=1, coarse_new=[c1], theta=theta)
+        w0 = 0.7 + 0.11 * X - 0.05 * Y + 0.031 * Z
+        w1 = 1.3 - 0.02 * X + 0.09 * Y + 0.017 * Z
+        want = (1 - theta) * w0 + theta * w1
+        assert np.allclose(d[0][0][ghost], want[ghost], rtol=0, atol=1e-13), theta
+    # theta = 0 is the fill from the old data, bit for bit
+    a, b = [np.zeros((1, 16, 16, 16))], [np.zeros((1, 16, 16, 16))]
+    rng = np.random.default_rng(8)
+    r0 = np.exp(rng.normal(0, 1, (1,) + cdom))
+    r1 = np.exp(rng.normal(0, 1, (1,) + cdom))
+    p0, p1 = synth.pad_periodic(r0, NG), synth.pad_periodic(r1, NG)
+    oracle.fill_level(fine, NG, (32, 32, 32), a, coarse=([(cdom, (0, 0, 0))], NG, [p0]), ncomp=1)
+    oracle.fill_level(fine, NG, (32, 32, 32), b, coarse=([(cdom, (0, 0, 0))], NG, [p0]), ncomp=1,
+                      coarse_new=[p1], theta=0.0)
+    assert np.array_equal(a[0], b[0])
+    # the children of a coarse cell average to its time-interpolated value
+    c = [np.zeros((1, 16, 16, 16))]
+    oracle.fill_level(fine, NG, (32, 32, 32), c, coarse=([(cdom, (0, 0, 0))], NG, [p0]), ncomp=1,
+                      coarse_new=[p1], theta=0.3)
+    # coarse cell (5, 4, 6): children x 10..11, y 8..9, z 12..13 are ghosts of the fine box
+    kids = c[0][0, 12 - lo[2] + NG:14 - lo[2] + NG, 8 - lo[1] + NG:10 - lo[1] + NG,
+                10 - lo[0] + NG:12 - lo[0] + NG]
+    u = p0[0, 6 + NG, 4 + NG, 5 + NG] + 0.3 * (p1[0, 6 + NG, 4 + NG, 5 + NG] - p0[0, 6 + NG, 4 + NG, 5 + NG])
+    assert kids.shape == (2, 2, 2) and kids.mean() == pytest.approx(u, rel=1e-14)
+    with pytest.raises(ValueError):
+        oracle.fill_level(fine, NG, (32, 32, 32), c, coarse=([(cdom, (0, 0, 0))], NG, [p0]),
+                          ncomp=1, coarse_new=[p1], theta=1.5)
