@@ -495,9 +495,9 @@ def two_level_leg(nyx, torch, synth, w, log, steps=4):
     level of 64 boxes of 64^3 (periodic 256^3), and a fine level of 8 boxes
     of 64^3 over the central 128^3 of the 512^3 fine domain (the coarse data
     injected).  Per two-level step: coarse ghost fill, coarse step feeding
-    the flux register, fine ghost fill from the coarse level, two fine
-    substeps feeding the register (the second fine fill also from the old
-    coarse data: no time interpolation), reflux, average-down.  Reports
+    the flux register, coarse ghost fill of the new state, fine ghost fills
+    from the coarse level interpolated in time to each substep's start, two
+    fine substeps feeding the register, reflux, average-down.  Reports
     composite zone-updates/s (coarse cells + 2 x fine cells per step), the
     time of the sync kernels, and the composite mass change."""
     import numpy as np
@@ -561,9 +561,10 @@ def two_level_leg(nyx, torch, synth, w, log, steps=4):
         reg.zero_()
         cfill.fill(c)
         cbat.step(c, cg, dtc, a[2 * k], a[2 * k + 2], c2)
+        cfill.fill(c2)
         ffill.fill(f, c)
         fbat.step(f, fg, dtf, a[2 * k], a[2 * k + 1], f2)
-        ffill.fill(f2, c)
+        ffill.fill(f2, c, coarse_new=c2, theta=0.5)
         fbat.step(f2, fg, dtf, a[2 * k + 1], a[2 * k + 2], f)
         sync.reflux(c2, reg)
         sync.average_down(c2, f)

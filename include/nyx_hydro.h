@@ -276,6 +276,14 @@ int nyx_fill_plan_create(int nbox, const nyx_box* boxes, const int32_t* lo, cons
 int nyx_fill_plan_counts(const nyx_fill_plan* plan, long long* copied, long long* interpolated);
 int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_state, int ncomp,
                    void* stream);
+/* The same fill at an intermediate time of a subcycled fine level (Sec.
+ * 4.2): every coarse value the interpolation reads is
+ * coarse_state + theta (coarse_state_new - coarse_state), with theta in
+ * [0, 1] the fine time's fraction of the coarse step (else NYX_E_PARAM);
+ * coarse_state_new (device, the coarse level at the end of its step, same
+ * layout, ghosts filled) may be NULL, which is nyx_fill_level. */
+int nyx_fill_level_time(nyx_fill_plan* plan, double* state, const double* coarse_state,
+                        const double* coarse_state_new, double theta, int ncomp, void* stream);
 int nyx_fill_plan_destroy(nyx_fill_plan* plan);
 
 /* ---------------- two-level synchronisation (Sec. 4.3) ----------------

@@ -257,9 +257,11 @@ class FillPlan:
                                                                  ctypes.byref(i)))
         return c.value, i.value
 
-    def fill(self, state, coarse_state=None, ncomp=6, stream=None):
-        check("nyx_fill_level", lib().nyx_fill_level(self.handle, _ptr(state), _ptr(coarse_state),
-                                                     int(ncomp), _stream(stream)))
+    def fill(self, state, coarse_state=None, ncomp=6, stream=None, coarse_new=None, theta=0.0):
+        """coarse_new with theta: the coarse data interpolated in time (subcycling)."""
+        check("nyx_fill_level_time", lib().nyx_fill_level_time(
+            self.handle, _ptr(state), _ptr(coarse_state), _ptr(coarse_new), float(theta),
+            int(ncomp), _stream(stream)))
 
     def close(self):
         if self.handle is not None and self.handle.value:

@@ -113,6 +113,7 @@ def lib():
             "nyx_fill_plan_counts": (i, [vp, ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_longlong)]),
             "nyx_fill_level": (i, [vp, vp, vp, i, vp]),
+            "nyx_fill_level_time": (i, [vp, vp, vp, vp, d, i, vp]),
             "nyx_fill_plan_destroy": (i, [vp]),
             "nyx_batch_get_tuning": (i, [vp, ctypes.POINTER(i)]),
             "nyx_sync_plan_bytes": (i, [i, B, ctypes.POINTER(i), ctypes.POINTER(i), i, B,
@@ -156,7 +157,7 @@ def exported_symbols():
             "nyx_batch_set_harvest", "nyx_mlp_init", "nyx_mlp_loss_grad", "nyx_mlp_adam",
             "nyx_mlp_pack", "nyx_mlp_predict", "nyx_batch_autotune", "nyx_batch_set_tuning",
             "nyx_batch_get_tuning", "nyx_fill_plan_bytes", "nyx_fill_plan_create",
-            "nyx_fill_plan_counts", "nyx_fill_level", "nyx_fill_plan_destroy",
+            "nyx_fill_plan_counts", "nyx_fill_level", "nyx_fill_level_time", "nyx_fill_plan_destroy",
             "nyx_sync_plan_bytes", "nyx_sync_plan_create", "nyx_sync_plan_counts",
             "nyx_sync_plan_destroy", "nyx_batch_set_flux_register", "nyx_reflux",
             "nyx_average_down", "nyx_cic_deposit", "nyx_poisson_workspace_bytes",

@@ -44,6 +44,8 @@ struct FillArgs {
   const BoxDev* coarse;  // coarse boxes (interpolation)
   double* state;
   const double* cstate;
+  const double* cstate_new;  // or nullptr: coarse data interpolated in time
+  double theta;
   int ncomp;
 };
 
@@ -116,14 +118,23 @@ __global__ __launch_bounds__(kBlock) void k_fill_interp(FillArgs A) {
   const unsigned st[3] = {1u, (unsigned)C.px, (unsigned)C.px * (unsigned)C.py};
   // the coarse level is read-only here and lives apart from the fine state
   const double* __restrict__ cs = A.cstate;
+  const double* __restrict__ cn = A.cstate_new;
   double* __restrict__ fs = A.state;
+  const double th = A.theta;
   for (int c = 0; c < A.ncomp; ++c) {
-    const double* u = cs + C.soff + (long long)c * C.sstride;
-    const double u0 = ldu(u, c0);
+    const long long co = C.soff + (long long)c * C.sstride;
+    const double* u = cs + co;
+    const double* un = cn ? cn + co : nullptr;
+    // a coarse value, at the fraction theta of the coarse step when a new
+    // state is given (subcycling)
+    auto cv = [&](unsigned i) {
+      return un ? ldu(u, i) + th * (ldu(un, i) - ldu(u, i)) : ldu(u, i);
+    };
+    const double u0 = cv(c0);
     double s[3], lo = u0, hi = u0;
     for (int d = 0; d < 3; ++d) {
-      const double um = ldu(u, c0 - st[d]);
-      const double up = ldu(u, c0 + st[d]);
+      const double um = cv(c0 - st[d]);
+      const double up = cv(c0 + st[d]);
       s[d] = mc_slope(um, u0, up);
       lo = fmin(lo, fmin(um, up));
       hi = fmax(hi, fmax(um, up));
@@ -524,15 +535,23 @@ int nyx_fill_plan_counts(const nyx_fill_plan* plan, long long* copied, long long
 
 int nyx_fill_level(nyx_fill_plan* plan, double* state, const double* coarse_state, int ncomp,
                    void* stream) {
+  return nyx_fill_level_time(plan, state, coarse_state, nullptr, 0.0, ncomp, stream);
+}
+
+int nyx_fill_level_time(nyx_fill_plan* plan, double* state, const double* coarse_state,
+                        const double* coarse_state_new, double theta, int ncomp, void* stream) {
   if (!plan || !state) return NYX_E_NULL;
   if (ncomp < 1 || ncomp > 16) return NYX_E_PARAM;
   if (plan->ninterp > 0 && !coarse_state) return NYX_E_NULL;
+  if (coarse_state_new && !(theta >= 0.0 && theta <= 1.0)) return NYX_E_PARAM;
   hipStream_t s = (hipStream_t)stream;
   FillArgs A{};
   A.fine = plan->fine;
   A.coarse = plan->coarse;
   A.state = state;
   A.cstate = coarse_state;
+  A.cstate_new = coarse_state_new;
+  A.theta = theta;
   A.ncomp = ncomp;
   if (plan->ncopy > 0) {
     A.tags = plan->copy_tags;

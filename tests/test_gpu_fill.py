@@ -51,18 +51,21 @@ def _unpack(flat, arrays):
     return out
 
 
-def _gpu_fill(nyx, layout, arrays, dom, coarse=None):
-    """coarse: None or (clayout, carrays) with filled ghosts."""
+def _gpu_fill(nyx, layout, arrays, dom, coarse=None, coarse_new=None, theta=0.0):
+    """coarse: None or (clayout, carrays) with filled ghosts; coarse_new: the
+    coarse arrays at the end of the step (time interpolation by theta)."""
     boxes, flat = _pack(nyx, layout, arrays)
-    cplan_arg, cflat = None, None
+    cplan_arg, cflat, cnew = None, None, None
     if coarse is not None:
         clayout, carrays = coarse
         cboxes, cf = _pack(nyx, clayout, carrays, 2.0)
         cplan_arg = (cboxes, [lo for _, lo in clayout])
         cflat = to_dev(cf)
+        if coarse_new is not None:
+            cnew = to_dev(_pack(nyx, clayout, coarse_new, 2.0)[1])
     plan = nyx.FillPlan(boxes, [lo for _, lo in layout], dom, coarse=cplan_arg)
     T = to_dev(flat)
-    plan.fill(T, cflat, ncomp=arrays[0].shape[0])
+    plan.fill(T, cflat, ncomp=arrays[0].shape[0], coarse_new=cnew, theta=theta)
     import torch
     torch.cuda.synchronize()
     counts = plan.counts()
@@ -167,3 +170,25 @@ def test_full_size_patch_grid_reproduces_periodic_padding(nyx):
     torch.cuda.synchronize()
     assert torch.equal(T, want)
     plan.close()
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.25])
+def test_two_level_fill_in_time_matches_oracle(nyx, theta):
+    # subcycling: the coarse data at fraction theta of the coarse step
+    rng = np.random.default_rng(21)
+    dom = (32, 32, 32)
+    clayout = _split((16, 16, 16), [(8,), (8,), (8,)])
+    layout = [((8, 8, 8), (24, 0, 12)), ((6, 6, 6), (2, 2, 2)), ((10, 4, 6), (10, 20, 20))]
+    c0 = synth.pad_periodic(np.exp(rng.normal(0, 0.5, size=(6, 16, 16, 16))), NG)
+    c1 = synth.pad_periodic(np.exp(rng.normal(0, 0.5, size=(6, 16, 16, 16))), NG)
+    cut = lambda cp: [cp[:, lo[2]:lo[2] + n[2] + 8, lo[1]:lo[1] + n[1] + 8,
+                         lo[0]:lo[0] + n[0] + 8].copy() for n, lo in clayout]
+    arrays = _with_blank_ghosts(layout, 6, rng)
+    got, (nc, ni) = _gpu_fill(nyx, layout, arrays, dom, coarse=(clayout, cut(c0)),
+                              coarse_new=cut(c1), theta=theta)
+    ref = [a.copy() for a in arrays]
+    rc, ri = oracle.fill_level(layout, NG, dom, ref, coarse=(clayout, NG, cut(c0)),
+                               coarse_new=cut(c1), theta=theta)
+    assert (nc, ni) == (rc, ri) and ni > 0
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)

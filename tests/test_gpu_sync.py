@@ -2,7 +2,7 @@
 by the batched steps, nyx_reflux, nyx_average_down) against the oracle.  One
 coarse step of eight 8^3 boxes and two fine substeps of three fine boxes
 (with a fine-fine face and neighbours across the periodic boundary), fine
-ghosts filled from the coarse level at the old and at the mid time.  FP64:
+ghosts filled from the coarse level interpolated in time.  FP64:
 the synchronised coarse level and the fine level equal the oracle's bit for
 bit, with the plan split into one or several workspace groups; FP32-mixed:
 within 1e-5 relative L1, and its composite sums conserved."""
@@ -89,11 +89,10 @@ def _gpu_two_levels(nyx, prm, setup, dt_c, groups, a0=0.5, a1=0.505):
     cnew = cstate.clone()
     cbat.step(cstate, cgrav, dtc, a0, a1, cnew)
     cfill.fill(cnew)
-    cmid = 0.5 * (cstate + cnew)
-    ffill.fill(fstate, cstate)
+    ffill.fill(fstate, cstate, coarse_new=cnew, theta=0.0)
     f1 = fstate.clone()
     fbat.step(fstate, fgrav, dtf, a0, am, f1)
-    ffill.fill(f1, cmid)
+    ffill.fill(f1, cstate, coarse_new=cnew, theta=0.5)
     f2 = f1.clone()
     fbat.step(f1, fgrav, dtf, am, a1, f2)
     csync = cnew.clone()

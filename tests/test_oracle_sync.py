@@ -85,8 +85,8 @@ def composite_sums(cboxes, cdatas, fboxes, fdatas, cdom):
 
 def advance_two_levels(cboxes, cdatas, fboxes, fdatas, cdom, dom, a0=0.5, a1=0.505):
     """One coarse step over dt_c, two fine substeps over dt_c / 2, recording
-    face fluxes; fine ghosts come from the coarse level at the old time and
-    at the mid-time (mean of old and new).  Returns the new coarse data, the
+    face fluxes; fine ghosts come from the coarse level interpolated in time
+    to the start of each substep.  Returns the new coarse data, the
     new fine data and the flux blocks, all steps' counters."""
     cdx, fdx = 1.0 / cdom[0], 1.0 / dom[0]
     cd = [x.copy() for x in cdatas]
@@ -101,11 +101,12 @@ def advance_two_levels(cboxes, cdatas, fboxes, fdatas, cdom, dom, a0=0.5, a1=0.5
         stats.append(st)
     oracle.fill_level(cboxes, NG, cdom, cnew)
     am = 0.5 * (a0 + a1)
-    cmid = [0.5 * (x + y) for x, y in zip(cd, cnew)]
     fd = [x.copy() for x in fdatas]
     ffl, dt_f = [], []
-    for s, (aa, ab, crs) in enumerate(((a0, am, cd), (am, a1, cmid))):
-        oracle.fill_level(fboxes, NG, dom, fd, coarse=(cboxes, NG, crs))
+    for s, (aa, ab, theta) in enumerate(((a0, am, 0.0), (am, a1, 0.5))):
+        # fine ghosts from the coarse data at the fine time (subcycling)
+        oracle.fill_level(fboxes, NG, dom, fd, coarse=(cboxes, NG, cd), coarse_new=cnew,
+                          theta=theta)
         outs, fls = [], []
         for x in fd:
             out, st, fl = oracle.hydro_step(x, np.zeros((3,) + x.shape[1:]), NG, 0.5 * dt_c,
