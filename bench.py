@@ -557,30 +557,50 @@ def two_level_leg(nyx, torch, synth, w, log, steps=4):
         fv = synth.join_valid(fst.view(-1), (2, 2, 2), (m, m, m))[0].cpu().numpy()
         return 8.0 * (cv.sum() - cv[96:160, 96:160, 96:160].sum()) + fv.sum()
 
-    def two_level_step(k):
+    def two_level_step(k, src, dst):
+        """coarse src -> dst (synchronised in dst); the fine level returns to f"""
         reg.zero_()
-        cfill.fill(c)
-        cbat.step(c, cg, dtc, a[2 * k], a[2 * k + 2], c2)
-        cfill.fill(c2)
-        ffill.fill(f, c)
+        cfill.fill(src)
+        cbat.step(src, cg, dtc, a[2 * k], a[2 * k + 2], dst)
+        cfill.fill(dst)
+        ffill.fill(f, src)
         fbat.step(f, fg, dtf, a[2 * k], a[2 * k + 1], f2)
-        ffill.fill(f2, c, coarse_new=c2, theta=0.5)
+        ffill.fill(f2, src, coarse_new=dst, theta=0.5)
         fbat.step(f2, fg, dtf, a[2 * k + 1], a[2 * k + 2], f)
-        sync.reflux(c2, reg)
-        sync.average_down(c2, f)
-        c.copy_(c2)
+        sync.reflux(dst, reg)
+        sync.average_down(dst, f)
 
-    two_level_step(0)
+    bufs = [c, c2]
+    two_level_step(0, c, c2)
     torch.cuda.synchronize()
-    mass0 = composite_mass(c, f)
+    mass0 = composite_mass(c2, f)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(1, steps + 1):
-        two_level_step(k)
+        two_level_step(k, bufs[k % 2], bufs[(k + 1) % 2])
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    mass1 = composite_mass(c, f)
+    mass1 = composite_mass(bufs[(steps + 1) % 2], f)
+    # the same two-level steps replayed as one captured HIP graph (two steps,
+    # the coarse state ping-ponging between the buffers)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            two_level_step(1, c, c2)
+            two_level_step(2, c2, c)
+    graph.replay()
+    torch.cuda.synchronize()
+    reps_g = max(steps // 2, 1)
+    e0.record()
+    for _ in range(reps_g):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / (2 * reps_g)
+    del graph
     cells = 64 * m ** 3 + 2 * 8 * m ** 3
     # the sync kernels alone
     reps = 10
@@ -594,11 +614,13 @@ def two_level_leg(nyx, torch, synth, w, log, steps=4):
     out = {"coarse": "64 x 64^3 (256^3 periodic)", "fine": "8 x 64^3 over the central 128^3",
            "interface_faces": nfaces, "reflux_cells": ncells, "covered_cells": ncov,
            "ms_per_two_level_step": ms, "zone_updates_per_s": cells / (ms * 1e-3),
+           "graph_ms_per_two_level_step": graph_ms,
+           "graph_zone_updates_per_s": cells / (graph_ms * 1e-3),
            "sync_ms": sync_ms, "sync_frac": sync_ms / ms,
            "composite_mass_rel_change": abs(mass1 - mass0) / abs(mass0)}
-    log("two-level step: %.3f ms, %.3e zone-updates/s, reflux + average-down %.4f ms, composite "
-        "mass change %.1e" % (ms, out["zone_updates_per_s"], sync_ms,
-                              out["composite_mass_rel_change"]))
+    log("two-level step: %.3f ms, %.3e zone-updates/s (graph replay %.3f ms), reflux + "
+        "average-down %.4f ms, composite mass change %.1e"
+        % (ms, out["zone_updates_per_s"], graph_ms, sync_ms, out["composite_mass_rel_change"]))
     fbat.set_flux_register(None, 1, None)
     cbat.set_flux_register(None, 0, None)
     for x in (cfill, ffill, cbat, fbat, sync):
