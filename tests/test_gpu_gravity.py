@@ -150,3 +150,14 @@ def test_poisson_256_meets_tolerance(nyx):
     err = np.sqrt(((got - ref) ** 2).sum())
     assert err <= 1.01 * np.sqrt((r ** 2).sum()) / _lam_min(shape, dx) + \
         1e-12 * np.sqrt((ref ** 2).sum())
+
+
+def test_uniform_density_gives_zero_potential(nyx):
+    import torch
+    shape, dx = (16, 16, 16), 1.0 / 16
+    solver = nyx.PoissonSolver((16, 16, 16))
+    rho = torch.full(shape, 2.5, dtype=torch.float64, device="cuda")
+    phi = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    cyc, rel = solver.solve(rho, phi, dx, 3.0, tol=1e-12, max_vcycles=40)
+    assert cyc == 1 and rel == 0.0
+    assert torch.count_nonzero(phi).item() == 0

@@ -284,3 +284,34 @@ def test_two_level_cycle_graph_replay_matches_eager(nyx, reference):
     cbat.set_flux_register(None, 0, None)
     for x in (cfill, ffill, cbat, fbat, sync):
         x.close()
+
+
+def test_fp64_sync_fine_slab_spanning_the_periodic_axis(nyx):
+    # a fine box that spans the whole domain along x: no interface faces
+    # across x (its x neighbours are its own periodic images)
+    setup = list(_random_layout(41))
+    cboxes, cdatas, _, _, cdom, dom = setup
+    rng = np.random.default_rng(41)
+    fboxes = [((32, 8, 6), (0, 10, 12))]
+    shape = cdom[::-1]
+    Uc = synth.conserved(synth.lognormal(rng, shape, 1.0, 0.5), rng.normal(0, 0.3, (3,) + shape),
+                         synth.lognormal(rng, shape, 0.6, 0.3), 0.5)
+    for (n, lo), a in zip(cboxes, cdatas):
+        _valid(a)[...] = Uc[:, lo[2]:lo[2] + n[2], lo[1]:lo[1] + n[1], lo[0]:lo[0] + n[0]]
+    n, lo = fboxes[0]
+    a = np.zeros((6,) + tuple(x + 2 * NG for x in n[::-1]))
+    cl = [x // 2 for x in lo]
+    blk = Uc[:, cl[2]:cl[2] + n[2] // 2, cl[1]:cl[1] + n[1] // 2, cl[0]:cl[0] + n[0] // 2]
+    _valid(a)[...] = blk.repeat(2, axis=1).repeat(2, axis=2).repeat(2, axis=3)
+    setup = (cboxes, cdatas, fboxes, [a], cdom, dom)
+    cnew, fnew, cflux, ffl, dt_c, dt_f, _ = advance_two_levels(*setup)
+    csync = [x.copy() for x in cnew]
+    nf, nc = oracle.reflux_average_down(cboxes, NG, 1.0 / cdom[0], csync, cflux, dt_c, fboxes,
+                                        NG, dom, fnew, ffl, dt_f)
+    assert nf == 2 * (16 * 3) + 2 * (16 * 4)  # y and z faces of the 16 x 4 x 3 coarse slab
+    got_c, got_f, counts = _gpu_two_levels(nyx, nyx.default_params(), setup, dt_c, False)
+    assert counts[0] == nf and counts[2] == nc
+    for x, y in zip(got_f, fnew):
+        assert np.array_equal(_valid(x), _valid(y))
+    for x, y in zip(got_c, csync):
+        assert np.array_equal(_valid(x), _valid(y))
