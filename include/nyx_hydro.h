@@ -7,7 +7,10 @@
  * the conservative update with the expansion-factor and gravity sources, the
  * gravity corrector and the dual-energy sync (Sec. 3.2 Gas Dynamics, Sec. 3.6
  * Single-Level Integration Algorithm, Steps 2 and 6), and the hydro CFL time
- * step (Sec. 3.5).
+ * step (Sec. 3.5).  Around the step it provides the level operations that
+ * prepare its inputs and follow it: the ghost fill of an AMR level (Sec. 4.1,
+ * with time interpolation for subcycling, Sec. 4.2), the two-level reflux and
+ * average-down (Sec. 4.3) and the mesh side of the gravity input (Sec. 3.4).
  *
  * Conventions shared by every entry point
  *  - State U (Sec. 3.2): 6 components (rho, a rho U_x, a rho U_y, a rho U_z,
@@ -27,7 +30,10 @@
  *    sizes are queried first and passed in.  Host pointers are read during
  *    the call only.
  *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
- *    only enqueue work; nothing synchronises the host.
+ *    only enqueue work, except where an entry point says it synchronises
+ *    (plan creation, autotuning, the Poisson solve's convergence checks).
+ *    A plan and its workspace serve one stream at a time: calls on one plan
+ *    that overlap on two streams race on its workspace.
  *  - Errors: argument errors return a negative nyx_status before anything is
  *    enqueued.  Conditions met on the device (non-finite values, rho <= 0,
  *    floors, rejected transverse corrections, learned-flux fallbacks) are only
