@@ -721,9 +721,18 @@ def cpu_baseline(w, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": m ** 3 * nstep / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
             "sample": "%d step(s) of a 64^3 cut (+4 ghosts) of the same 256^3 fields, one thread"
-                      % nstep}
+                      % nstep,
+            "host": {"cpu_model": model, "nproc": os.cpu_count(),
+                     "usable_cpus": len(os.sched_getaffinity(0))}}
 
 
 def main():
