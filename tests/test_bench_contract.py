@@ -1,0 +1,34 @@
+"""Host-side checks of the benchmark's contract (no GPU): more than one GPU
+is refused with a message; the roofline traffic record is keyed to the
+stage kernels' sources; the per-launch byte table covers every stage."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_record_matches_the_kernel_sources():
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_riem1_box256_mixed.json")))
+    assert rec["sources_sha256"] == bench.kernel_source_hash()
+    t = bench.measured_traffic("riem1", "mixed")
+    assert t is not None and t > 0
+    assert bench.measured_traffic("riem1", "fp64") is None
+
+
+def test_bytes_per_launch_for_every_stage():
+    import bench
+    for st in ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update"):
+        assert bench.bytes_per_launch(st, 256, 4) > 0
+        assert bench.bytes_per_launch(st, 256, 8) > bench.bytes_per_launch(st, 256, 4)
