@@ -172,7 +172,7 @@ def test_full_size_patch_grid_reproduces_periodic_padding(nyx):
     plan.close()
 
 
-@pytest.mark.parametrize("theta", [0.5, 0.25])
+@pytest.mark.parametrize("theta", [0.0, 0.25, 0.5, 1.0])
 def test_two_level_fill_in_time_matches_oracle(nyx, theta):
     # subcycling: the coarse data at fraction theta of the coarse step
     rng = np.random.default_rng(21)
