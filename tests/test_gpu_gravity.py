@@ -53,6 +53,16 @@ def test_cic_deposit_matches_oracle(nyx):
     assert np.allclose(rho.cpu().numpy(), ref2, rtol=1e-13, atol=0)
 
 
+
+def test_cic_deposit_of_no_particles_is_a_no_op(nyx):
+    import torch
+    rho = torch.full((4, 6, 8), 1.5, dtype=torch.float64, device="cuda")
+    empty = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    nyx.cic_deposit(empty, torch.zeros(0, dtype=torch.float64, device="cuda"), (8, 6, 4),
+                    0.125, rho)
+    torch.cuda.synchronize()
+    assert torch.equal(rho, torch.full_like(rho, 1.5))
+
 def _resid_ok(r, f, phi, dx, tol):
     """max|r| within tol max|f| plus the rounding of evaluating the 7-point
     residual in another order (terms of size 6 max|phi| / dx^2)."""

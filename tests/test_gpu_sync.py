@@ -172,6 +172,12 @@ def _random_layout(seed):
             continue
         used[sl] = True
         fboxes.append((n, lo))
+    return _fields(rng, cboxes, fboxes, cdom, dom)
+
+
+def _fields(rng, cboxes, fboxes, cdom, dom):
+    """Fields of the layout as in two_level_setup: a random coarse state, the
+    fine level injected from it with a perturbed density."""
     shape = cdom[::-1]
     rho = synth.lognormal(rng, shape, 1.0, 0.5)
     u = rng.normal(0.0, 0.3, (3,) + shape)
@@ -211,6 +217,32 @@ def test_fp64_sync_random_layouts_bitwise(nyx, seed):
     for a, b in zip(got_c, csync):
         assert np.array_equal(_valid(a), _valid(b))
 
+
+
+def test_fp64_fine_level_covering_the_domain(nyx):
+    """The degenerate layout with no coarse-fine interface: the fine level
+    covers the whole domain, so the plan has no register faces and no reflux
+    cells, every fine ghost is a copy, and the synchronisation is the
+    average-down alone; still equal to the oracle bit for bit."""
+    rng = np.random.default_rng(35)
+    cdom, dom = (8, 12, 8), (16, 24, 16)
+    cboxes = [((8, 12, 4), (0, 0, 0)), ((8, 12, 4), (0, 0, 4))]
+    fboxes = [((16, 24, 6), (0, 0, 0)), ((16, 24, 4), (0, 0, 6)), ((16, 24, 6), (0, 0, 10))]
+    setup = _fields(rng, cboxes, fboxes, cdom, dom)
+    cboxes, cdatas, fboxes, fdatas, cdom, dom = setup
+    print("fine level covering the domain", flush=True)
+    cnew, fnew, cflux, ffl, dt_c, dt_f, _ = advance_two_levels(cboxes, cdatas, fboxes, fdatas,
+                                                               cdom, dom)
+    csync = [x.copy() for x in cnew]
+    nf, nc = oracle.reflux_average_down(cboxes, NG, 1.0 / cdom[0], csync, cflux, dt_c, fboxes,
+                                        NG, dom, fnew, ffl, dt_f)
+    assert nf == 0 and nc == 8 * 12 * 8
+    got_c, got_f, counts = _gpu_two_levels(nyx, nyx.default_params(), setup, dt_c, False)
+    assert counts == (0, 0, nc)
+    for a, b in zip(got_f, fnew):
+        assert np.array_equal(_valid(a), _valid(b))
+    for a, b in zip(got_c, csync):
+        assert np.array_equal(_valid(a), _valid(b))
 
 def test_two_level_cycle_graph_replay_matches_eager(nyx, reference):
     """Two two-level cycles (coarse fills and step feeding the register, fine
