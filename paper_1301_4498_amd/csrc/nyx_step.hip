@@ -501,17 +501,26 @@ __device__ __forceinline__ double rsq64(double x) {
   double r = fma(-h, y, 1.0);
   return fma(0.5 * y, r, y);
 }
+// Raw hardware estimates (relative error below 2^-24, FP64 range) for
+// quantities that only scale a Newton step or feed the FP32-stored sample of
+// the wave fan.
+__device__ __forceinline__ double rcp_est(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ double rsq_est(double x) { return __builtin_amdgcn_rsq(x); }
 
 // The two-shock Newton iteration, rearranged so that each evaluation needs
 // one reciprocal and two reciprocal square roots: with
 // X_K = W_K^2 = C_K + (gamma+1)/2 rho_K (p - p_K) and w_K = 1/W_K,
 //   u*_L = u_L - (p - p_L) w_L,  u*_R = u_R + (p - p_R) w_R,
-//   1/Z_K = (X_K + C_K) w_K^3 / 2,
+//   1/Z_K = (X_K + C_K) w_K^3 / 2 = w_K (1/2 + (C_K/2) w_K^2),
 //   p' = p - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
 //   u* = (u*_L / Z_R + u*_R / Z_L) / (1/Z_L + 1/Z_R),
 //   1/rho*_K = 1/rho_K - (p* - p_K) w_K^2.
+// The converged pressure is the root of u*_R - u*_L, which takes the refined
+// w_K; the slope 1/Z_L + 1/Z_R only scales the step, so its reciprocal is the
+// raw estimate: a relative error of 2^-24 in a step that the stopping rule
+// bounds by 2^-12 p moves p' by less than 2^-36 p.
 struct TwoShock {
-  double gam, sp, rl, ul, pl, rr, ur, pr, CL, CR, gl, gr;
+  double gam, sp, rl, ul, pl, rr, ur, pr, CL, CR, hCL, hCR, gl, gr;
 };
 struct TwoShockEval {
   double XL, XR, wL, wR, usL, usR, zL, zR;
@@ -525,6 +534,8 @@ __device__ __forceinline__ TwoShock ts_setup(const StepArgs& A, const double* qL
   t.rr = qR[0]; t.ur = qR[1]; t.pr = qR[4];
   t.CL = (t.gam * t.pl) * t.rl;
   t.CR = (t.gam * t.pr) * t.rr;
+  t.hCL = 0.5 * t.CL;
+  t.hCR = 0.5 * t.CR;
   const double g2 = 0.5 * (t.gam + 1.0);
   t.gl = g2 * t.rl;
   t.gr = g2 * t.rr;
@@ -538,18 +549,14 @@ __device__ __forceinline__ TwoShockEval ts_eval(const TwoShock& t, double p) {
   e.wR = rsq64(e.XR);
   e.usL = t.ul - (p - t.pl) * e.wL;
   e.usR = t.ur + (p - t.pr) * e.wR;
-  e.zL = 0.5 * (e.XL + t.CL) * (e.wL * e.wL * e.wL);
-  e.zR = 0.5 * (e.XR + t.CR) * (e.wR * e.wR * e.wR);
+  e.zL = (0.5 + t.hCL * (e.wL * e.wL)) * e.wL;
+  e.zR = (0.5 + t.hCR * (e.wR * e.wR)) * e.wR;
   return e;
 }
+// fmax is the floor max(p', small_pres): small_pres is never NaN
 __device__ __forceinline__ double ts_newton(const TwoShock& t, const TwoShockEval& e, double p) {
-  return vmax(p - (e.usR - e.usL) * rcp64(e.zL + e.zR), t.sp);
+  return fmax(p - (e.usR - e.usL) * rcp_est(e.zL + e.zR), t.sp);
 }
-// Raw hardware estimates (relative error below 2^-24, FP64 range) for the
-// quantities that only feed the FP32-stored sample of the wave fan.
-__device__ __forceinline__ double rcp_est(double x) { return __builtin_amdgcn_rcp(x); }
-__device__ __forceinline__ double rsq_est(double x) { return __builtin_amdgcn_rsq(x); }
-
 // The two-shock relations at the converged pressure for the sample: the same
 // expressions as ts_eval with estimate-only reciprocal square roots.
 __device__ __forceinline__ TwoShockEval ts_eval_est(const TwoShock& t, double p) {
@@ -560,8 +567,8 @@ __device__ __forceinline__ TwoShockEval ts_eval_est(const TwoShock& t, double p)
   e.wR = rsq_est(e.XR);
   e.usL = t.ul - (p - t.pl) * e.wL;
   e.usR = t.ur + (p - t.pr) * e.wR;
-  e.zL = 0.5 * (e.XL + t.CL) * (e.wL * e.wL * e.wL);
-  e.zR = 0.5 * (e.XR + t.CR) * (e.wR * e.wR * e.wR);
+  e.zL = (0.5 + t.hCL * (e.wL * e.wL)) * e.wL;
+  e.zR = (0.5 + t.hCR * (e.wR * e.wR)) * e.wR;
   return e;
 }
 
