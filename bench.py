@@ -102,17 +102,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, form):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    record (profiles/traffic_*.json), or None when that record was taken on
-    different kernel sources."""
+def measured_traffic(kernel, form, candidate):
+    """HBM bytes per launch of `kernel` under launch-order candidate
+    `candidate` (the autotuner's choice for its stage) from the committed
+    rocprofv3 counter record (profiles/traffic_*.json), or None when that
+    record was taken on different kernel sources.  The record holds one value
+    per candidate: the cell order changes how often neighbours are re-read
+    from HBM, so the traffic of one order says nothing of another."""
     import glob
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         with open(path) as fh:
             rec = json.load(fh)
         if (rec.get("kernel") == kernel and rec.get("form") == form and
                 rec.get("sources_sha256") == kernel_source_hash()):
-            return rec["bytes_per_launch"]
+            return rec["bytes_per_launch_by_candidate"][candidate]
     return None
 
 
@@ -834,7 +837,7 @@ def main():
         roof, other = alu, hbm
     else:
         roof, other = hbm, alu
-    t = measured_traffic(dom, chosen)
+    t = measured_traffic(dom, chosen, R["tuning"][STAGES.index(dom)])
     roof["traffic"] = t
     other["traffic"] = t
     out = {

@@ -209,14 +209,14 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
 // ---------------------------------------------------------------------------
 // stage 3: PPM (O3) and characteristic tracing (O4)
 // ---------------------------------------------------------------------------
+// Under dr dl > 0 neither dl nor dr is NaN, so fmin (one instruction) takes
+// the same value as the compare-and-select minimum, infinite slopes included.
 __device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
   real dc = (real)0.5 * (qp1 - qm1);
   real dr = qp1 - q0;
   real dl = q0 - qm1;
   if (dr * dl > (real)0) {
-    real m = fabs(dc);
-    m = vmin(m, (real)2 * fabs(dl));
-    m = vmin(m, (real)2 * fabs(dr));
+    const real m = fmin(fmin(fabs(dc), (real)2 * fabs(dl)), (real)2 * fabs(dr));
     return dc > (real)0 ? m : -m;
   }
   return (real)0;
@@ -305,7 +305,7 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
   real ap = (real)0.5 * (D[2][2] * icsq + (rho * D[2][1]) * ic);
   real a0 = D[1][0] - D[1][2] * icsq;
   out[0] = ref[0] - ((am + a0) + ap);
-  out[nv] = ref[1] - (c * ((real)1 / rho)) * (ap - am);
+  out[nv] = ref[1] - (c * __builtin_amdgcn_rcpf(rho)) * (ap - am);
 #else
   real am = (real)0.5 * (D[0][2] / csq - (rho * D[0][1]) / c);
   real ap = (real)0.5 * (D[2][2] / csq + (rho * D[2][1]) / c);
@@ -339,19 +339,24 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
     const real* prim = (const real*)A.work + b.w_prim;
     const unsigned c0 = pidx_e(b, ie, je, ke);
     const unsigned s = d == 0 ? 1u : (d == 1 ? (unsigned)b.px : (unsigned)b.px * (unsigned)b.py);
+    // every load of the cell is issued before any arithmetic, so a wave
+    // waits once for all of them instead of once per variable
     const real chi = ldu((const real*)A.work + b.w_chi, e);
+    real qs[5][5];
+    for (int v = 0; v < 5; ++v)
+      for (int o = -2; o <= 2; ++o) qs[v][o + 2] = ldu(prim + v * b.P + (long long)o * s, c0);
+    const real c = ldu(prim + 5 * b.P, c0);
+    const real* G = (const real*)A.grav + b.goff;
+    const real g[3] = {ldu(G, c0), ldu(G + b.gstride, c0), ldu(G + 2 * b.gstride, c0)};
     real qc[5], qm[5], qp[5], dq[5], q6[5];
     for (int v = 0; v < 5; ++v) {
-      const real* Q = prim + v * b.P;
-      real q5[5];
-      for (int o = -2; o <= 2; ++o) q5[o + 2] = ldu(Q + (long long)o * s, c0);
+      const real* q5 = qs[v];
       qc[v] = q5[2];
       if (A.recon == NYX_RECON_PLM) plm_edges(q5, chi, qm[v], qp[v]);
       else ppm_edges(q5, chi, qm[v], qp[v]);
       dq[v] = qp[v] - qm[v];
       q6[v] = (real)6 * qc[v] - (real)3 * (qm[v] + qp[v]);
     }
-    const real c = ldu(prim + 5 * b.P, c0);
     const int nv = 1 + d, t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
     const real u = qc[nv];
     real lam[3] = {u - c, u, u + c};
@@ -362,8 +367,6 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
     trace_side<+1>(qc, c, qp, dq, q6, lam, sig, nv, t1, t2, hi);
     trace_side<-1>(qc, c, qm, dq, q6, lam, sig, nv, t1, t2, lo);
     // half-step gravity and expansion sources, then floors
-    const real* G = (const real*)A.grav + b.goff;
-    real g[3] = {ldu(G, c0), ldu(G + b.gstride, c0), ldu(G + 2 * b.gstride, c0)};
     const real hdt_a = (real)C.hdt_a, hda_a = (real)C.hda_a, pexp = (real)C.pexp;
     const real sd_ = (real)A.small_dens, sp_ = (real)A.small_pres;
     real* out[2] = {lo, hi};
@@ -786,13 +789,19 @@ __device__ __forceinline__ void store_god(real* G, long long E, unsigned i, cons
   stu(G + 4 * E, i, (real)g.p);
 }
 
-// O6: lab-frame fluxes of a d-face from its stored Godunov state (flux
-// arithmetic in real): f = (f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g).
-__device__ __forceinline__ void face_flux(double gamma, int d, const real* G, long long E,
-                                          unsigned i, real* f) {
+// A stored Godunov state of a face, in the rotated frame of that face.
+struct God {
+  real r, u, v, w, p;
+};
+__device__ __forceinline__ God ld_god(const real* G, long long E, unsigned i) {
+  return God{ldu(G, i), ldu(G + E, i), ldu(G + 2 * E, i), ldu(G + 3 * E, i), ldu(G + 4 * E, i)};
+}
+
+// O6: lab-frame fluxes of a d-face from its Godunov state (flux arithmetic
+// in real): f = (f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g).
+__device__ __forceinline__ void face_flux(double gamma, int d, const God& g, real* f) {
   const real gm1 = (real)(gamma - 1.0);
-  const real r = ldu(G, i), u = ldu(G + E, i), v = ldu(G + 2 * E, i), w = ldu(G + 3 * E, i),
-             p = ldu(G + 4 * E, i);
+  const real r = g.r, u = g.u, v = g.v, w = g.w, p = g.p;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const real ru = r * u;
   f[0] = ru;
@@ -812,6 +821,10 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const real* G, lo
   f[6] = p;
   f[7] = u;
 }
+__device__ __forceinline__ void face_flux(double gamma, int d, const real* G, long long E,
+                                          unsigned i, real* f) {
+  face_flux(gamma, d, ld_god(G, E, i), f);
+}
 
 __device__ __forceinline__ void e_coords(const BoxDev& b, unsigned e, int* c) {
   space_coords(b, kSpaceE, e, c);
@@ -829,11 +842,11 @@ __device__ __forceinline__ unsigned e_stride(const BoxDev& b, int d) {
 // at the low and high t-faces of a cell) to Dc, De; the first direction sets
 // them, a second one is added, in that order
 template <bool FIRST>
-__device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, const real* Ghi,
-                                      unsigned i, long long E, double* Dc, double& De) {
+__device__ __forceinline__ void tdiff(double gamma, int t, const God& glo, const God& ghi,
+                                      double* Dc, double& De) {
   real fm[8], fp[8];
-  face_flux(gamma, t, Glo, E, i, fm);
-  face_flux(gamma, t, Ghi, E, i, fp);
+  face_flux(gamma, t, glo, fm);
+  face_flux(gamma, t, ghi, fp);
 #if defined(NYX_PREC_MIXED)
   // flux differences are flux arithmetic: FP32, widened once
   for (int c = 0; c < 5; ++c) {
@@ -850,6 +863,11 @@ __device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, cons
                     (0.5 * ((double)fp[6] + (double)fm[6])) * ((double)fp[7] - (double)fm[7]);
 #endif
   De = FIRST ? de : De + de;
+}
+template <bool FIRST>
+__device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, const real* Ghi,
+                                      unsigned i, long long E, double* Dc, double& De) {
+  tdiff<FIRST>(gamma, t, ld_god(Glo, E, i), ld_god(Ghi, E, i), Dc, De);
 }
 
 __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q,
@@ -1135,15 +1153,26 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
     const real* W = (const real*)A.work + b.w_edge;
     const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
     const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
-    double qs[2][5];
+    // both cells' loads are issued before any arithmetic, so a wave waits
+    // once for all of them
+    real qe[2][5];
+    God ga[2][2], gb[2][2];
     for (int s = 0; s < 2; ++s) {
       const long long sh = s == 0 ? -sdd : 0;  // cell shift in the bases, offset e
       const int side = s == 0 ? 1 : 0;
+      for (int v = 0; v < 5; ++v) qe[s][v] = ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
+      ga[s][0] = ld_god(G1a + sh, b.E, e);
+      ga[s][1] = ld_god(G1a + sh + s1, b.E, e);
+      gb[s][0] = ld_god(G1b + sh, b.E, e);
+      gb[s][1] = ld_god(G1b + sh + s2, b.E, e);
+    }
+    double qs[2][5];
+    for (int s = 0; s < 2; ++s) {
       double q[5];
-      for (int v = 0; v < 5; ++v) q[v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
+      for (int v = 0; v < 5; ++v) q[v] = (double)qe[s][v];
       double Dc[5], De;
-      tdiff<true>(A.gamma, t1, G1a + sh, G1a + sh + s1, e, b.E, Dc, De);   // t1-flux corrected by t2
-      tdiff<false>(A.gamma, t2, G1b + sh, G1b + sh + s2, e, b.E, Dc, De);  // t2-flux corrected by t1
+      tdiff<true>(A.gamma, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
+      tdiff<false>(A.gamma, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
       T.reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
     }
     rotate(d, qs[0], ql);
@@ -1190,9 +1219,8 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
 
 // O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
 // F_m = f_m, F_E = a_h f_E, F_e = a_h f_e; p_g and u_g kept for S_e.
-__device__ __forceinline__ void final_flux(double gamma, int d, const real* G, long long E,
-                                           unsigned i, real ah, real* f) {
-  face_flux(gamma, d, G, E, i, f);
+__device__ __forceinline__ void final_flux(double gamma, int d, const God& g, real ah, real* f) {
+  face_flux(gamma, d, g, f);
   f[0] = f[0] / ah;
   f[4] = ah * f[4];
   f[5] = ah * f[5];
@@ -1265,22 +1293,15 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
                        (unsigned)(i + 1);
     const real* G2 = (const real*)A.work + b.w_f2;
     const real ah = (real)C.a_h;
-    double D[6];
-    double Pi = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      const real* G = G2 + (long long)d * kGod * b.E;
-      real fl[8], fh[8];
-      final_flux(A.gamma, d, G, b.E, e, ah, fl);
-      final_flux(A.gamma, d, G + (long long)e_stride(b, d), b.E, e, ah, fh);
-      for (int c = 0; c < 6; ++c) {
-        double dF = (double)fh[c] - (double)fl[c];
-        D[c] = (d == 0) ? dF : D[c] + dF;
-      }
-      double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
-      Pi = (d == 0) ? pd : Pi + pd;
-    }
     const unsigned id = ((unsigned)(k + b.ng) * (unsigned)b.py + (unsigned)(j + b.ng)) *
                             (unsigned)b.px + (unsigned)(i + b.ng);
+    // every load of the cell is issued before any arithmetic
+    God gl[3], gh[3];
+    for (int d = 0; d < 3; ++d) {
+      const real* G = G2 + (long long)d * kGod * b.E;
+      gl[d] = ld_god(G, b.E, e);
+      gh[d] = ld_god(G + (long long)e_stride(b, d), b.E, e);
+    }
     const double* U = A.Uin + b.soff;
     const double U0 = ldu(U, id);
     const double Um[3] = {ldu(U + b.sstride, id), ldu(U + 2 * b.sstride, id),
@@ -1289,6 +1310,19 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     const real* G = (const real*)A.grav + b.goff;
     const double g[3] = {(double)ldu(G, id), (double)ldu(G + b.gstride, id),
                          (double)ldu(G + 2 * b.gstride, id)};
+    double D[6];
+    double Pi = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      real fl[8], fh[8];
+      final_flux(A.gamma, d, gl[d], ah, fl);
+      final_flux(A.gamma, d, gh[d], ah, fh);
+      for (int c = 0; c < 6; ++c) {
+        double dF = (double)fh[c] - (double)fl[c];
+        D[c] = (d == 0) ? dF : D[c] + dF;
+      }
+      double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
+      Pi = (d == 0) ? pd : Pi + pd;
+    }
     const double dt = C.dt, kk = C.k;
     // predictor (Step 2)
     const double s0 = U0 - kk * D[0];
@@ -1384,14 +1418,14 @@ __global__ __launch_bounds__(kBlock) void k_flux_record(StepArgs A, const BoxDev
   const real ah = (real)C.a_h;
   double acc[6];
   real f[8];
-  final_flux(A.gamma, d, G, b.E, e, ah, f);
+  final_flux(A.gamma, d, ld_god(G, b.E, e), ah, f);
   for (int c = 0; c < 6; ++c) acc[c] = (double)f[c];
   if (R.nsub == 2) {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const unsigned o1 = e_stride(b, t1), o2 = e_stride(b, t2);
     const unsigned sub[3] = {e + o1, e + o2, e + o1 + o2};
     for (int q = 0; q < 3; ++q) {
-      final_flux(A.gamma, d, G, b.E, sub[q], ah, f);
+      final_flux(A.gamma, d, ld_god(G, b.E, sub[q]), ah, f);
       for (int c = 0; c < 6; ++c) acc[c] = acc[c] + (double)f[c];
     }
   }

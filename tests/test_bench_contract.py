@@ -1,6 +1,6 @@
 """Host-side checks of the benchmark's contract (no GPU): more than one GPU
 is refused with a message; the roofline traffic record is keyed to the
-stage kernels' sources; the per-launch byte table covers every stage."""
+stage kernels' sources and holds one value per launch-order candidate; the per-launch byte table covers every stage."""
 import json
 import os
 import subprocess
@@ -22,9 +22,11 @@ def test_traffic_record_matches_the_kernel_sources():
     import bench
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_riem1_box256_mixed.json")))
     assert rec["sources_sha256"] == bench.kernel_source_hash()
-    t = bench.measured_traffic("riem1", "mixed")
-    assert t is not None and t > 0
-    assert bench.measured_traffic("riem1", "fp64") is None
+    assert len(rec["bytes_per_launch_by_candidate"]) == 16
+    for c in range(16):
+        t = bench.measured_traffic("riem1", "mixed", c)
+        assert t is not None and t > 0
+    assert bench.measured_traffic("riem1", "fp64", 0) is None
 
 
 def test_bytes_per_launch_for_every_stage():
