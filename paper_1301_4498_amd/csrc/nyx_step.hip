@@ -185,14 +185,20 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
   const real sp = (real)A.small_pres;
   const unsigned c0 = pidx_e(b, ie, je, ke);
   const unsigned sd[3] = {1u, (unsigned)b.px, (unsigned)b.px * (unsigned)b.py};
-  real cmin = (real)1;
+  // neighbour shifts go into the (uniform) base; all loads share c0 and are
+  // issued before any arithmetic, so a wave waits once for all of them
+  real pd[3][7], ud[3][5];
+  const real pc = ldu(P, c0);
   for (int d = 0; d < 3; ++d) {
     const unsigned s = sd[d];
     const real* U = prim + (1 + d) * b.P;
-    real p[7], u[5];
-    // neighbour shifts go into the (uniform) base; all loads share c0
-    for (int o = -3; o <= 3; ++o) p[o + 3] = ldu(P + (long long)o * s, c0);
-    for (int o = -2; o <= 2; ++o) u[o + 2] = ldu(U + (long long)o * s, c0);
+    for (int o = -3; o <= 3; ++o) pd[d][o + 3] = o == 0 ? pc : ldu(P + (long long)o * s, c0);
+    for (int o = -2; o <= 2; ++o) ud[d][o + 2] = ldu(U + (long long)o * s, c0);
+  }
+  real cmin = (real)1;
+  for (int d = 0; d < 3; ++d) {
+    const real* p = pd[d];
+    const real* u = ud[d];
     real fm = flat_tilde(sp, p[0], p[1], p[3], p[4], u[0], u[2]);
     real f0 = flat_tilde(sp, p[1], p[2], p[4], p[5], u[1], u[3]);
     real fp = flat_tilde(sp, p[2], p[3], p[5], p[6], u[2], u[4]);
