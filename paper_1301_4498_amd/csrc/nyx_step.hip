@@ -1047,40 +1047,80 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
 // by stage-0 t-fluxes (t = t1 and t = t2), Riemann -> F^{d|t1}, F^{d|t2}.
 // Both pairs share the loads of the d-states.
 // ---------------------------------------------------------------------------
-// Plain form: grid.y = 3 directions, both pairs of a direction per thread.
-// Learned form: grid.y = 6, one (direction, pair) per thread (fewer live
-// registers next to the network's accumulators).
-// KSEL: -1 both pairs of direction D (plain form), else pair KSEL only
-template <bool LEARNED, int D, int KSEL>
-__device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, unsigned idx,
-                                          __bf16* lds, Tally& T) {
+// Learned form: grid.y = 6, one (direction, pair K) per thread (fewer live
+// registers next to the network's accumulators).  The plain form takes both
+// pairs of a direction per thread (riem1_both below).
+template <int D, int K>
+__device__ __forceinline__ void riem1_pair(const StepArgs& A, const BoxDev& b, unsigned idx,
+                                           __bf16* lds, Tally& T) {
+  constexpr int d = D;
+  constexpr int t = K == 0 ? (D + 1) % 3 : (D + 2) % 3;
+  int c[3] = {0, 0, 0};
+  if (idx < b.E) e_coords(b, idx, c);
+  const unsigned e = idx;
+  const bool active = idx < b.E && c[d] >= 1 && c[t] >= 1 && c[t] <= b.n[t];
+  // the left cell's arrays are read through bases shifted by -sdd, so every
+  // load of the thread uses the one offset e
+  const long long sdd = e_stride(b, d);
+  double ql[5], qr[5];
+  if (active) {
+    const StepC& C = step_consts(A, b);
+    const real* W = (const real*)A.work + b.w_edge;
+    const long long stt = e_stride(b, t);
+    const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
+    double qs[2][5];
+    for (int s = 0; s < 2; ++s) {
+      const long long sh = s == 0 ? -sdd : 0;
+      const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
+      double q[5];
+      for (int v = 0; v < 5; ++v) q[v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
+      const real* Gc = G0 + sh;
+      double Dc[5], De;
+      tdiff<true>(A.gamma, t, Gc, Gc + stt, e, b.E, Dc, De);
+      T.reverts += trans_correct(A, q, Dc, De, C.kap1, qs[s]) ? 1u : 0u;
+    }
+    rotate(d, qs[0], ql);
+    rotate(d, qs[1], qr);
+  }
+  RiemannOut g = solve<true>(A, active, ql, qr, lds, &T.used, &T.fb);
+  if (active) {
+    T.calls += 1;
+    T.iters += g.iters;
+    store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, t) * kGod * b.E, b.E, e, g);
+  }
+}
+
+// Plain form, both pairs of direction D: the corrected states of both pairs
+// come first, so the second pair's loads are in flight during the first
+// pair's arithmetic instead of after its solve; the second pair's rotated
+// states wait in LDS (park, kPark doubles per thread, lane-strided) across
+// the first solve, where they would otherwise add live registers and cost
+// a wave per SIMD.
+constexpr int kPark = 10;
+template <int D>
+__device__ __forceinline__ void riem1_both(const StepArgs& A, const BoxDev& b, unsigned idx,
+                                           double* park, Tally& T) {
   constexpr int d = D;
   int c[3] = {0, 0, 0};
   if (idx < b.E) e_coords(b, idx, c);
   const unsigned e = idx;
   constexpr int ts[2] = {(D + 1) % 3, (D + 2) % 3};
   const bool inb = idx < b.E && c[d] >= 1;
-  constexpr bool pick0 = KSEL != 1, pick1 = KSEL != 0;
-  const bool want[2] = {pick0 && inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
-                        pick1 && inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
-  double q[2][5];
-  // the left cell's arrays are read through bases shifted by -sdd, so every
-  // load of the thread uses the one offset e
+  const bool want[2] = {inb && c[ts[0]] >= 1 && c[ts[0]] <= b.n[ts[0]],
+                        inb && c[ts[1]] >= 1 && c[ts[1]] <= b.n[ts[1]]};
   const long long sdd = e_stride(b, d);
+  double ql[2][5], qr[2][5];
   if (want[0] || want[1]) {
+    const StepC& C = step_consts(A, b);
     const real* W = (const real*)A.work + b.w_edge;
+    double q[2][5];
     for (int s = 0; s < 2; ++s) {
       const long long sh = s == 0 ? -sdd : 0;
       const int side = s == 0 ? 1 : 0;  // left cell gives its right-face state
       for (int v = 0; v < 5; ++v) q[s][v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
     }
-  }
-  constexpr int kfirst = KSEL < 0 ? 0 : KSEL, klast = KSEL < 0 ? 1 : KSEL;
-  for (int k = kfirst; k <= klast; ++k) {
-    const bool active = want[k];
-    double ql[5], qr[5];
-    if (active) {
-      const StepC& C = step_consts(A, b);
+    for (int k = 0; k < 2; ++k) {
+      if (!want[k]) continue;
       const int t = ts[k];
       const long long stt = e_stride(b, t);
       const real* G0 = (const real*)A.work + b.w_f0 + (long long)t * kGod * b.E;
@@ -1091,11 +1131,29 @@ __device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, un
         tdiff<true>(A.gamma, t, Gc, Gc + stt, e, b.E, Dc, De);
         T.reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
       }
-      rotate(d, qs[0], ql);
-      rotate(d, qs[1], qr);
+      rotate(d, qs[0], ql[k]);
+      rotate(d, qs[1], qr[k]);
     }
-    RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
-    if (active) {
+    if (want[1])
+      for (int v = 0; v < 5; ++v) {
+        park[v * kBlock + threadIdx.x] = ql[1][v];
+        park[(5 + v) * kBlock + threadIdx.x] = qr[1][v];
+      }
+  }
+  for (int k = 0; k < 2; ++k) {
+    double l[5], r[5];
+    if (k == 1 && want[1])
+      for (int v = 0; v < 5; ++v) {
+        l[v] = park[v * kBlock + threadIdx.x];
+        r[v] = park[(5 + v) * kBlock + threadIdx.x];
+      }
+    else
+      for (int v = 0; v < 5; ++v) {
+        l[v] = ql[k][v];
+        r[v] = qr[k][v];
+      }
+    RiemannOut g = solve<false>(A, want[k], l, r, nullptr, &T.used, &T.fb);
+    if (want[k]) {
       T.calls += 1;
       T.iters += g.iters;
       store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E, b.E, e, g);
@@ -1106,6 +1164,7 @@ __device__ __forceinline__ void riem1_dir(const StepArgs& A, const BoxDev& b, un
 template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  __shared__ double park[LEARNED ? 1 : kPark * kBlock];
   int y;
   Loc L = locate(A, kStRiem1, kSpaceE, &y);
   const BoxDev& b = *L.bd;
@@ -1113,17 +1172,17 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
   Tally T;
   if constexpr (LEARNED) {
     switch (y) {
-      case 0: riem1_dir<LEARNED, 0, 0>(A, b, L.idx, lds, T); break;
-      case 1: riem1_dir<LEARNED, 0, 1>(A, b, L.idx, lds, T); break;
-      case 2: riem1_dir<LEARNED, 1, 0>(A, b, L.idx, lds, T); break;
-      case 3: riem1_dir<LEARNED, 1, 1>(A, b, L.idx, lds, T); break;
-      case 4: riem1_dir<LEARNED, 2, 0>(A, b, L.idx, lds, T); break;
-      default: riem1_dir<LEARNED, 2, 1>(A, b, L.idx, lds, T); break;
+      case 0: riem1_pair<0, 0>(A, b, L.idx, lds, T); break;
+      case 1: riem1_pair<0, 1>(A, b, L.idx, lds, T); break;
+      case 2: riem1_pair<1, 0>(A, b, L.idx, lds, T); break;
+      case 3: riem1_pair<1, 1>(A, b, L.idx, lds, T); break;
+      case 4: riem1_pair<2, 0>(A, b, L.idx, lds, T); break;
+      default: riem1_pair<2, 1>(A, b, L.idx, lds, T); break;
     }
   } else {
-    if (y == 0) riem1_dir<LEARNED, 0, -1>(A, b, L.idx, lds, T);
-    else if (y == 1) riem1_dir<LEARNED, 1, -1>(A, b, L.idx, lds, T);
-    else riem1_dir<LEARNED, 2, -1>(A, b, L.idx, lds, T);
+    if (y == 0) riem1_both<0>(A, b, L.idx, park, T);
+    else if (y == 1) riem1_both<1>(A, b, L.idx, park, T);
+    else riem1_both<2>(A, b, L.idx, park, T);
   }
   count_tally<LEARNED>(A, T, true);
 }
