@@ -20,8 +20,9 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-__device__ __forceinline__ const BoxDev* locate_box(const StepArgs& A, int space, long long& idx) {
-  const unsigned bx = xcd_linear_block();  // 1-D grids here
+__device__ __forceinline__ const BoxDev* locate_box(const StepArgs& A, int space, long long& idx,
+                                                   bool remap = true) {
+  const unsigned bx = xcd_linear_block(remap);  // 1-D grids here
   if (A.table == nullptr) {
     idx = (long long)bx * kBlock + threadIdx.x;
     return &A.single;
@@ -168,19 +169,53 @@ hipError_t launch_min_dt(double* dt, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Ghost cell q of a box, q < P - V, as box-local coordinates (ghosts negative
+// or >= n): first the 2 ng whole padded planes below and above the box in z,
+// then the 2 ng padded rows below and above it in y on each valid plane, then
+// the ng cells at each end of every valid row.  Planes and rows are
+// contiguous in memory across consecutive q.
+__device__ __forceinline__ void ghost_coords(const BoxDev& b, unsigned q, int* c) {
+  const unsigned ng = (unsigned)b.ng, px = (unsigned)b.px, py = (unsigned)b.py;
+  const unsigned n0 = (unsigned)b.n[0], n1 = (unsigned)b.n[1], n2 = (unsigned)b.n[2];
+  const unsigned nz = 2u * ng * px * py, ny = 2u * ng * px * n2;
+  unsigned pi, pj, pk;
+  if (q < nz) {
+    const unsigned plane = q / (px * py), r = q - plane * (px * py);
+    pj = r / px;
+    pi = r - pj * px;
+    pk = plane < ng ? plane : n2 + plane;
+  } else if (q < nz + ny) {
+    const unsigned r = q - nz, row = r / px;
+    pi = r - row * px;
+    const unsigned kk = row / (2u * ng), jj = row - kk * (2u * ng);
+    pj = jj < ng ? jj : n1 + jj;
+    pk = kk + ng;
+  } else {
+    const unsigned r = q - nz - ny, row = r / (2u * ng), ii = r - row * (2u * ng);
+    pi = ii < ng ? ii : n0 + ii;
+    const unsigned kk = row / n1;
+    pj = row - kk * n1 + ng;
+    pk = kk + ng;
+  }
+  c[0] = (int)pi - b.ng;
+  c[1] = (int)pj - b.ng;
+  c[2] = (int)pk - b.ng;
+}
+
 // Ghost fill.  mode 0: periodic within the box.  mode 1: boxes tile a
 // periodic domain as a gx*gy*gz grid of equal boxes; `A.table` then points at
-// the group's boxes and `full` at the whole list in box order.
+// the group's boxes and `full` at the whole list in box order.  The grid is
+// the padded-cell grid; the first P - V work items of each box take its ghost
+// cells (ghost_coords) and the rest return at once.  Blocks keep the hardware
+// order, so the ghost blocks at the start of each box spread over the XCDs.
 __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full, double* state,
                                                  int ncomp, int mode, int gx, int gy, int gz) {
   long long id;
-  const BoxDev& b = *locate_box(A, kSpaceP, id);
-  if (id >= b.P) return;
-  int pc[3];
-  space_coords(b, kSpaceP, (unsigned)id, pc);
-  const int i = pc[0] - b.ng, j = pc[1] - b.ng, k = pc[2] - b.ng;
-  const bool valid = i >= 0 && i < b.n[0] && j >= 0 && j < b.n[1] && k >= 0 && k < b.n[2];
-  if (valid) return;
+  const BoxDev& b = *locate_box(A, kSpaceP, id, false);
+  if (id >= b.P - b.V) return;
+  int gc[3];
+  ghost_coords(b, (unsigned)id, gc);
+  const int i = gc[0], j = gc[1], k = gc[2];
   long long src;
   if (mode == 0) {
     const int si = ((i % b.n[0]) + b.n[0]) % b.n[0];
@@ -198,8 +233,19 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full,
     const int si = X - sbx * b.n[0], sj = Y - sby * b.n[1], sk = Z - sbz * b.n[2];
     src = sb.soff + ((long long)(sk + sb.ng) * sb.py + (sj + sb.ng)) * sb.px + (si + sb.ng);
   }
-  const long long dst = b.soff + id;
-  for (int c = 0; c < ncomp; ++c) state[dst + c * b.sstride] = state[src + c * b.sstride];
+  const long long dst = b.soff + ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
+  const long long cs = b.sstride;
+  if (ncomp == 6) {
+    // the gas state: every component is loaded before any is stored (sources
+    // are valid cells, destinations ghost cells, so no store feeds a load)
+    double v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = state[src + c * cs];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) state[dst + c * cs] = v[c];
+  } else {
+    for (int c = 0; c < ncomp; ++c) state[dst + c * cs] = state[src + c * cs];
+  }
 }
 
 hipError_t launch_fill_periodic(const StepArgs& a, const BoxDev* full, double* state, int ncomp,
