@@ -30,9 +30,12 @@ COMMON = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17",
 
 UNITS = [
     ("nyx_step.hip", "nyx_step_fp64.o", ["-DNYX_PREC_FP64", "-ffp-contract=off"]),
+    # -amdgpu-mfma-vgpr-form: the network's MFMA accumulators live in VGPRs,
+    # so reading them back costs no v_accvgpr_read per value
     ("nyx_step.hip", "nyx_step_mixed.o", ["-DNYX_PREC_MIXED", "-ffp-contract=on",
-                                          "-fno-hip-fp32-correctly-rounded-divide-sqrt"]),
-    ("nyx_mlp.hip", "nyx_mlp.o", ["-ffp-contract=on"]),
+                                          "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+                                          "-mllvm", "-amdgpu-mfma-vgpr-form"]),
+    ("nyx_mlp.hip", "nyx_mlp.o", ["-ffp-contract=on", "-mllvm", "-amdgpu-mfma-vgpr-form"]),
     ("nyx_util.hip", "nyx_util.o", ["-ffp-contract=off"]),
     ("nyx_fill.hip", "nyx_fill.o", ["-ffp-contract=off"]),
     ("nyx_sync.hip", "nyx_sync.o", ["-ffp-contract=off"]),

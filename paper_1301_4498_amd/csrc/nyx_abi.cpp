@@ -91,6 +91,8 @@ size_t state_span_bytes(const nyx_box& b) {
 
 void fill_physics(StepArgs& a, const nyx_params* p) {
   a.gamma = p->gamma;
+  a.igm1 = 1.0 / (p->gamma - 1.0);
+  a.igm1f = 1.0f / (float)(p->gamma - 1.0);
   a.eta = p->eta_dual;
   a.small_dens = p->small_dens;
   a.small_pres = p->small_pres;

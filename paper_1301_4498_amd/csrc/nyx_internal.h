@@ -234,6 +234,8 @@ struct StepArgs {
   double dt_host;
   double a_old, a_new;
   double gamma, eta, small_dens, small_pres, riemann_tol, cfl;
+  double igm1;   // 1 / (gamma - 1), for the mixed build's products
+  float igm1f;   // the same in FP32 (the FP32 flux formulas)
   double mixed_stop;  // FP32-mixed stopping rule (see two_shock)
   int maxiter;
   nyx_stats* stats;

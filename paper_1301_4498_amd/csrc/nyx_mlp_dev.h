@@ -55,26 +55,44 @@ __host__ __device__ constexpr int mlp_fbase(int layer) {
 }
 __host__ __device__ constexpr int mlp_nk(int layer) { return layer == 0 ? 1 : 4; }
 
-// normalised inputs of one face (float) from rotated states in double
+// FP64 reciprocal and reciprocal square root: hardware estimate (relative
+// error below 2^-24) and one Newton step, about 2^-47; positive arguments.
+__device__ __forceinline__ double mlp_rcp(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double mlp_rsq(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+}
+
+// Normalised inputs of one face (float) from rotated states in double.  The
+// inputs are rounded to float (and to BF16 in the network), so the scalings
+// are products with refined reciprocals instead of divisions.  A non-positive
+// or non-finite state gives a non-finite or huge input, which the caller's
+// domain test sends to the plain solver.
 __device__ __forceinline__ void mlp_inputs(double gamma, const double* qL, const double* qR,
                                            float* x, double* rbar_o, double* cbar_o,
                                            double* ubar_o) {
-  const double cl = sqrt(gamma * qL[4] / qL[0]);
-  const double cr = sqrt(gamma * qR[4] / qR[0]);
+  const double sl = gamma * qL[4] * mlp_rcp(qL[0]);
+  const double sr = gamma * qR[4] * mlp_rcp(qR[0]);
+  const double cl = sl * mlp_rsq(sl);
+  const double cr = sr * mlp_rsq(sr);
   const double rbar = 0.5 * (qL[0] + qR[0]);
   const double cbar = 0.5 * (cl + cr);
   const double ubar = 0.5 * (qL[1] + qR[1]);
   const double pbar = rbar * cbar * cbar;
-  x[0] = (float)(qL[0] / rbar);
-  x[1] = (float)((qL[1] - ubar) / cbar);
-  x[2] = (float)(qL[2] / cbar);
-  x[3] = (float)(qL[3] / cbar);
-  x[4] = (float)(qL[4] / pbar);
-  x[5] = (float)(qR[0] / rbar);
-  x[6] = (float)((qR[1] - ubar) / cbar);
-  x[7] = (float)(qR[2] / cbar);
-  x[8] = (float)(qR[3] / cbar);
-  x[9] = (float)(qR[4] / pbar);
+  const double ir = mlp_rcp(rbar), ic = mlp_rcp(cbar), ip = mlp_rcp(pbar);
+  x[0] = (float)(qL[0] * ir);
+  x[1] = (float)((qL[1] - ubar) * ic);
+  x[2] = (float)(qL[2] * ic);
+  x[3] = (float)(qL[3] * ic);
+  x[4] = (float)(qL[4] * ip);
+  x[5] = (float)(qR[0] * ir);
+  x[6] = (float)((qR[1] - ubar) * ic);
+  x[7] = (float)(qR[2] * ic);
+  x[8] = (float)(qR[3] * ic);
+  x[9] = (float)(qR[4] * ip);
   *rbar_o = rbar;
   *cbar_o = cbar;
   *ubar_o = ubar;
@@ -120,7 +138,8 @@ __device__ __forceinline__ void mlp_wave_forward(const void* packed, const float
           bf16x4 w;
           for (int q = 0; q < 4; ++q) {
             const float z = acc[t][m][4 * j + q];
-            w[q] = (__bf16)(z > 0.0f ? z : 0.0f);
+            // ReLU on the bits: a negative float is a negative integer
+            w[q] = (__bf16)__int_as_float(max(__float_as_int(z), 0));
           }
           *(bf16x4*)(lds + (32 * t + col) * kMlpRow + 32 * m + 8 * j + 4 * hi) = w;
         }

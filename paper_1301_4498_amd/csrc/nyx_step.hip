@@ -725,7 +725,7 @@ __device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const dou
   const double p0 = vmax(pbar * exp(y), t.sp);
   const double p1 = ts_newton(t, ts_eval(t, p0), p0);
   const TwoShockEval e = ts_eval(t, p1);
-  const double resid = fabs(e.usR - e.usL) / cbar;
+  const double resid = fabs(e.usR - e.usL) * rcp64(cbar);
   bool ok = in_domain && resid < A.mlp_tol;  // never true for tol = 0 or a NaN residual
   if (ok) {
     RiemannOut o = ts_finish(t, e, p1, qL, qR);
@@ -805,8 +805,8 @@ __device__ __forceinline__ God ld_god(const real* G, long long E, unsigned i) {
 
 // O6: lab-frame fluxes of a d-face from its Godunov state (flux arithmetic
 // in real): f = (f_rho, f_mx, f_my, f_mz, f_E, f_e, p_g, u_g).
-__device__ __forceinline__ void face_flux(double gamma, int d, const God& g, real* f) {
-  const real gm1 = (real)(gamma - 1.0);
+__device__ __forceinline__ void face_flux(const StepArgs& A, int d, const God& g, real* f) {
+  const real gm1 = (real)(A.gamma - 1.0);
   const real r = g.r, u = g.u, v = g.v, w = g.w, p = g.p;
   const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
   const real ru = r * u;
@@ -815,7 +815,7 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const God& g, rea
   f[1 + t1] = ru * v;
   f[1 + t2] = ru * w;
 #if defined(NYX_PREC_MIXED)
-  const real igm1 = (real)1 / gm1;
+  const real igm1 = A.igm1f;  // (real)1 / gm1, computed on the host
   const real rE = p * igm1 + ((real)0.5 * r) * ((u * u + v * v) + w * w);
   f[4] = u * (rE + p);
   f[5] = (u * p) * igm1;
@@ -827,9 +827,9 @@ __device__ __forceinline__ void face_flux(double gamma, int d, const God& g, rea
   f[6] = p;
   f[7] = u;
 }
-__device__ __forceinline__ void face_flux(double gamma, int d, const real* G, long long E,
+__device__ __forceinline__ void face_flux(const StepArgs& A, int d, const real* G, long long E,
                                           unsigned i, real* f) {
-  face_flux(gamma, d, ld_god(G, E, i), f);
+  face_flux(A, d, ld_god(G, E, i), f);
 }
 
 __device__ __forceinline__ void e_coords(const BoxDev& b, unsigned e, int* c) {
@@ -848,11 +848,11 @@ __device__ __forceinline__ unsigned e_stride(const BoxDev& b, int d) {
 // at the low and high t-faces of a cell) to Dc, De; the first direction sets
 // them, a second one is added, in that order
 template <bool FIRST>
-__device__ __forceinline__ void tdiff(double gamma, int t, const God& glo, const God& ghi,
+__device__ __forceinline__ void tdiff(const StepArgs& A, int t, const God& glo, const God& ghi,
                                       double* Dc, double& De) {
   real fm[8], fp[8];
-  face_flux(gamma, t, glo, fm);
-  face_flux(gamma, t, ghi, fp);
+  face_flux(A, t, glo, fm);
+  face_flux(A, t, ghi, fp);
 #if defined(NYX_PREC_MIXED)
   // flux differences are flux arithmetic: FP32, widened once
   for (int c = 0; c < 5; ++c) {
@@ -871,9 +871,9 @@ __device__ __forceinline__ void tdiff(double gamma, int t, const God& glo, const
   De = FIRST ? de : De + de;
 }
 template <bool FIRST>
-__device__ __forceinline__ void tdiff(double gamma, int t, const real* Glo, const real* Ghi,
+__device__ __forceinline__ void tdiff(const StepArgs& A, int t, const real* Glo, const real* Ghi,
                                       unsigned i, long long E, double* Dc, double& De) {
-  tdiff<FIRST>(gamma, t, ld_god(Glo, E, i), ld_god(Ghi, E, i), Dc, De);
+  tdiff<FIRST>(A, t, ld_god(Glo, E, i), ld_god(Ghi, E, i), Dc, De);
 }
 
 __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q,
@@ -887,7 +887,7 @@ __device__ __forceinline__ bool trans_correct(const StepArgs& A, const double* q
   U[2] = rho * uy;
   U[3] = rho * uz;
 #if defined(NYX_PREC_MIXED)
-  const double Ue = p * (1.0 / gm1);
+  const double Ue = p * A.igm1;  // p * (1 / gm1), the reciprocal from the host
 #else
   const double Ue = p / gm1;
 #endif
@@ -1076,7 +1076,7 @@ __device__ __forceinline__ void riem1_pair(const StepArgs& A, const BoxDev& b, u
       for (int v = 0; v < 5; ++v) q[v] = (double)ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
       const real* Gc = G0 + sh;
       double Dc[5], De;
-      tdiff<true>(A.gamma, t, Gc, Gc + stt, e, b.E, Dc, De);
+      tdiff<true>(A, t, Gc, Gc + stt, e, b.E, Dc, De);
       T.reverts += trans_correct(A, q, Dc, De, C.kap1, qs[s]) ? 1u : 0u;
     }
     rotate(d, qs[0], ql);
@@ -1128,7 +1128,7 @@ __device__ __forceinline__ void riem1_both(const StepArgs& A, const BoxDev& b, u
       for (int s = 0; s < 2; ++s) {
         const real* Gc = G0 + (s == 0 ? -sdd : 0);
         double Dc[5], De;
-        tdiff<true>(A.gamma, t, Gc, Gc + stt, e, b.E, Dc, De);
+        tdiff<true>(A, t, Gc, Gc + stt, e, b.E, Dc, De);
         T.reverts += trans_correct(A, q[s], Dc, De, C.kap1, qs[s]) ? 1u : 0u;
       }
       rotate(d, qs[0], ql[k]);
@@ -1236,8 +1236,8 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
       double q[5];
       for (int v = 0; v < 5; ++v) q[v] = (double)qe[s][v];
       double Dc[5], De;
-      tdiff<true>(A.gamma, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
-      tdiff<false>(A.gamma, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
+      tdiff<true>(A, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
+      tdiff<false>(A, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
       T.reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
     }
     rotate(d, qs[0], ql);
@@ -1284,8 +1284,8 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
 
 // O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
 // F_m = f_m, F_E = a_h f_E, F_e = a_h f_e; p_g and u_g kept for S_e.
-__device__ __forceinline__ void final_flux(double gamma, int d, const God& g, real ah, real* f) {
-  face_flux(gamma, d, g, f);
+__device__ __forceinline__ void final_flux(const StepArgs& A, int d, const God& g, real ah, real* f) {
+  face_flux(A, d, g, f);
   f[0] = f[0] / ah;
   f[4] = ah * f[4];
   f[5] = ah * f[5];
@@ -1379,8 +1379,8 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     double Pi = 0.0;
     for (int d = 0; d < 3; ++d) {
       real fl[8], fh[8];
-      final_flux(A.gamma, d, gl[d], ah, fl);
-      final_flux(A.gamma, d, gh[d], ah, fh);
+      final_flux(A, d, gl[d], ah, fl);
+      final_flux(A, d, gh[d], ah, fh);
       for (int c = 0; c < 6; ++c) {
         double dF = (double)fh[c] - (double)fl[c];
         D[c] = (d == 0) ? dF : D[c] + dF;
@@ -1483,14 +1483,14 @@ __global__ __launch_bounds__(kBlock) void k_flux_record(StepArgs A, const BoxDev
   const real ah = (real)C.a_h;
   double acc[6];
   real f[8];
-  final_flux(A.gamma, d, ld_god(G, b.E, e), ah, f);
+  final_flux(A, d, ld_god(G, b.E, e), ah, f);
   for (int c = 0; c < 6; ++c) acc[c] = (double)f[c];
   if (R.nsub == 2) {
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const unsigned o1 = e_stride(b, t1), o2 = e_stride(b, t2);
     const unsigned sub[3] = {e + o1, e + o2, e + o1 + o2};
     for (int q = 0; q < 3; ++q) {
-      final_flux(A.gamma, d, ld_god(G, b.E, sub[q]), ah, f);
+      final_flux(A, d, ld_god(G, b.E, sub[q]), ah, f);
       for (int c = 0; c < 6; ++c) acc[c] = acc[c] + (double)f[c];
     }
   }
