@@ -88,15 +88,25 @@ KERNEL_SOURCES = ("paper_1301_4498_amd/csrc/nyx_step.hip", "paper_1301_4498_amd/
                   "paper_1301_4498_amd/csrc/nyx_mlp_dev.h")
 
 
+def _code_tokens(text):
+    """C++ source with comments removed and whitespace collapsed (the hashed
+    sources hold no string literal that contains a comment marker)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """sha256 over the sources of the stage kernels and the compiler flags of
-    their two builds (other translation units of the library do not enter)."""
+    """sha256 over the code of the stage kernels' sources (comments and
+    whitespace do not enter) and the compiler flags of their two builds
+    (other translation units of the library do not enter)."""
     import hashlib
     from paper_1301_4498_amd import build as B
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            h.update(_code_tokens(fh.read()).encode())
     flags = [B.COMMON] + [u for u in B.UNITS if u[0] == "nyx_step.hip"]
     h.update(repr(flags).encode())
     return h.hexdigest()

@@ -138,11 +138,11 @@ __device__ __forceinline__ void max_bits(unsigned long long* dst, double m) {
 __device__ __forceinline__ unsigned fast_div(unsigned n, const FastDiv& f) {
   return (__umulhi(n, f.m) + n) >> f.l;
 }
-// Element i of an array whose base is uniform over the workgroup, addressed
-// through a 32-bit byte offset: the access takes the scalar-base form of the
-// memory instructions, with no 64-bit address arithmetic per lane.  Every
-// per-box array has fewer than 2^29 elements (checked on the host), so the
-// byte offset fits 32 bits.
+// Element i of an array through a 32-bit byte offset.  Every per-box array
+// has fewer than 2^29 elements (checked on the host), so the byte offset fits
+// 32 bits.  With a base that is uniform over the workgroup the compiler can
+// use the scalar-base form of the memory instructions where the offset and
+// the access sit in one block; elsewhere the access costs one 64-bit add.
 template <class T>
 __device__ __forceinline__ T ldu(const T* base, unsigned i) {
   return *(const T*)((const char*)base + i * (unsigned)sizeof(T));

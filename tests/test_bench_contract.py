@@ -34,3 +34,11 @@ def test_bytes_per_launch_for_every_stage():
     for st in ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update"):
         assert bench.bytes_per_launch(st, 256, 4) > 0
         assert bench.bytes_per_launch(st, 256, 8) > bench.bytes_per_launch(st, 256, 4)
+
+
+def test_source_hash_ignores_comments_and_layout():
+    import bench
+    a = "int f(int x) {  // one\n  return x + 1; /* two\n lines */ }\n"
+    b = "int f(int x) {\n/* other */ return x + 1; }"
+    assert bench._code_tokens(a) == bench._code_tokens(b) == "int f(int x) { return x + 1; }"
+    assert bench._code_tokens("a - b") != bench._code_tokens("a + b")
