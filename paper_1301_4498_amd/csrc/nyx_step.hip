@@ -1140,24 +1140,19 @@ __device__ __forceinline__ void riem1_both(const StepArgs& A, const BoxDev& b, u
         park[(5 + v) * kBlock + threadIdx.x] = qr[1][v];
       }
   }
+  // the plain solver needs no wave-wide participation: lanes without a
+  // face of pair k skip it
   for (int k = 0; k < 2; ++k) {
+    if (!want[k]) continue;
     double l[5], r[5];
-    if (k == 1 && want[1])
-      for (int v = 0; v < 5; ++v) {
-        l[v] = park[v * kBlock + threadIdx.x];
-        r[v] = park[(5 + v) * kBlock + threadIdx.x];
-      }
-    else
-      for (int v = 0; v < 5; ++v) {
-        l[v] = ql[k][v];
-        r[v] = qr[k][v];
-      }
-    RiemannOut g = solve<false>(A, want[k], l, r, nullptr, &T.used, &T.fb);
-    if (want[k]) {
-      T.calls += 1;
-      T.iters += g.iters;
-      store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E, b.E, e, g);
+    for (int v = 0; v < 5; ++v) {
+      l[v] = k == 0 ? ql[0][v] : park[v * kBlock + threadIdx.x];
+      r[v] = k == 0 ? qr[0][v] : park[(5 + v) * kBlock + threadIdx.x];
     }
+    RiemannOut g = solve<false>(A, true, l, r, nullptr, &T.used, &T.fb);
+    T.calls += 1;
+    T.iters += g.iters;
+    store_god((real*)A.work + b.w_f1 + (long long)pair_index(d, ts[k]) * kGod * b.E, b.E, e, g);
   }
 }
 
