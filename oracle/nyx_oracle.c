@@ -35,6 +35,17 @@
 #define FLAT_OMEGA1 0.75
 #define FLAT_OMEGA2 10.0
 
+/* Stage markers for the operation-count build (oracle/opcount.cpp), which
+ * compiles this file with a counting number type and attributes every
+ * floating-point operation to the stage and, inside the two-shock solver, to
+ * the Newton iteration that is running.  They do nothing here. */
+#ifndef NYXO_STAGE
+#define NYXO_STAGE(s) ((void)0)
+#endif
+#ifndef NYXO_ITER
+#define NYXO_ITER(on) ((void)0)
+#endif
+
 static double dmax(double a, double b) { return a > b ? a : b; }
 /* kinetic energy |m|^2 / (2 rho) of a momentum m in the stored variables */
 static double kinetic(const double* m, double rho) {
@@ -132,6 +143,7 @@ static int riemann_solve(const nyxo_params* prm, const double* qL,
   int it = 0;
   double WL, WR, usL, usR, ZL, ZR;
   while (it < prm->riemann_maxiter) {
+    NYXO_ITER(1);
     WL = sqrt(CL + (g2 * rl) * (p - pl));
     WR = sqrt(CR + (g2 * rr) * (p - pr));
     usL = ul - (p - pl) / WL;
@@ -145,6 +157,7 @@ static int riemann_solve(const nyxo_params* prm, const double* qL,
     p = pn;
     if (conv) break;
   }
+  NYXO_ITER(0);
   /* final evaluation at the converged pressure */
   WL = sqrt(CL + (g2 * rl) * (p - pl));
   WR = sqrt(CR + (g2 * rr) * (p - pr));
@@ -487,6 +500,7 @@ int nyxo_estimate_dt(const nyxo_params* prm, int nx, int ny, int nz, int ng,
     return -1;
   Box b;
   box_init(&b, nx, ny, nz, ng);
+  NYXO_STAGE(8);
   const double gam = prm->gamma, gm1 = gam - 1.0;
   double smax = 0.0;
   for (int k = 0; k < nz; ++k)
@@ -575,6 +589,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
 #define FL2(d, v, id) F2[((d) * NF + (v)) * E + (id)]
 
   /* ---- O1: primitives on every padded cell ---- */
+  NYXO_STAGE(1);
   for (int kk = -ng; kk < n[2] + ng; ++kk)
     for (int j = -ng; j < n[1] + ng; ++j)
       for (int i = -ng; i < n[0] + ng; ++i) {
@@ -594,6 +609,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
       }
 
   /* ---- O2: flattening, chi = min over directions, cells [-1, n]^3 ---- */
+  NYXO_STAGE(2);
   for (int kk = -1; kk <= n[2]; ++kk)
     for (int j = -1; j <= n[1]; ++j)
       for (int i = -1; i <= n[0]; ++i) {
@@ -614,6 +630,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
       }
 
   /* ---- O3 + O4: PPM and tracing, all directions, cells [-1, n]^3 ---- */
+  NYXO_STAGE(3);
   for (int kk = -1; kk <= n[2]; ++kk)
     for (int j = -1; j <= n[1]; ++j)
       for (int i = -1; i <= n[0]; ++i) {
@@ -647,6 +664,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
       }
 
   /* ---- O8 stage 0: Riemann on d-faces between cells of [-1, n] ---- */
+  NYXO_STAGE(4);
   for (int d = 0; d < 3; ++d) {
     int lo3[3] = {-1, -1, -1}, hi3[3] = {n[0], n[1], n[2]};
     lo3[d] = 0; /* face index f in [0, n_d] */
@@ -668,6 +686,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
   }
 
   /* ---- O8 stage 1: d-states corrected by stage-0 t-fluxes ---- */
+  NYXO_STAGE(5);
   for (int d = 0; d < 3; ++d)
     for (int t = 0; t < 3; ++t) {
       if (t == d) continue;
@@ -709,6 +728,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
     }
 
   /* ---- O8 stage 2: final d-states and fluxes on valid faces ---- */
+  NYXO_STAGE(6);
   for (int d = 0; d < 3; ++d) {
     int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     int lo3[3] = {0, 0, 0}, hi3[3] = {n[0] - 1, n[1] - 1, n[2] - 1};
@@ -767,6 +787,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
   }
 
   /* ---- O10-O12: update, gravity corrector, dual-energy sync ---- */
+  NYXO_STAGE(7);
   for (int kk = 0; kk < n[2]; ++kk)
     for (int j = 0; j < n[1]; ++j)
       for (int i = 0; i < n[0]; ++i) {
