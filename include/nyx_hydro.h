@@ -185,8 +185,20 @@ int nyx_batch_estimate_dt(nyx_batch* plan, const double* state, double a, double
  * time step for all boxes. */
 int nyx_batch_min_dt(nyx_batch* plan, double* dt, void* stream);
 
-/* One step of every box: dt (device, nbox doubles); dt_next (device, nbox
- * doubles, or NULL) receives each box's CFL step of the new state. */
+/* One step of every box of the plan: the gas step of Sec. 3.6 (Step 2
+ * predictor, Step 6 gravity corrector and dual-energy sync) applied to each
+ * grid of a level, a level being a union of non-overlapping boxes with
+ * ghost cells (Sec. 4.1), each advanced with its own time step (the hydro
+ * CFL of Sec. 3.5 per box, or one level dt after nyx_batch_min_dt).
+ * state_in, state_out (device, FP64) hold every box at its own offsets and
+ * must not overlap; grav (device, FP64 or FP32 per precision); dt (device,
+ * nbox doubles, read on the device, so a captured graph replays step after
+ * step); dt_next (device, nbox doubles, or NULL) receives each box's CFL step
+ * of the new state at a_new; stats (device or NULL) sums the counters of all
+ * boxes.  Each box's result is bit for bit that of nyx_hydro_step on it,
+ * whatever the grouping and launch orders.  Errors: NYX_E_NULL for a missing
+ * plan or buffer, NYX_E_PARAM for a_old, a_new <= 0, NYX_E_ALIAS for
+ * overlapping states; nothing is enqueued then. */
 int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* grav,
                            const double* dt, double a_old, double a_new,
                            double* state_out, double* dt_next, nyx_stats* stats,

@@ -1,11 +1,11 @@
 /*
  * sync_oracle.c -- FP64 CPU reference of the synchronisation of two AMR
  * levels after the fine level has been advanced (Sec. 4.3 Multilevel
- * Algorithm, Step 2: an explicit reflux of the hydrodynamic quantities from
- * the fine level to the coarse one keeps the composite solution
- * conservative; Step 8: reflux, then average the fine solution down onto the
- * coarse cells it covers).  TEST INFRASTRUCTURE ONLY; shares no code with the
- * HIP library.
+ * Algorithm, Steps 2 and 8): the coarse cells beside the fine level are
+ * corrected by the difference between the fine and the coarse fluxes through
+ * their shared faces, which keeps the sums over both levels conserved, and
+ * each covered coarse cell takes the mean of its eight children.  TEST
+ * INFRASTRUCTURE ONLY; shares no code with the HIP library.
  *
  * The coarse step moved conserved quantities through a coarse face with its
  * own flux over dt_c; the fine level moved them through the same face with

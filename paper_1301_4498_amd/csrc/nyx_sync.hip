@@ -1,8 +1,9 @@
 // nyx_sync.hip -- synchronisation of two AMR levels after the fine level has
-// been advanced (Sec. 4.3 Multilevel Algorithm, Step 2: an explicit reflux
-// of the hydrodynamic quantities keeps the composite solution conservative;
-// Step 8: reflux, then average the fine solution down onto the coarse cells
-// it covers).
+// been advanced (Sec. 4.3 Multilevel Algorithm, Steps 2 and 8): the coarse
+// cells beside the fine level get the difference between the fine and the
+// coarse fluxes through their shared faces, so that the sums over both
+// levels stay conserved, and each covered coarse cell takes the mean of its
+// eight children.
 //
 // The host plans once per pair of box layouts:
 //   - the interface faces: coarse faces with exactly one side covered by the
