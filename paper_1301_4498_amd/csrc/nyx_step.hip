@@ -59,21 +59,21 @@ struct Loc {
   unsigned idx;  // cell index within the box's space (< 2^31)
 };
 
-// Returns the box and cell index of this thread; *ylane receives the
-// grid-y coordinate (direction or direction pair).  The workgroup's place in
-// the walk follows the stage's tuning entry (kTune* bits).
-__device__ __forceinline__ Loc locate(const StepArgs& A, int stage, int space,
-                                      int* ylane = nullptr) {
+// Box and cell index of this thread for the workgroup at walk position
+// `lin` of a stage grid of gx blocks per row and gy rows; *ylane receives the
+// row (direction or direction pair).  The walk follows the stage's tuning
+// entry (kTune* bits).
+__device__ __forceinline__ Loc locate_at(const StepArgs& A, int stage, int space, unsigned lin,
+                                         unsigned gx, unsigned gy, int* ylane) {
   Loc L;
   const int tune = A.tune[stage];
-  const unsigned lin = xcd_linear_block(!(tune & kTuneHwOrder));
   unsigned bx, yl;
   if (tune & kTuneCellMajor) {
-    bx = lin / gridDim.y;
-    yl = lin % gridDim.y;
+    bx = lin / gy;
+    yl = lin % gy;
   } else {
-    bx = lin % gridDim.x;
-    yl = lin / gridDim.x;
+    bx = lin % gx;
+    yl = lin / gx;
   }
   if (ylane) *ylane = (int)yl;
   const int* pre = A.prefix[space];
@@ -88,6 +88,23 @@ __device__ __forceinline__ Loc locate(const StepArgs& A, int stage, int space,
   L.idx = (unsigned)(x - pre[lo]) * (unsigned)kBlock + threadIdx.x;
   const int slab = (tune >> kTuneSlabShift) & 3;
   if (slab) L.idx = slab_to_natural(*L.bd, space, L.idx, slab + 2);
+  return L;
+}
+// Where a work item of a stage sits: the walk position and grid shape of
+// the stage's own launch (position from the hardware block index,
+// XCD-contiguous unless the tuning says otherwise), or of one item of the
+// persistent step's queue.
+struct Item {
+  unsigned lin, gx, gy;
+};
+__device__ __forceinline__ Item launch_item(const StepArgs& A, int stage) {
+  return Item{xcd_linear_block(!(A.tune[stage] & kTuneHwOrder)), gridDim.x, gridDim.y};
+}
+__device__ __forceinline__ Loc locate(const StepArgs& A, int stage, int space, const Item& it,
+                                      int* ylane = nullptr) {
+  int y = 0;
+  Loc L = locate_at(A, stage, space, it.lin, it.gx, it.gy, &y);
+  if (ylane) *ylane = y;
   return L;
 }
 
@@ -126,8 +143,8 @@ __device__ __forceinline__ void count(const StepArgs& A, int field, unsigned v) 
 // ---------------------------------------------------------------------------
 // stage 1: primitives on every padded cell
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
-  Loc L = locate(A, kStPrim, kSpaceP);
+__device__ __forceinline__ void prim_body(const StepArgs& A, const Item& it) {
+  Loc L = locate(A, kStPrim, kSpaceP, it);
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.P) {
@@ -153,6 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) {
   }
   if (A.stats) count(A, kFloorHits, floors);
 }
+__global__ __launch_bounds__(kBlock) void k_prim(StepArgs A) { prim_body(A, launch_item(A, kStPrim)); }
 
 // padded index of the cell at E-array coordinates (ie, je, ke) (cell ie - 1)
 __device__ __forceinline__ unsigned pidx_e(const BoxDev& b, int ie, int je, int ke) {
@@ -172,8 +190,8 @@ __device__ __forceinline__ real flat_tilde(real sp, real pm2, real pm1, real pp1
   return w ? vmax((real)0, vmin((real)1, (real)FLAT_OMEGA2 * (z - (real)FLAT_OMEGA1))) : (real)0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
-  Loc L = locate(A, kStFlat, kSpaceE);
+__device__ __forceinline__ void flat_body(const StepArgs& A, const Item& it) {
+  Loc L = locate(A, kStFlat, kSpaceE, it);
   const BoxDev& b = *L.bd;
   if (L.idx >= b.E) return;
   const unsigned e = L.idx;
@@ -211,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) {
   }
   stu((real*)A.work + b.w_chi, e, cmin);
 }
+__global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) { flat_body(A, launch_item(A, kStFlat)); }
 
 // ---------------------------------------------------------------------------
 // stage 3: PPM (O3) and characteristic tracing (O4)
@@ -392,9 +411,9 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
   return floors;
 }
 
-__global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
+__device__ __forceinline__ void trace_body(const StepArgs& A, const Item& it) {
   int d;
-  Loc L = locate(A, kStTrace, kSpaceE, &d);
+  Loc L = locate(A, kStTrace, kSpaceE, it, &d);
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.E) {
@@ -404,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) {
   }
   if (A.stats) count(A, kFloorHits, floors);
 }
+__global__ __launch_bounds__(kBlock) void k_trace(StepArgs A) { trace_body(A, launch_item(A, kStTrace)); }
 
 // ---------------------------------------------------------------------------
 // two-shock Riemann solver (O5), always FP64
@@ -713,31 +733,40 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
 
 // Learned solve.  The network's pressure guess p0 = Pbar exp(y0) is corrected
 // by one Newton step of the two-shock relations; the result is accepted when
-// the face's inputs lie in the training domain (`in_domain`), the two-shock
-// velocity residual |u*_R(p1) - u*_L(p1)| / cbar at the corrected pressure
-// is below tol and the star state is positive and finite.  Otherwise the
-// plain two-shock solver decides the face (*used = false).
+// the network's output is finite, the face's inputs lie in the training
+// domain (`in_domain`), the two-shock velocity residual |u*_R(p1) -
+// u*_L(p1)| / cbar at the corrected pressure is below tol and the star state
+// is positive and finite.  Otherwise the plain two-shock solver decides the
+// face (*used = false).  The Newton step and the residual are two
+// evaluations of the two-shock relations, counted as two iterations, on top
+// of the fallback solver's own.
+constexpr int kLearnedEvals = 2;
 __device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const double* qL,
                                                     const double* qR, float y0, double pbar,
                                                     double cbar, bool in_domain, bool* used) {
   const TwoShock t = ts_setup(A, qL, qR);
+  const bool out_finite = isfinite(y0);  // NaN or infinite weights never pass
   const double y = (double)(y0 < -40.0f ? -40.0f : (y0 > 40.0f ? 40.0f : y0));
   const double p0 = vmax(pbar * exp(y), t.sp);
   const double p1 = ts_newton(t, ts_eval(t, p0), p0);
   const TwoShockEval e = ts_eval(t, p1);
   const double resid = fabs(e.usR - e.usL) * rcp64(cbar);
-  bool ok = in_domain && resid < A.mlp_tol;  // never true for tol = 0 or a NaN residual
+  // never true for tol = 0 or a NaN residual
+  bool ok = out_finite && in_domain && resid < A.mlp_tol;
   if (ok) {
     RiemannOut o = ts_finish(t, e, p1, qL, qR);
     ok = o.rsL > 0.0 && o.rsR > 0.0 && isfinite(o.rsL) && isfinite(o.rsR) && isfinite(o.r) &&
          isfinite(o.u) && isfinite(o.p) && o.r > 0.0 && o.p > 0.0;
     if (ok) {
       *used = true;
+      o.iters = kLearnedEvals;
       return o;
     }
   }
   *used = false;
-  return two_shock(A, qL, qR);
+  RiemannOut o = two_shock(A, qL, qR);
+  o.iters += kLearnedEvals;
+  return o;
 }
 #else
 
@@ -1028,11 +1057,11 @@ __device__ __forceinline__ void count_tally(const StepArgs& A, const Tally& T, b
   }
 }
 
+// mlp_lds: the block's (kBlock / 64) x kMlpWaveLds network tile (learned)
 template <bool LEARNED>
-__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+__device__ __forceinline__ void riem0_body(const StepArgs& A, const Item& it, __bf16* mlp_lds) {
   int d;
-  Loc L = locate(A, kStRiem0, kSpaceE, &d);
+  Loc L = locate(A, kStRiem0, kSpaceE, it, &d);
   const BoxDev& b = *L.bd;
   __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
   Tally T;
@@ -1040,6 +1069,11 @@ __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
   else if (d == 1) riem0_dir<LEARNED, 1>(A, b, L.idx, lds, T);
   else riem0_dir<LEARNED, 2>(A, b, L.idx, lds, T);
   count_tally<LEARNED>(A, T, false);
+}
+template <bool LEARNED>
+__global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  riem0_body<LEARNED>(A, launch_item(A, kStRiem0), mlp_lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1156,12 +1190,12 @@ __device__ __forceinline__ void riem1_both(const StepArgs& A, const BoxDev& b, u
   }
 }
 
+// park: kPark x kBlock doubles (plain form); mlp_lds as in riem0_body
 template <bool LEARNED>
-__global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
-  __shared__ double park[LEARNED ? 1 : kPark * kBlock];
+__device__ __forceinline__ void riem1_body(const StepArgs& A, const Item& it, __bf16* mlp_lds,
+                                           double* park) {
   int y;
-  Loc L = locate(A, kStRiem1, kSpaceE, &y);
+  Loc L = locate(A, kStRiem1, kSpaceE, it, &y);
   const BoxDev& b = *L.bd;
   __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
   Tally T;
@@ -1180,6 +1214,12 @@ __global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
     else riem1_both<2>(A, b, L.idx, park, T);
   }
   count_tally<LEARNED>(A, T, true);
+}
+template <bool LEARNED>
+__global__ __launch_bounds__(kBlock) void k_riem1(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
+  __shared__ double park[LEARNED ? 1 : kPark * kBlock];
+  riem1_body<LEARNED>(A, launch_item(A, kStRiem1), mlp_lds, park);
 }
 
 // 32-bit hash of a face for the training-sample harvest
@@ -1263,11 +1303,10 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
 
 // MODE 0: plain; 1: learned; 2: plain and harvest training records
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+__device__ __forceinline__ void riem2_body(const StepArgs& A, const Item& it, __bf16* mlp_lds) {
   constexpr bool LEARNED = MODE == 1;
-  __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   int d;
-  Loc L = locate(A, kStRiem2, kSpaceE, &d);
+  Loc L = locate(A, kStRiem2, kSpaceE, it, &d);
   const BoxDev& b = *L.bd;
   __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
   Tally T;
@@ -1275,6 +1314,11 @@ __global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
   else if (d == 1) riem2_dir<MODE, 1>(A, b, L.idx, lds, T);
   else riem2_dir<MODE, 2>(A, b, L.idx, lds, T);
   count_tally<LEARNED>(A, T, true);
+}
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_riem2(StepArgs A) {
+  __shared__ __bf16 mlp_lds[MODE == 1 ? (kBlock / 64) * kMlpWaveLds : 1];
+  riem2_body<MODE>(A, launch_item(A, kStRiem2), mlp_lds);
 }
 
 // O9: comoving flux vector of a final face (Sec. 3.2): F_rho = f_rho/a_h,
@@ -1339,8 +1383,8 @@ __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* d
 // ---------------------------------------------------------------------------
 // stage 7: conservative update, gravity corrector, dual-energy sync
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
-  Loc L = locate(A, kStUpdate, kSpaceV);
+__device__ __forceinline__ void update_body(const StepArgs& A, const Item& it) {
+  Loc L = locate(A, kStUpdate, kSpaceV, it);
   const BoxDev& b = *L.bd;
   unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
   double smax = 0.0;
@@ -1455,6 +1499,9 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
     count(A, kNegEint, nne);
   }
   if (A.dt_next) block_max_atomic(smax, A.smax + b.gidx);
+}
+__global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
+  update_body(A, launch_item(A, kStUpdate));
 }
 
 // ---------------------------------------------------------------------------
