@@ -62,7 +62,8 @@ typedef enum {
   NYX_E_ALIAS = -4,       /* input and output state overlap */
   NYX_E_HIP = -5,         /* a HIP launch or runtime call failed */
   NYX_E_UNSUPPORTED = -6, /* combination not built into this library */
-  NYX_E_WORKSPACE = -7    /* workspace too small or misaligned */
+  NYX_E_WORKSPACE = -7,   /* workspace too small or misaligned */
+  NYX_E_SCRATCH = -8      /* box too large for nyx_hydro_step_noalloc's scratch */
 } nyx_status;
 
 typedef enum { NYX_FP64 = 0, NYX_MIXED = 1 } nyx_precision;
@@ -155,6 +156,24 @@ int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_
                    const void* grav, double dt, double a_old, double a_new,
                    double* state_out, double* dt_next, nyx_stats* stats,
                    void* workspace, size_t ws_bytes, void* stream);
+
+/* The same step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument.  The stage arrays live in a library-held device
+ * array of nyx_noalloc_max_bytes() bytes (64 MiB), one per GPU, held until
+ * the process ends; the call allocates nothing (no hipMalloc, no events).
+ * A box whose nyx_workspace_bytes exceed it returns NYX_E_SCRATCH (FP64 up
+ * to about 40^3 valid cells, FP32-mixed up to about 50^3).  Every call on a
+ * GPU shares that GPU's array and leaves its contents there: calls that
+ * overlap on one GPU (two streams, two threads) race on it; the counters and
+ * the CFL maximum it holds are cleared by each call.  Other arguments,
+ * results and errors are those of nyx_hydro_step, bit for bit. */
+int nyx_hydro_step_noalloc(const nyx_params* p, const nyx_box* box, const double* state_in,
+                           const void* grav, double dt, double a_old, double a_new,
+                           double* state_out, double* dt_next, nyx_stats* stats,
+                           void* stream);
+/* Bytes of the scratch array of nyx_hydro_step_noalloc. */
+int nyx_noalloc_max_bytes(size_t* bytes);
 
 /* ---------------- batched boxes (one AMR level) ----------------
  * A plan describes a list of boxes living in shared state / gravity buffers

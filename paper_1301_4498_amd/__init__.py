@@ -17,7 +17,7 @@ from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMAN
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
-           "hydro_step", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "cic_deposit", "PoissonSolver",
+           "hydro_step", "hydro_step_noalloc", "noalloc_max_bytes", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "cic_deposit", "PoissonSolver",
            "gravity_from_phi", "stats_dict"]
 
 
@@ -84,6 +84,19 @@ def hydro_step(params, box, state_in, grav, dt, a_old, a_new, state_out, dt_next
         ctypes.byref(params), ctypes.byref(box), _ptr(state_in), _ptr(grav), float(dt),
         float(a_old), float(a_new), _ptr(state_out), _ptr(dt_next), _ptr(stats), _ptr(workspace),
         ws_bytes, _stream(stream)))
+
+
+def hydro_step_noalloc(params, box, state_in, grav, dt, a_old, a_new, state_out, dt_next=None,
+                       stats=None, stream=None) -> None:
+    check("nyx_hydro_step_noalloc", lib().nyx_hydro_step_noalloc(
+        ctypes.byref(params), ctypes.byref(box), _ptr(state_in), _ptr(grav), float(dt),
+        float(a_old), float(a_new), _ptr(state_out), _ptr(dt_next), _ptr(stats), _stream(stream)))
+
+
+def noalloc_max_bytes() -> int:
+    out = ctypes.c_size_t(0)
+    check("nyx_noalloc_max_bytes", lib().nyx_noalloc_max_bytes(ctypes.byref(out)))
+    return out.value
 
 
 def fill_ghosts_periodic(box, state, ncomp=6, stream=None) -> None:

@@ -19,7 +19,8 @@ NYX_RECON_PPM = 0
 NYX_RECON_PLM = 1
 
 STATUS = {0: "NYX_OK", -1: "NYX_E_NULL", -2: "NYX_E_SHAPE", -3: "NYX_E_PARAM",
-          -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE"}
+          -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE",
+          -8: "NYX_E_SCRATCH"}
 
 
 class Params(ctypes.Structure):
@@ -86,6 +87,8 @@ def lib():
             "nyx_workspace_bytes": (i, [P, B, ctypes.POINTER(sz)]),
             "nyx_estimate_dt": (i, [P, B, vp, d, d, vp, vp, sz, vp]),
             "nyx_hydro_step": (i, [P, B, vp, vp, d, d, d, vp, vp, vp, vp, sz, vp]),
+            "nyx_hydro_step_noalloc": (i, [P, B, vp, vp, d, d, d, vp, vp, vp, vp]),
+            "nyx_noalloc_max_bytes": (i, [ctypes.POINTER(sz)]),
             "nyx_batch_workspace_bytes": (i, [P, i, B, ctypes.POINTER(sz), ctypes.POINTER(sz)]),
             "nyx_batch_create": (i, [P, i, B, vp, sz, vp, ctypes.POINTER(vp)]),
             "nyx_batch_destroy": (i, [vp]),
@@ -161,7 +164,8 @@ def exported_symbols():
             "nyx_sync_plan_bytes", "nyx_sync_plan_create", "nyx_sync_plan_counts",
             "nyx_sync_plan_destroy", "nyx_batch_set_flux_register", "nyx_reflux",
             "nyx_average_down", "nyx_cic_deposit", "nyx_poisson_workspace_bytes",
-            "nyx_poisson_solve", "nyx_gravity_from_phi"]
+            "nyx_poisson_solve", "nyx_gravity_from_phi", "nyx_hydro_step_noalloc",
+            "nyx_noalloc_max_bytes"]
 
 TUNE_CANDIDATES = 16
 MLP_NPARAM = 9349

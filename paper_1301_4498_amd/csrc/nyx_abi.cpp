@@ -15,6 +15,13 @@
 
 using namespace nyx;
 
+// Scratch of the allocation-free single-box step (nyx_hydro_step_noalloc): a
+// file-scope device array that every call on a GPU shares.  In host code
+// `scratch` only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (scratch_address below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 // Single-box workspace header: [0, 256) running maximum of the CFL reduction,
@@ -146,9 +153,66 @@ hipEvent_t* take_events() {
   return ev;
 }
 
-hipError_t run_stages(const nyx_params* p, StepArgs a, hipStream_t s) {
-  a.ev = take_events();
+hipError_t run_stages(const nyx_params* p, StepArgs a, hipStream_t s, bool timed = true) {
+  a.ev = timed ? take_events() : nullptr;
   return p->precision == NYX_MIXED ? mixed::launch_step(a, s) : fp64::launch_step(a, s);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of the current GPU's scratch array, looked up once per
+// device (with that device current); nullptr on a HIP error.
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+// The single-box step on a validated box and workspace (shared by
+// nyx_hydro_step and nyx_hydro_step_noalloc).
+int step_one_box(const nyx_params* p, const nyx_box* box, const double* state_in,
+                 const void* grav, double dt, double a_old, double a_new, double* state_out,
+                 double* dt_next, nyx_stats* stats, void* workspace, hipStream_t s,
+                 bool timed) {
+  StepArgs A{};
+  box_layout(*box, 0, 0, &A.single);
+  set_blocks(A.single, A.nblocks);
+  fill_physics(A, p);
+  A.Uin = state_in;
+  A.Uout = state_out;
+  A.grav = grav;
+  A.work = (char*)workspace + kHeaderBytes;
+  A.smax = (unsigned long long*)workspace;
+  A.dt_host = dt;
+  A.a_old = a_old;
+  A.a_new = a_new;
+  A.stats = stats;
+  A.slots = (unsigned long long*)((char*)workspace + kOffSlots);
+  A.dt_next = dt_next;
+  BoxDev* tab = (BoxDev*)((char*)workspace + kOffTable);
+  int* pre = (int*)((char*)workspace + kOffPrefix);
+  StepC* cst = (StepC*)((char*)workspace + kOffConsts);
+  if (launch_prologue(A, 1, cst, tab, pre, s) != hipSuccess) return NYX_E_HIP;
+  A.table = tab;
+  A.nb = 1;
+  for (int k = 0; k < 3; ++k) A.prefix[k] = pre + 2 * k;
+  A.consts = cst;
+  // the running CFL maximum and the partial counters start from zero (fill
+  // kernels, so that a captured graph holds no memset node)
+  if (dt_next && launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
+  if (stats && launch_zero_u64(A.slots, kStatSlots * kStatFields, s) != hipSuccess) return NYX_E_HIP;
+  if (run_stages(p, A, s, timed) != hipSuccess) return NYX_E_HIP;
+  if (stats && launch_stats_reduce(A.slots, stats, s) != hipSuccess) return NYX_E_HIP;
+  if (dt_next && launch_dt_finalize(A, a_new, p->cfl, dt_next, s) != hipSuccess) return NYX_E_HIP;
+  return NYX_OK;
 }
 
 }  // namespace
@@ -187,6 +251,8 @@ const char* nyx_status_string(int s) {
     case NYX_E_HIP: return "HIP runtime or launch error";
     case NYX_E_UNSUPPORTED: return "combination not supported by this library";
     case NYX_E_WORKSPACE: return "workspace too small or misaligned";
+    case NYX_E_SCRATCH:
+      return "box needs more scratch than the allocation-free entry point holds";
     default: return "unknown status";
   }
 }
@@ -236,36 +302,34 @@ int nyx_hydro_step(const nyx_params* p, const nyx_box* box, const double* state_
   size_t need = 0;
   nyx_workspace_bytes(p, box, &need);
   if (ws_bytes < need || ((uintptr_t)workspace & 255)) return NYX_E_WORKSPACE;
-  StepArgs A{};
-  box_layout(*box, 0, 0, &A.single);
-  set_blocks(A.single, A.nblocks);
-  fill_physics(A, p);
-  A.Uin = state_in;
-  A.Uout = state_out;
-  A.grav = grav;
-  A.work = (char*)workspace + kHeaderBytes;
-  A.smax = (unsigned long long*)workspace;
-  A.dt_host = dt;
-  A.a_old = a_old;
-  A.a_new = a_new;
-  A.stats = stats;
-  A.slots = (unsigned long long*)((char*)workspace + kOffSlots);
-  A.dt_next = dt_next;
-  hipStream_t s = (hipStream_t)stream;
-  BoxDev* tab = (BoxDev*)((char*)workspace + kOffTable);
-  int* pre = (int*)((char*)workspace + kOffPrefix);
-  StepC* cst = (StepC*)((char*)workspace + kOffConsts);
-  if (launch_prologue(A, 1, cst, tab, pre, s) != hipSuccess) return NYX_E_HIP;
-  A.table = tab;
-  A.nb = 1;
-  for (int k = 0; k < 3; ++k) A.prefix[k] = pre + 2 * k;
-  A.consts = cst;
-  if (dt_next && launch_zero_u64(A.smax, 1, s) != hipSuccess) return NYX_E_HIP;
-  if (stats && launch_zero_u64(A.slots, kStatSlots * kStatFields, s) != hipSuccess) return NYX_E_HIP;
-  if (run_stages(p, A, s) != hipSuccess) return NYX_E_HIP;
-  if (stats && launch_stats_reduce(A.slots, stats, s) != hipSuccess) return NYX_E_HIP;
-  if (dt_next && launch_dt_finalize(A, a_new, p->cfl, dt_next, s) != hipSuccess) return NYX_E_HIP;
+  return step_one_box(p, box, state_in, grav, dt, a_old, a_new, state_out, dt_next, stats,
+                      workspace, (hipStream_t)stream, true);
+}
+
+int nyx_noalloc_max_bytes(size_t* bytes) {
+  if (!bytes) return NYX_E_NULL;
+  *bytes = kScratchBytes;
   return NYX_OK;
+}
+
+int nyx_hydro_step_noalloc(const nyx_params* p, const nyx_box* box, const double* state_in,
+                           const void* grav, double dt, double a_old, double a_new,
+                           double* state_out, double* dt_next, nyx_stats* stats, void* stream) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if ((rc = check_box(box))) return rc;
+  if (!state_in || !grav || !state_out) return NYX_E_NULL;
+  if (!finite_pos(dt) || !finite_pos(a_old) || !finite_pos(a_new)) return NYX_E_PARAM;
+  size_t span = state_span_bytes(*box);
+  if (overlaps(state_in, span, state_out, span)) return NYX_E_ALIAS;
+  size_t need = 0;
+  nyx_workspace_bytes(p, box, &need);
+  if (need > kScratchBytes) return NYX_E_SCRATCH;
+  void* ws = scratch_address();
+  if (!ws) return NYX_E_HIP;
+  // no stage timing here: the profiler creates events on demand
+  return step_one_box(p, box, state_in, grav, dt, a_old, a_new, state_out, dt_next, stats, ws,
+                      (hipStream_t)stream, false);
 }
 
 }  // extern "C"

@@ -258,3 +258,33 @@ def test_gravity_entry_points_validate_before_launch(nyx):
     assert L.nyx_cic_deposit(fake, fake, -1, dom, 1 / 16, fake, None) == -3
     assert L.nyx_cic_deposit(fake, fake, 0, dom, 1 / 16, None, None) == -1
     assert L.nyx_cic_deposit(fake, fake, 0, dom, 1 / 16, fake, None) == 0  # nothing to do
+
+
+def _noalloc(nyx, p, b, sin=0x10000000, g=0x20000000, dt=1e-3, ao=0.5, an=0.51, sout=0x30000000):
+    L = nyx.lib()
+    return L.nyx_hydro_step_noalloc(ctypes.byref(p) if p is not None else None,
+                                    ctypes.byref(b) if b is not None else None, sin, g, dt, ao,
+                                    an, sout, None, None, None)
+
+
+def test_noalloc_step_validates_before_launch(nyx):
+    # host-side checks only: every case returns before any GPU call
+    p = nyx.default_params()
+    b = nyx.make_box((8, 8, 8), 4, 0.1)
+    assert _noalloc(nyx, None, b) == -1
+    assert _noalloc(nyx, p, None) == -1
+    assert _noalloc(nyx, p, b, sin=None) == -1
+    assert _noalloc(nyx, p, b, dt=0.0) == -3
+    assert _noalloc(nyx, p, b, sout=0x10000008) == -4
+    assert _noalloc(nyx, p, nyx.make_box((7, 8, 8), 4, 0.1)) == -2
+    # the scratch limit: the largest cube that fits, and the next even one
+    cap = nyx.noalloc_max_bytes()
+    assert cap == 64 << 20
+    for prec in (nyx.NYX_FP64, nyx.NYX_MIXED):
+        q = nyx.default_params(precision=prec)
+        fits = [m for m in range(8, 200, 2)
+                if nyx.workspace_bytes(q, nyx.make_box((m, m, m), 4, 0.1)) <= cap]
+        big = nyx.make_box((fits[-1] + 2,) * 3, 4, 0.1)
+        assert _noalloc(nyx, q, big) == -8
+        assert nyx.lib().nyx_status_string(-8).decode().startswith("box needs more scratch")
+    assert fits[-1] >= 48  # FP32-mixed holds the 48^3 boxes of the level workload
