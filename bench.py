@@ -1,38 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the comoving PPM gas step on one MI355X.
 
-Headline workload (box256_smooth): one periodic 256^3 box (+4 ghost cells)
-with the smooth-flow fields of the single-box configuration (rho lognormal
-sigma_ln 0.3, k^-2 velocity sigma 0.5, p = 0.6 rho^gamma, g ~ N(0, 0.05^2)),
-a from 0.25 linearly over 20 steps to 0.26, CFL 0.5, dt from the fused CFL
-reduction of the previous step (device-resident, no host round trip).  One
-timed step is [hydro step with fused dt_next -> periodic ghost fill].
+Headline workload (box512_stress): the 512^3 stress box (density contrast up
+to 10^4 with ln rho ~ N(., 2^2) clipped at +-ln 100, T/T_mean lognormal
+sigma_ln 1.5, k^-2 velocities of sigma 0.5 clipped to Mach 30, g ~ N(0,
+0.2^2)), a 0.10 -> 0.11 over 10 steps, one level dt.  The metric compares,
+on the same GPU and inputs:
+  * plain FP64 with the domain as one box (one launch per stage);
+  * the chosen form: FP32-mixed + batched, the domain as an 8^3 grid of 64^3
+    patches in one batched plan with the same-level ghost fill, with or
+    without the learned Riemann flux (network trained, untimed, on about 2e7
+    faces harvested from stress fields of other seeds).
+`value` is the fastest FP32-mixed batched form whose density stays within
+1e-3 relative L1 of plain FP64 after the timed steps (the FP64 run's dt
+sequence drives every form); every form's rate, error and fallback rate is
+in the line.  One timed step is [batched step -> patch-grid ghost fill].
 
-Forms on the same GPU and inputs: plain FP64, FP32-mixed, and FP32-mixed with
-the learned Riemann flux on all twelve solves per zone or on stages 0 and 1
-only (trained beforehand, untimed, on about 2e7 faces harvested from other
-seeds).  The headline value is the fastest form whose density
-stays within 1e-3 relative L1 of plain FP64 after the timed steps.
+`roofline` is that of the chosen form's dominant stage kernel: algorithmic
+flops per launch (the oracle's operation counts per work unit,
+profiles/opcounts_step.json, times the launch's units, with the measured
+two-shock iterations) over the launch's mean duration from HIP events the
+library records around its stage launches on the step's stream.
+`hbm_step` is the whole step's algorithmic bytes (the padded state and
+gravity read once, the valid state written once) over the step time.
 
-Batched-level leg (level4096): 4096 boxes with edges drawn from {16, 24, 32,
-48, 64} per axis, self-periodic ghosts, per-box dt: one batched plan per
-step (also replayed as a captured HIP graph) against per-box launches.
-
-Variants leg: PLM reconstruction, the linearised Riemann solver and the
-second form of the energy gravity term (Sec. 3.2) on the same box, each in
-FP32-mixed against its own plain FP64 run.
-
-Level-fill leg: the ghost fill of AMR levels (same-level copies, and
-coarse-fine interpolation from a coarser level), rated in algorithmic GB/s.
-
-Stress leg (box512_stress): a 512^3 domain with density contrast up to 10^4
-and flows up to Mach 30, plain FP64 as one box against FP32-mixed (and the
-learned flux, trained on smooth flows or on stress faces) on an 8^3 grid of
-64^3 patches with the same-level ghost fill and one level dt; density
-relative L1 against FP64 and the fallback rate.
-
-Stage times come from HIP events the library records between its stage
-launches on the step's stream.
+Other legs (same JSON line):
+  box256 (single 256^3 box of smooth flow, 20 steps): plain FP64 vs FP32-mixed;
+  learned256 (a fresh-seed 256^3 box of the same type, 20 steps): FP32-mixed
+    with and without the learned flux (all twelve solves, or stages 0-1);
+  level4096 (4096 boxes, edges from {16, 24, 32, 48, 64}, per-box dt, a
+    0.25 -> 0.255): batched plan, its HIP-graph replay and the learned form,
+    against per-box plain FP64 launches, with density error against FP64;
+  variants (PLM, linearised solver, gravity form 2, gamma 1.4), level
+  ghost fill, two-level reflux/average-down, gravity input;
+  cpu_baseline: the FP64 oracle on 64^3 patches of the headline fields, on
+  all usable host cores (threads, at most 16) and on one.
 """
 from __future__ import annotations
 
@@ -47,31 +49,64 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-updates/s (plain FP64 vs FP32+batched+learned flux) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+ALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, FP64 and FP32
 STAGES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")
+RIEMANN = ("riem0", "riem1", "riem2")
+OPCOUNTS = os.path.join(ROOT, "profiles", "opcounts_step.json")
+OPCOUNT_KEYS = {"box256": "box256_smooth fields (64^3 box of the same distributions, seed 2)",
+                "box512_stress": "box512_stress fields (64^3 box of the same distributions, seed 5)"}
 
 
-def flops_per_launch(stage, n, it):
-    """Algorithmic floating-point operations of one stage launch on an n^3 box
-    (+, -, *, /, sqrt count 1 each; comparisons, min/max, selects 0), read off
-    the stage formulas; `it` is the mean two-shock iteration count."""
-    P, E, V = (n + 8) ** 3, (n + 2) ** 3, n ** 3
-    solve = 76.0 + 36.0 * it
-    return {
-        "prim": 10.0 * P,
-        "flat": 69.0 * E,
-        "trace": 530.0 * 3 * E,
-        "riem0": solve * 3 * (n + 1) * (n + 2) ** 2,
-        "riem1": (172.0 + solve) * 6 * n * (n + 1) * (n + 2),
-        "riem2": (278.0 + solve) * 3 * n * n * (n + 1),
-        "update": 252.0 * V,
-    }[stage]
+def units(n):
+    """Work units of each stage kernel's grid on one box n = (nx, ny, nz):
+    padded cells, cells of [-1, n]^3, tracing cell-directions, the faces of
+    each Riemann stage, valid cells."""
+    nx, ny, nz = n
+    P = (nx + 8) * (ny + 8) * (nz + 8)
+    E = (nx + 2) * (ny + 2) * (nz + 2)
+    ext = (nx, ny, nz)
+    f0 = f1 = f2 = 0
+    for d in range(3):
+        e = [x + 2 for x in ext]
+        e[d] = ext[d] + 1
+        f0 += e[0] * e[1] * e[2]
+        for t in range(3):
+            if t != d:
+                e1 = [x + 2 for x in ext]
+                e1[d] = ext[d] + 1
+                e1[t] = ext[t]
+                f1 += e1[0] * e1[1] * e1[2]
+        e2 = list(ext)
+        e2[d] = ext[d] + 1
+        f2 += e2[0] * e2[1] * e2[2]
+    return {"prim": P, "flat": E, "trace": 3 * E, "riem0": f0, "riem1": f1, "riem2": f2,
+            "update": nx * ny * nz}
+
+
+def flop_table(key):
+    """Per-unit flops of each stage counted by the oracle on `key`'s fields."""
+    with open(OPCOUNTS) as fh:
+        return json.load(fh)["workloads"][OPCOUNT_KEYS[key]]
+
+
+def stage_flops(table, stage, shapes, iters_per_face):
+    """Algorithmic flops of one launch of `stage` over boxes of `shapes`: the
+    oracle's flops per unit times the units; for a Riemann stage the flops
+    outside the Newton iterations per face plus the flops of one iteration
+    times the measured iterations per face (the GPU's counter, the mean over
+    the three Riemann stages)."""
+    u = sum(units(n)[stage] for n in shapes)
+    row = table[stage]
+    if stage in RIEMANN:
+        return u * (row["flops_per_face_outside_iterations"] +
+                    row["flops_per_iteration"] * iters_per_face)
+    return u * row["flops_per_unit"]
 
 
 def bytes_per_launch(stage, n, rb):
-    """Algorithmic HBM bytes of one stage launch: every distinct input value
-    read once and every output written once (rb = bytes of a stage-array
-    element: 8 in FP64, 4 in FP32-mixed)."""
+    """Algorithmic HBM bytes of one stage launch on an n^3 box in this staged
+    design: every distinct input value read once and every output written
+    once (rb = bytes of a stage-array element: 8 in FP64, 4 in FP32-mixed)."""
     P, E, V = (n + 8) ** 3, (n + 2) ** 3, n ** 3
     return {
         "prim": 6 * 8 * P + 6 * rb * P,
@@ -84,6 +119,57 @@ def bytes_per_launch(stage, n, rb):
     }[stage]
 
 
+def step_bytes(shapes, grav_bytes):
+    """Algorithmic bytes of one whole step (one fused pass): the padded FP64
+    state and the padded gravity read once, the valid FP64 state written
+    once."""
+    tot = 0
+    for (nx, ny, nz) in shapes:
+        P = (nx + 8) * (ny + 8) * (nz + 8)
+        tot += (48 + 3 * grav_bytes) * P + 48 * nx * ny * nz
+    return tot
+
+
+def roofline_of(stage_ms, table, shapes, iters, step_ms, grav_bytes, form, workload,
+                tune=None, persistent_ms=None):
+    """The dominant kernel's figures: algorithmic TFLOP/s against the vector
+    ALU peak (the dominant stage kernel, or the persistent step kernel, which
+    runs every stage), and the whole step's algorithmic bytes against HBM."""
+    if persistent_ms is not None:
+        dom, ms = "step_persistent", persistent_ms
+        fl = sum(stage_flops(table, st, shapes, iters) for st in STAGES)
+    else:
+        dom = max(STAGES, key=lambda s: stage_ms[s])
+        ms = stage_ms[dom]
+        fl = stage_flops(table, dom, shapes, iters)
+    ach = fl / (ms * 1e-3) / 1e12
+    t = None
+    if tune is not None and persistent_ms is None:
+        t = measured_traffic(dom, form, tune[STAGES.index(dom)], workload)
+    roof = {"bound": "alu" if dom in RIEMANN + ("trace", "step_persistent") else "hbm",
+            "kernel": dom, "ms_per_launch": round(ms, 4),
+            "flops_per_launch": fl, "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 4), "traffic": t}
+    if roof["bound"] == "hbm":
+        b = sum(bytes_per_launch(dom, n[0], 4) for n in shapes)
+        gbs = b / (ms * 1e-3) / 1e9
+        roof.update({"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    sb = step_bytes(shapes, grav_bytes)
+    gbs = sb / (step_ms * 1e-3) / 1e9
+    hbm = {"bytes_per_step": sb, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return roof, hbm
+
+
+def stage_rates(stage_ms, table, shapes, iters):
+    """Per-stage ms, algorithmic TFLOP/s (oracle op counts)."""
+    out = {}
+    for s in STAGES:
+        ms = stage_ms[s]
+        fl = stage_flops(table, s, shapes, iters)
+        out[s] = {"ms": round(ms, 4), "tflops": round(fl / max(ms, 1e-9) / 1e9, 3)}
+    return out
 KERNEL_SOURCES = ("paper_1301_4498_amd/csrc/nyx_step.hip", "paper_1301_4498_amd/csrc/nyx_internal.h",
                   "paper_1301_4498_amd/csrc/nyx_mlp_dev.h")
 
@@ -112,18 +198,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, form, candidate):
+def measured_traffic(kernel, form, candidate, workload=None):
     """HBM bytes per launch of `kernel` under launch-order candidate
     `candidate` (the autotuner's choice for its stage) from the committed
-    rocprofv3 counter record (profiles/traffic_*.json), or None when that
-    record was taken on different kernel sources.  The record holds one value
-    per candidate: the cell order changes how often neighbours are re-read
-    from HBM, so the traffic of one order says nothing of another."""
+    rocprofv3 counter record (profiles/traffic_*.json) of that workload, or
+    None when no record was taken on the current kernel sources.  A record
+    holds one value per candidate: the cell order changes how often
+    neighbours are re-read from HBM, so the traffic of one order says
+    nothing of another."""
     import glob
-    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
         with open(path) as fh:
             rec = json.load(fh)
         if (rec.get("kernel") == kernel and rec.get("form") == form and
+                (workload is None or rec.get("workload") == workload) and
                 rec.get("sources_sha256") == kernel_source_hash()):
             return rec["bytes_per_launch_by_candidate"][candidate]
     return None
@@ -135,9 +223,60 @@ def aligned(torch, nbytes):
     return raw[off:off + nbytes]
 
 
-def run_box(nyx, torch, w, prm, steps, warmup):
+
+
+def run_plan(nyx, torch, plan, A0, bufs, G, steps, warmup, dt_of, a_at, fill, dt_next_of=None):
+    """`warmup` untimed steps of a batched plan from the initial state A0,
+    with the device counters summed over them; then, from A0 again, `steps`
+    timed steps (HIP events on torch's current stream, the library's stream)
+    with the library's per-stage events.  dt_of(k) / dt_next_of(k): device dt
+    tensors of step k.  Returns ms per step, per-stage ms per step, the
+    counters and the final state buffer."""
+    st = torch.zeros(10, dtype=torch.int64, device="cuda")
+    bufs[0].copy_(A0)
+    for k in range(max(min(warmup, steps), 1)):
+        plan.step(bufs[k % 2], G, dt_of(k), a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
+                  dt_next=dt_next_of(k) if dt_next_of else None, stats=st)
+        fill(bufs[(k + 1) % 2])
+    torch.cuda.synchronize()
+    stats = nyx.stats_dict(st)
+    bufs[0].copy_(A0)
+    torch.cuda.synchronize()
+    nyx._lib.profile_enable(True)
+    nyx._lib.profile_read(reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    e0.record()
+    for k in range(steps):
+        ev[k][0].record()
+        plan.step(bufs[k % 2], G, dt_of(k), a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
+                  dt_next=dt_next_of(k) if dt_next_of else None)
+        ev[k][1].record()
+        fill(bufs[(k + 1) % 2])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stage_ms, seq = nyx._lib.profile_read(reset=True)
+    nyx._lib.profile_enable(False)
+    stage_ms = {s: v / max(seq, 1) for s, v in stage_ms.items()}
+    # the step call alone (every kernel it enqueues), per step
+    stage_ms["step_call"] = sum(a.elapsed_time(b) for a, b in ev) / steps
+    return ms, stage_ms, stats, bufs[steps % 2]
+
+
+def iters_per_face(stats):
+    return stats["riemann_iters"] / max(stats["riemann_calls"], 1)
+
+
+def fallback_rate(stats):
+    return stats["mlp_fallback"] / max(stats["mlp_used"] + stats["mlp_fallback"], 1)
+
+
+def run_box(nyx, torch, w, prm, steps, warmup, table):
     """Time `steps` steps (after `warmup`) of one periodic box with a one-box
-    batched plan; returns rates, stage times and the final density."""
+    batched plan and device-resident dt from the fused CFL of the previous
+    step; returns rates, stage times and the final density."""
     n = w.n[0]
     box = nyx.make_box(w.n, 4, w.dx)
     gdt = torch.float64 if prm.precision == nyx.NYX_FP64 else torch.float32
@@ -168,7 +307,7 @@ def run_box(nyx, torch, w, prm, steps, warmup):
         one_step(st if i == 0 else None)  # counters of the first step
     torch.cuda.synchronize()
     stats = nyx.stats_dict(st)
-    it = stats["riemann_iters"] / max(stats["riemann_calls"], 1)
+    it = iters_per_face(stats)
     nyx._lib.profile_enable(True)
     nyx._lib.profile_read(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -182,23 +321,195 @@ def run_box(nyx, torch, w, prm, steps, warmup):
     ms = e0.elapsed_time(e1)
     stage_ms, seq = nyx._lib.profile_read(reset=True)
     nyx._lib.profile_enable(False)
+    stage_ms = {s: v / max(seq, 1) for s, v in stage_ms.items()}
     rho = bufs[k % 2].reshape(6, n + 8, n + 8, n + 8)[0, 4:-4, 4:-4, 4:-4].cpu().numpy()
     finite = bool(torch.isfinite(bufs[k % 2]).all().item())
     plan.close()
     del ws, U, Uo, G, bufs
     torch.cuda.empty_cache()
-    rb = 8 if prm.precision == nyx.NYX_FP64 else 4
-    per_stage = {}
-    for s in STAGES:
-        tl = stage_ms[s] / max(seq, 1)
-        per_stage[s] = {"ms": round(tl, 4),
-                        "tflops": round(flops_per_launch(s, n, it) / (tl * 1e-3) / 1e12, 3),
-                        "gbs": round(bytes_per_launch(s, n, rb) / (tl * 1e-3) / 1e9, 1)}
+    mixed = prm.precision != nyx.NYX_FP64
+    roof, hbm = roofline_of(stage_ms, table, [w.n], it, ms / steps, 4 if mixed else 8,
+                            "fp64" if not mixed else "mixed", "box256_smooth", tune)
     return {"zone_updates_per_s": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
-            "stage": per_stage, "mean_riemann_iters": it, "stats_first_step": stats,
-            "finite": finite, "rho": rho, "tuning": tune, "tuning_ms": tune_ms}
+            "stage": stage_rates(stage_ms, table, [w.n], it), "mean_riemann_iters": it,
+            "stats_first_step": stats, "finite": finite, "rho": rho, "tuning": tune,
+            "tuning_ms": tune_ms, "roofline": roof, "hbm_step": hbm}
 
 
+def box256_leg(nyx, torch, synth, steps, warmup, log, n=256):
+    """Single 256^3 box of smooth flow (seed 2): plain FP64 against
+    FP32-mixed."""
+    import numpy as np
+    w = synth.config2(n=n)
+    table = flop_table("box256")
+    out = {"workload": "box256_smooth: one periodic %d^3 box + 4 ghosts, smooth-flow fields "
+                       "(seed 2), a 0.25->0.26, CFL 0.5" % n, "steps": steps, "forms": {}}
+    res = {}
+    for f, prec in (("fp64", nyx.NYX_FP64), ("mixed", nyx.NYX_MIXED)):
+        res[f] = run_box(nyx, torch, w, nyx.default_params(precision=prec), steps, warmup, table)
+        log("box256 %s: %.3e zone-updates/s" % (f, res[f]["zone_updates_per_s"]))
+    for f, v in res.items():
+        v["rho_l1_vs_fp64"] = float(np.abs(v["rho"] - res["fp64"]["rho"]).sum() /
+                                    np.abs(res["fp64"]["rho"]).sum())
+        out["forms"][f] = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage",
+                                             "mean_riemann_iters", "finite", "rho_l1_vs_fp64",
+                                             "tuning", "roofline", "hbm_step")}
+    return out, w
+
+
+def learned256_leg(nyx, torch, synth, learn, flux, steps, warmup, log, n=256):
+    """A fresh-seed 256^3 box of the smooth-flow type (seed 7, not a training
+    seed), 20 steps: FP32-mixed against the learned flux on all twelve
+    solves per zone and on stages 0-1 only; density L1 against FP64 and
+    against FP32-mixed, fallback rate."""
+    import numpy as np
+    w = synth.config2(n=n, seed=7)
+    table = flop_table("box256")
+    out = {"workload": "box256_smooth type, seed 7 (fresh), %d^3, a 0.25->0.26" % n,
+           "steps": steps, "forms": {}}
+    res = {}
+    for f in ("fp64", "mixed", "learned", "learned01"):
+        if f == "fp64":
+            prm = nyx.default_params(precision=nyx.NYX_FP64)
+        elif f == "mixed":
+            prm = nyx.default_params(precision=nyx.NYX_MIXED)
+        else:
+            prm = learn.learned_params(flux, tol=1e-3, stages=7 if f == "learned" else 3)
+        res[f] = run_box(nyx, torch, w, prm, steps, warmup, table)
+        log("learned256 %s: %.3e zone-updates/s" % (f, res[f]["zone_updates_per_s"]))
+    for f, v in res.items():
+        r = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage", "mean_riemann_iters",
+                               "finite")}
+        for ref in ("fp64", "mixed"):
+            r["rho_l1_vs_" + ref] = float(np.abs(v["rho"] - res[ref]["rho"]).sum() /
+                                          np.abs(res[ref]["rho"]).sum())
+        if f.startswith("learned"):
+            r["fallback_rate"] = fallback_rate(v["stats_first_step"])
+            r["gain_vs_mixed"] = v["zone_updates_per_s"] / res["mixed"]["zone_updates_per_s"]
+        out["forms"][f] = r
+    return out
+
+
+def headline_leg(nyx, torch, synth, learn, steps, warmup, log, n=512, m=64, learned=True):
+    """box512_stress: plain FP64 with the domain as one box, against
+    FP32-mixed (and mixed + learned flux trained on stress faces) on an
+    (n/m)^3 grid of m^3 patches in one batched plan with the same-level
+    ghost fill and one level dt (the FP64 run's dt sequence).  Every plan is
+    autotuned (untimed) first."""
+    t0 = time.perf_counter()
+    grid = (n // m,) * 3
+    nb = grid[0] * grid[1] * grid[2]
+    a0, a1 = 0.10, 0.11
+    table = flop_table("box512_stress")
+
+    def a_at(k):
+        return a0 + (a1 - a0) * k / steps
+
+    state, grav = synth.stress_fields_torch(n=n)
+    log("stress fields ready in %.1f s" % (time.perf_counter() - t0))
+    zones = n ** 3
+    out = {"workload": "box512_stress: %d^3, density contrast <= 1e4, Mach <= 30, g ~ N(0, 0.2^2), "
+                       "a 0.10->0.11, one level dt" % n, "steps": steps,
+           "patches": "%d x %d^3" % (nb, m), "forms": {}}
+    # plain FP64, one box, dt from its own fused CFL
+    prm = nyx.default_params()
+    box = nyx.make_box((n, n, n), 4, 1.0 / n)
+    _, one = nyx.Batch.workspace_bytes(prm, [box])
+    ws = aligned(torch, one)
+    plan = nyx.Batch(prm, [box], ws)
+    A0 = state
+    bufs = [state.clone(), torch.empty_like(state)]
+    dts = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    plan.estimate_dt(A0, a0, 0.5, dts[0:1])
+    tune, _ = plan.autotune(A0, grav, dts[0:1], a_at(0), a_at(1), bufs[1], reps=2)
+    ms, stage_ms, st, fin = run_plan(nyx, torch, plan, A0, bufs, grav, steps, warmup,
+                                     lambda k: dts[k:k + 1], a_at, plan.fill_ghosts,
+                                     dt_next_of=lambda k: dts[k + 1:k + 2])
+    rho64 = fin[0, 4:-4, 4:-4, 4:-4].contiguous()
+    it = iters_per_face(st)
+    roof, hbm = roofline_of(stage_ms, table, [(n, n, n)], it, ms, 8, "fp64", "box512_stress",
+                            tune)
+    out["forms"]["fp64_one_box"] = {
+        "zone_updates_per_s": zones / (ms * 1e-3), "ms_per_step": ms,
+        "stage": stage_rates(stage_ms, table, [(n, n, n)], it), "mean_riemann_iters": it,
+        "stats": st, "tuning": tune, "roofline": roof, "hbm_step": hbm,
+        "finite": bool(torch.isfinite(fin).all().item())}
+    log("stress fp64 one box: %.3e zone-updates/s" % (zones / (ms * 1e-3)))
+    dt_host = dts.cpu().tolist()
+    plan.close()
+    del plan, ws, bufs, fin
+    torch.cuda.empty_cache()
+    # the same domain as patches (FP32 gravity), the FP64 run's level dt
+    P = (m + 8) ** 3
+    A0 = torch.cat([p.reshape(-1) for p in synth.split_patches(state, grid)])
+    G32 = torch.cat([p.reshape(-1).float() for p in synth.split_patches(grav, grid)])
+    sample = [(synth.split_patches(state, grid)[b].cpu().numpy(),
+               synth.split_patches(grav, grid)[b].cpu().numpy()) for b in range(0, nb, nb // 64)]
+    del state, grav
+    torch.cuda.empty_cache()
+    dtp = dts[:steps, None].expand(steps, nb).contiguous()
+    boxes = [nyx.make_box((m, m, m), 4, 1.0 / n, state_off=6 * P * b, grav_off=3 * P * b)
+             for b in range(nb)]
+    shapes = [(m, m, m)] * nb
+    # the mixed form as built (the star-state iteration stops at FP32
+    # resolution), and with the FP64 form's stopping rule for comparison
+    runs = [("mixed_patches", nyx.default_params(precision=nyx.NYX_MIXED)),
+            ("mixed_patches_fp64_stop", nyx.default_params(precision=nyx.NYX_MIXED,
+                                                           mixed_riemann_stop=1e-14))]
+    if learned:
+        sflux, out["learned_training"] = train_learned_stress(nyx, learn, synth, log)
+        runs.append(("learned_patches", learn.learned_params(sflux, tol=1e-3, stages=7)))
+    for name, prm in runs:
+        _, one = nyx.Batch.workspace_bytes(prm, boxes)
+        ws = aligned(torch, one)
+        plan = nyx.Batch(prm, boxes, ws)
+        bufs = [A0.clone(), torch.empty_like(A0)]
+        # launch orders by time; near-ties go to the order with the least
+        # HBM traffic where a counter record of the current kernels exists
+        traffic = {}
+        for i, stg in enumerate(STAGES):
+            per = [measured_traffic(stg, "mixed", c, "box512_stress_patches") for c in range(16)]
+            if all(v is not None for v in per):
+                traffic[i] = per
+        tune, _ = plan.autotune(A0, G32, dtp[0], a_at(0), a_at(1), bufs[1], reps=2,
+                                traffic=(traffic or None) if name == "mixed_patches" else None)
+        # staged or persistent launch, whichever is faster for this plan
+        mode, mode_ms = plan.autotune_mode(A0, G32, dtp[0], a_at(0), a_at(1), bufs[1], reps=2)
+        persistent = mode == nyx.NYX_LAUNCH_PERSISTENT
+
+        def fill(s):
+            plan.fill_ghosts(s, mode=1, grid=grid)
+
+        ms, stage_ms, st, fin = run_plan(nyx, torch, plan, A0, bufs, G32, steps, warmup,
+                                         lambda k: dtp[k], a_at, fill)
+        if persistent:
+            assert not plan.persistent_aborted()
+        rho = synth.join_valid(fin, grid, (m, m, m))[0]
+        l1 = float((rho - rho64).abs().sum() / rho64.abs().sum())
+        it = iters_per_face(st)
+        roof, hbm = roofline_of(stage_ms, table, shapes, it, ms, 4, "mixed",
+                                "box512_stress_patches", tune,
+                                persistent_ms=stage_ms["step_call"] if persistent else None)
+        r = {"zone_updates_per_s": zones / (ms * 1e-3), "ms_per_step": ms,
+             "rho_l1_vs_fp64": l1, "finite": bool(torch.isfinite(fin).all().item()),
+             "launch_mode": "persistent" if persistent else "staged",
+             "mode_step_ms": {"staged": mode_ms[0], "persistent": mode_ms[1]},
+             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it),
+             "step_call_ms": stage_ms["step_call"], "mean_riemann_iters": it,
+             "stats": st, "tuning": tune, "roofline": roof, "hbm_step": hbm}
+        if name.startswith("learned"):
+            r["fallback_rate"] = fallback_rate(st)
+        out["forms"][name] = r
+        log("stress %s: %.3e zone-updates/s, rho L1 vs FP64 %.2e" % (name, r["zone_updates_per_s"], l1))
+        plan.close()
+        del plan, ws, bufs, fin
+        torch.cuda.empty_cache()
+    if "learned_patches" in out["forms"]:
+        out["forms"]["learned_patches"]["gain_vs_mixed_patches"] = (
+            out["forms"]["learned_patches"]["zone_updates_per_s"] /
+            out["forms"]["mixed_patches"]["zone_updates_per_s"])
+    out["dt_first"] = dt_host[0]
+    return out, sample, (a_at(0), a_at(1)), 1.0 / n
 def train_learned(nyx, learn, synth, log):
     """Harvest about 2e7 final-stage faces of plain FP64 steps on ten 64^3
     boxes of the same field type (seeds 100-109) and train the network
@@ -235,51 +546,101 @@ def train_learned_stress(nyx, learn, synth, log):
     return f, info
 
 
-def level_leg(nyx, torch, synth, steps, log):
-    """4096 uneven boxes: batched plan (+ graph) against per-box launches."""
+
+
+def level_leg(nyx, torch, synth, learn, flux, steps, warmup, log):
+    """4096 uneven boxes (each axis from {16, 24, 32, 48, 64}), smooth-flow
+    fields per box, self-periodic ghosts, a 0.25 -> 0.255 over the steps.
+    Plain FP64 batched first, with per-box dt from its fused CFL; its dt
+    sequence then drives FP32-mixed batched (also replayed as a captured HIP
+    graph) and mixed + learned flux, whose densities are compared with the
+    FP64 run's over every box's valid cells; per-box FP64 launches (one
+    nyx_hydro_step per box) are the baseline of the batching gain."""
     shapes = synth.config3_shapes()
     t0 = time.perf_counter()
-    out = {"boxes": len(shapes), "valid_cells": int(sum(a * b * c for a, b, c in shapes))}
-    zones = out["valid_cells"]
+    V = int(sum(a * b * c for a, b, c in shapes))
+    out = {"boxes": len(shapes), "valid_cells": V, "steps": steps, "a": [0.25, 0.255]}
+    a0, a1 = 0.25, 0.255
+
+    def a_at(k):
+        return a0 + (a1 - a0) * k / steps
+
+    table = flop_table("box256")
     res = {}
-    for form, prec in (("mixed", nyx.NYX_MIXED), ("fp64", nyx.NYX_FP64)):
-        gdt = torch.float32 if prec == nyx.NYX_MIXED else torch.float64
-        state, grav, offs = synth.level_fields_torch(shapes, grav_dtype=gdt)
+    rho64 = None
+    dt_seq = None
+    forms = [("fp64", nyx.default_params(precision=nyx.NYX_FP64)),
+             ("mixed", nyx.default_params(precision=nyx.NYX_MIXED))]
+    if flux is not None:
+        forms.append(("learned", learn.learned_params(flux, tol=1e-3, stages=7)))
+    gdt_of = {"fp64": torch.float64, "mixed": torch.float32, "learned": torch.float32}
+    for form, prm in forms:
+        state, grav, offs = synth.level_fields_torch(shapes, grav_dtype=gdt_of[form])
         log("level fields (%s) ready in %.1f s" % (form, time.perf_counter() - t0))
         boxes = [nyx.make_box(n, 4, 1.0 / 256, state_off=so, grav_off=go)
                  for n, (so, go) in zip(shapes, offs)]
-        prm = nyx.default_params(precision=prec)
-        mn, one = nyx.Batch.workspace_bytes(prm, boxes)
+        _, one = nyx.Batch.workspace_bytes(prm, boxes)
         free = torch.cuda.mem_get_info()[0]
-        wsb = min(one, int(free - 2 * state.numel() * 8 - (8 << 30)))
+        wsb = min(one, int(free - 3 * state.numel() * 8 - (8 << 30)))
         ws = aligned(torch, wsb)
         plan = nyx.Batch(prm, boxes, ws)
-        other = torch.empty_like(state)
-        dts = [torch.zeros(len(boxes), dtype=torch.float64, device="cuda") for _ in range(2)]
-        plan.estimate_dt(state, 0.25, 0.5, dts[0])
-        tune, tune_ms = plan.autotune(state, grav, dts[0], 0.25, 0.25 + 5e-4, other,
-                                      dt_next=dts[1], reps=2)
-        bufs = [state, other]
-
-        def step(k):
-            plan.step(bufs[k % 2], grav, dts[k % 2], 0.25, 0.25 + 5e-4, bufs[(k + 1) % 2],
-                      dt_next=dts[(k + 1) % 2])
-            plan.fill_ghosts(bufs[(k + 1) % 2])
-
-        step(0)
-        step(1)
-        torch.cuda.synchronize()
+        bufs = [state.clone(), torch.empty_like(state)]
+        if dt_seq is None:
+            dt_seq = torch.zeros((steps + 1, len(boxes)), dtype=torch.float64, device="cuda")
+            plan.estimate_dt(state, a0, 0.5, dt_seq[0])
+            dt_next_of = lambda k: dt_seq[k + 1]  # noqa: E731
+        else:
+            dt_next_of = None
+        tune, _ = plan.autotune(state, grav, dt_seq[0], a_at(0), a_at(1), bufs[1], reps=2)
+        mode_ms = None
+        if form != "fp64":
+            mode, mode_ms = plan.autotune_mode(state, grav, dt_seq[0], a_at(0), a_at(1), bufs[1],
+                                               reps=2)
+        persistent = plan.launch_mode == nyx.NYX_LAUNCH_PERSISTENT
+        ms, stage_ms, st, fin = run_plan(nyx, torch, plan, state, bufs, grav, steps, warmup,
+                                         lambda k: dt_seq[k], a_at, plan.fill_ghosts,
+                                         dt_next_of=dt_next_of)
+        if persistent:
+            assert not plan.persistent_aborted()
+        it = iters_per_face(st)
+        finite = bool(torch.isfinite(fin).all().item())
+        # density of every box's valid cells
+        num = torch.zeros((), dtype=torch.float64, device="cuda")
+        den = torch.zeros((), dtype=torch.float64, device="cuda")
+        rho_boxes = []
+        for n, (so, _go) in zip(shapes, offs):
+            nx, ny, nz = n
+            P = (nx + 8) * (ny + 8) * (nz + 8)
+            r = fin[so:so + P].view(nz + 8, ny + 8, nx + 8)[4:-4, 4:-4, 4:-4]
+            if rho64 is None:
+                rho_boxes.append(r.clone())
+            else:
+                ref = rho64[len(rho_boxes)]
+                rho_boxes.append(None)
+                num += (r - ref).abs().sum()
+                den += ref.abs().sum()
+        if rho64 is None:
+            rho64 = rho_boxes
+        roof, hbm = roofline_of(stage_ms, table, shapes, it, ms, 8 if form == "fp64" else 4,
+                                form, "level4096", tune,
+                                persistent_ms=stage_ms["step_call"] if persistent else None)
+        r = {"batched_zone_updates_per_s": V / (ms * 1e-3), "batched_ms_per_step": ms,
+             "groups": plan.num_groups, "tuning": tune, "finite": finite,
+             "launch_mode": "persistent" if persistent else "staged",
+             "mode_step_ms": mode_ms,
+             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it),
+             "mean_riemann_iters": it, "roofline": roof, "hbm_step": hbm}
+        if form != "fp64":
+            r["rho_l1_vs_fp64"] = float(num / den)
+        if form == "learned":
+            r["fallback_rate"] = fallback_rate(st)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for k in range(steps):
-            step(k)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        r = {"batched_zone_updates_per_s": zones / (ms * 1e-3), "batched_ms_per_step": ms,
-             "groups": plan.num_groups, "tuning": tune, "tuning_ms": tune_ms}
         if form == "mixed":
             # two steps captured once, replayed
+            def step(k):
+                plan.step(bufs[k % 2], grav, dt_seq[k], a_at(k), a_at(k + 1), bufs[(k + 1) % 2])
+                plan.fill_ghosts(bufs[(k + 1) % 2])
+
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
@@ -296,124 +657,37 @@ def level_leg(nyx, torch, synth, steps, log):
             e1.record()
             torch.cuda.synchronize()
             gms = e0.elapsed_time(e1) / (2 * (steps // 2))
-            r["graph_zone_updates_per_s"] = zones / (gms * 1e-3)
+            r["graph_zone_updates_per_s"] = V / (gms * 1e-3)
             r["graph_ms_per_step"] = gms
-        # per-box launches: one nyx_hydro_step per box (workspace of the largest box)
-        big = max(nyx.workspace_bytes(prm, b) for b in boxes)
-        wsb1 = aligned(torch, big)
-        dth = dts[0].cpu().tolist()
-        torch.cuda.synchronize()
-        e0.record()
-        for b, bx in enumerate(boxes):
-            nyx.hydro_step(prm, bx, bufs[0], grav, dth[b], 0.25, 0.25 + 5e-4, bufs[1],
-                           workspace=wsb1)
-        e1.record()
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1)
-        r["per_box_zone_updates_per_s"] = zones / (pms * 1e-3)
-        r["per_box_ms_per_step"] = pms
+            del g
+        if form == "fp64":
+            # per-box launches: one nyx_hydro_step per box (workspace of the largest box)
+            big = max(nyx.workspace_bytes(prm, b) for b in boxes)
+            wsb1 = aligned(torch, big)
+            dth = dt_seq[0].cpu().tolist()
+            torch.cuda.synchronize()
+            e0.record()
+            for b, bx in enumerate(boxes):
+                nyx.hydro_step(prm, bx, state, grav, dth[b], a_at(0), a_at(1), bufs[1],
+                               workspace=wsb1)
+            e1.record()
+            torch.cuda.synchronize()
+            pms = e0.elapsed_time(e1)
+            r["per_box_zone_updates_per_s"] = V / (pms * 1e-3)
+            r["per_box_ms_per_step"] = pms
+            del wsb1
         res[form] = r
-        log("level %s: %s" % (form, {k: (round(v, 3) if isinstance(v, float) else v)
-                                     for k, v in r.items()}))
+        log("level %s: %s" % (form, {k: (round(v, 4) if isinstance(v, float) else v)
+                                     for k, v in r.items() if k not in ("stage", "tuning")}))
         plan.close()
-        del ws, wsb1, state, grav, other, bufs
+        del plan, ws, state, grav, bufs, fin  # the plan object holds its workspace
         torch.cuda.empty_cache()
+    del rho64
+    torch.cuda.empty_cache()
     out["forms"] = res
     out["gain_batched_graph_vs_per_box_plain_fp64"] = (
         res["mixed"]["graph_zone_updates_per_s"] / res["fp64"]["per_box_zone_updates_per_s"])
     return out
-
-
-def stress_leg(nyx, torch, synth, learn, flux, steps, log, n=512, m=64):
-    """box512_stress: plain FP64 with the domain as one box, against FP32-mixed
-    (and mixed + learned flux) on an (n/m)^3 grid of m^3 patches with the
-    same-level ghost fill and one level dt (the FP64 run's dt sequence).
-    Reports rates, density relative L1 against FP64 and the fallback rate."""
-    t0 = time.perf_counter()
-    grid = (n // m,) * 3
-    nb = grid[0] * grid[1] * grid[2]
-    a0, a1 = 0.10, 0.11
-
-    def a_at(k):
-        return a0 + (a1 - a0) * k / steps
-
-    state, grav = synth.stress_fields_torch(n=n)
-    A0 = torch.cat([p.reshape(-1) for p in synth.split_patches(state, grid)])
-    G32 = torch.cat([p.reshape(-1).float() for p in synth.split_patches(grav, grid)])
-    log("stress fields ready in %.1f s" % (time.perf_counter() - t0))
-    zones = n ** 3
-    out = {"workload": "box512_stress: %d^3, density contrast <= 1e4, Mach <= 30, g ~ N(0, 0.2^2), "
-                       "a 0.10->0.11" % n, "steps": steps, "patches": "%d x %d^3" % (nb, m)}
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # plain FP64, one box
-    prm = nyx.default_params()
-    box = nyx.make_box((n, n, n), 4, 1.0 / n)
-    _, one = nyx.Batch.workspace_bytes(prm, [box])
-    ws = aligned(torch, one)
-    plan = nyx.Batch(prm, [box], ws)
-    bufs = [state, torch.empty_like(state)]
-    dts = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
-    st = torch.zeros(10, dtype=torch.int64, device="cuda")
-    plan.estimate_dt(state, a0, 0.5, dts[0:1])
-    torch.cuda.synchronize()
-    e0.record()
-    for k in range(steps):
-        plan.step(bufs[k % 2], grav, dts[k:k + 1], a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
-                  dt_next=dts[k + 1:k + 2], stats=st if k == 0 else None)
-        plan.fill_ghosts(bufs[(k + 1) % 2])
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    rho64 = bufs[steps % 2][0, 4:-4, 4:-4, 4:-4].contiguous()
-    s64 = nyx.stats_dict(st)
-    out["fp64_one_box"] = {"zone_updates_per_s": zones * steps / (ms * 1e-3),
-                           "ms_per_step": ms / steps, "stats_first_step": s64}
-    plan.close()
-    del plan, ws, bufs, state, grav
-    torch.cuda.empty_cache()
-    dtp = dts[:steps, None].expand(steps, nb).contiguous()
-    P = (m + 8) ** 3
-    boxes = [nyx.make_box((m, m, m), 4, 1.0 / n, state_off=6 * P * b, grav_off=3 * P * b)
-             for b in range(nb)]
-    runs = [("mixed_patches", nyx.default_params(precision=nyx.NYX_MIXED))]
-    if flux is not None:
-        # the network trained on smooth flows, and one trained on stress faces
-        runs.append(("learned_patches", learn.learned_params(flux, tol=1e-3, stages=7)))
-        sflux, out["stress_training"] = train_learned_stress(nyx, learn, synth, log)
-        runs.append(("learned_patches_stress_trained",
-                     learn.learned_params(sflux, tol=1e-3, stages=7)))
-    for name, prm in runs:
-        _, one = nyx.Batch.workspace_bytes(prm, boxes)
-        ws = aligned(torch, one)
-        plan = nyx.Batch(prm, boxes, ws)
-        bufs = [A0.clone(), torch.empty_like(A0)]
-        st.zero_()
-        torch.cuda.synchronize()
-        e0.record()
-        for k in range(steps):
-            plan.step(bufs[k % 2], G32, dtp[k], a_at(k), a_at(k + 1), bufs[(k + 1) % 2],
-                      stats=st if k == 0 else None)
-            plan.fill_ghosts(bufs[(k + 1) % 2], mode=1, grid=grid)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        rho = synth.join_valid(bufs[steps % 2], grid, (m, m, m))[0]
-        l1 = float((rho - rho64).abs().sum() / rho64.abs().sum())
-        s = nyx.stats_dict(st)
-        r = {"zone_updates_per_s": zones * steps / (ms * 1e-3), "ms_per_step": ms / steps,
-             "rho_l1_vs_fp64": l1, "finite": bool(torch.isfinite(bufs[steps % 2]).all().item()),
-             "stats_first_step": s}
-        if name.startswith("learned"):
-            r["fallback_rate"] = s["mlp_fallback"] / max(s["mlp_used"] + s["mlp_fallback"], 1)
-        out[name] = r
-        log("stress %s: %.3e zone-updates/s, rho L1 vs FP64 %.2e" % (name, r["zone_updates_per_s"], l1))
-        plan.close()
-        del plan, ws, bufs
-        torch.cuda.empty_cache()
-    log("stress fp64 one box: %.3e zone-updates/s" % out["fp64_one_box"]["zone_updates_per_s"])
-    return out
-
-
 def variants_leg(nyx, torch, w, steps, warmup, log):
     """The scheme variants of Sec. 3.2 on the benchmark box (FP32-mixed, each
     against its own plain FP64 run): PLM reconstruction, the linearised
@@ -425,8 +699,10 @@ def variants_leg(nyx, torch, w, steps, warmup, log):
                      ("linearized_riemann", dict(riemann=nyx.NYX_RIEMANN_LINEARIZED)),
                      ("gravity_energy_form2", dict(grav_energy_form=2)),
                      ("gamma14_expansion", dict(gamma=1.4))):
-        m = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_MIXED, **kw), steps, warmup)
-        f = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_FP64, **kw), steps, warmup)
+        m = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_MIXED, **kw), steps, warmup,
+                    flop_table("box256"))
+        f = run_box(nyx, torch, w, nyx.default_params(precision=nyx.NYX_FP64, **kw), steps, warmup,
+                    flop_table("box256"))
         l1 = float(np.abs(m["rho"] - f["rho"]).sum() / np.abs(f["rho"]).sum())
         out[name] = {"mixed_zone_updates_per_s": m["zone_updates_per_s"],
                      "fp64_zone_updates_per_s": f["zone_updates_per_s"],
@@ -718,22 +994,75 @@ def gravity_leg(nyx, torch, synth, w, log, reps=3):
     return out
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The FP64 oracle, single-threaded, on a 64^3 sample of the workload."""
+
+
+def launch_modes_leg(nyx, torch, synth, log):
+    """Staged against persistent launches of FP32-mixed batched plans on
+    small workloads, where launch overhead weighs most: the 32^3 box of the
+    smallest configuration, and a level of 512 boxes of 16^3 (smooth-flow
+    fields).  Both modes from nyx_batch_autotune_mode (best of 5 steps after
+    one untimed, launch orders autotuned first)."""
+    out = {}
+    cases = {"box32_plain (one 32^3 box)": [(32, 32, 32)], "level of 512 boxes of 16^3": [(16, 16, 16)] * 512}
+    for name, shapes in cases.items():
+        if len(shapes) == 1:
+            w = synth.config1()
+            state = torch.from_numpy(w.state).cuda()
+            grav = torch.from_numpy(w.grav).float().cuda()
+            boxes = [nyx.make_box(w.n, 4, w.dx)]
+            a0 = w.a0
+        else:
+            state, grav, offs = synth.level_fields_torch(shapes, grav_dtype=torch.float32)
+            boxes = [nyx.make_box(n, 4, 1.0 / 256, state_off=so, grav_off=go)
+                     for n, (so, go) in zip(shapes, offs)]
+            a0 = 0.25
+        prm = nyx.default_params(precision=nyx.NYX_MIXED)
+        _, one = nyx.Batch.workspace_bytes(prm, boxes)
+        ws = aligned(torch, one)
+        plan = nyx.Batch(prm, boxes, ws)
+        dt = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+        plan.estimate_dt(state, a0, 0.5, dt)
+        other = torch.empty_like(state)
+        plan.autotune(state, grav, dt, a0, a0 * 1.001, other, reps=2)
+        mode, ms = plan.autotune_mode(state, grav, dt, a0, a0 * 1.001, other, reps=5)
+        V = sum(a * b * c for a, b, c in shapes)
+        out[name] = {"staged_ms": ms[0], "persistent_ms": ms[1],
+                     "staged_zone_updates_per_s": V / (ms[0] * 1e-3),
+                     "persistent_zone_updates_per_s": V / (ms[1] * 1e-3) if ms[1] > 0 else None,
+                     "kept": "persistent" if mode == nyx.NYX_LAUNCH_PERSISTENT else "staged"}
+        log("launch modes, %s: staged %.4f ms, persistent %.4f ms" % (name, ms[0], ms[1]))
+        plan.close()
+        del plan, ws, state, grav, other
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(sample, a_pair, dx, dt, budget_s=12.0):
+    """The FP64 oracle on 64^3 patches (+4 ghosts, cut from the headline's
+    fields): one step per patch, on all usable host cores (one thread per
+    core, at most 16; the oracle's C step releases the GIL) for about
+    `budget_s` seconds, then one patch on one thread."""
     import oracle
-    import numpy as np
-    m = 64
-    U = np.ascontiguousarray(w.state[:, :m + 8, :m + 8, :m + 8])
-    g = np.ascontiguousarray(w.grav[:, :m + 8, :m + 8, :m + 8])
-    dt = oracle.estimate_dt(U, 4, w.a0, w.dx, 0.5)
+    from concurrent.futures import ThreadPoolExecutor
+    m = sample[0][0].shape[-1] - 8
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+
+    def one(i):
+        U, g = sample[i % len(sample)]
+        oracle.hydro_step(U, g, 4, dt, dx, a_pair[0], a_pair[1])
+        return 1
+
+    done = 0
     t0 = time.perf_counter()
-    nstep = 0
-    while True:
-        oracle.hydro_step(U, g, 4, dt, w.dx, w.a0, w.a_at(1))
-        nstep += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        i = 0
+        while time.perf_counter() - t0 < budget_s:
+            done += sum(ex.map(one, range(i, i + threads)))
+            i += threads
     el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    one(0)
+    el1 = time.perf_counter() - t1
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -741,9 +1070,11 @@ def cpu_baseline(w, budget_s=12.0):
                          "")
     except OSError:
         pass
-    return {"value": m ** 3 * nstep / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d step(s) of a 64^3 cut (+4 ghosts) of the same 256^3 fields, one thread"
-                      % nstep,
+    return {"value": m ** 3 * done / el, "unit": "zone-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d one-step runs of %d^3 patches (+4 ghosts) of the headline's stress "
+                      "fields (%d distinct patches), %d threads" % (done, m, len(sample), threads),
+            "single_thread": {"value": m ** 3 / el1, "unit": "zone-updates/s", "cores": 1},
             "host": {"cpu_model": model, "nproc": os.cpu_count(),
                      "usable_cpus": len(os.sched_getaffinity(0))}}
 
@@ -751,13 +1082,14 @@ def cpu_baseline(w, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10, help="steps of the headline (box512_stress)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--forms", default="fp64,mixed,learned,learned01")
+    ap.add_argument("--n", type=int, default=512, help="edge of the headline domain")
+    ap.add_argument("--steps256", type=int, default=20, help="steps of the 256^3 legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip every learned-flux form")
+    ap.add_argument("--no-box256", action="store_true", help="skip the 256^3 legs")
     ap.add_argument("--no-level", action="store_true", help="skip the 4096-box batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-stress", action="store_true", help="skip the 512^3 stress leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the PLM / linearised-solver / gravity-form-2 leg")
     ap.add_argument("--no-fill", action="store_true", help="skip the level ghost-fill leg")
@@ -765,6 +1097,7 @@ def main():
                     help="skip the two-level step (reflux, average-down) leg")
     ap.add_argument("--no-gravity", action="store_true",
                     help="skip the gravity input leg (deposit, Poisson solve, gradient)")
+    ap.add_argument("--only-headline", action="store_true", help="the headline leg alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (3 times), to scale HBM counters")
     args = ap.parse_args()
@@ -793,63 +1126,21 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
                           "ms_per_copy": ms, "gbs_read_plus_write": 2 * nbytes / ms / 1e6}))
         return
-    import numpy as np
+    if args.only_headline:
+        args.no_box256 = args.no_level = args.no_variants = args.no_fill = True
+        args.no_two_level = args.no_gravity = True
     import paper_1301_4498_amd as nyx
     from paper_1301_4498_amd import learn, synth
     nyx.lib()
-    t0 = time.perf_counter()
-    w = synth.config2(n=args.n)
-    log("inputs ready in %.1f s" % (time.perf_counter() - t0))
-    forms, extra = {}, {}
-    flux = None
-    for f in args.forms.split(","):
-        if f == "fp64":
-            prm = nyx.default_params(precision=nyx.NYX_FP64)
-        elif f == "mixed":
-            prm = nyx.default_params(precision=nyx.NYX_MIXED)
-        elif f in ("learned", "learned01"):
-            if flux is None:
-                flux, extra["learned_training"] = train_learned(nyx, learn, synth, log)
-            # all twelve solves per zone, or stages 0 and 1 only (the final
-            # stage keeps the two-shock solver)
-            prm = learn.learned_params(flux, tol=1e-3, stages=7 if f == "learned" else 3)
-        else:
-            raise SystemExit("unknown form " + f)
-        forms[f] = run_box(nyx, torch, w, prm, args.steps, args.warmup)
-        log("%s: %.3e zone-updates/s" % (f, forms[f]["zone_updates_per_s"]))
-    ref = forms.get("fp64")
-    for f, v in forms.items():
-        v["rho_l1_vs_fp64"] = (float(np.abs(v["rho"] - ref["rho"]).sum() / np.abs(ref["rho"]).sum())
-                               if ref is not None else None)
-    for lf in ("learned", "learned01"):
-        if lf in forms and "mixed" in forms:
-            v = forms[lf]
-            v["rho_l1_vs_mixed"] = float(np.abs(v["rho"] - forms["mixed"]["rho"]).sum() /
-                                         np.abs(forms["mixed"]["rho"]).sum())
-            st = v["stats_first_step"]
-            v["fallback_rate"] = st["mlp_fallback"] / max(st["mlp_used"] + st["mlp_fallback"], 1)
-    ok = [f for f, v in forms.items() if v["finite"] and
-          (v["rho_l1_vs_fp64"] is None or v["rho_l1_vs_fp64"] <= 1e-3)]
-    chosen = max(ok, key=lambda f: forms[f]["zone_updates_per_s"])
-    R = forms[chosen]
-    dom = max(R["stage"], key=lambda s: R["stage"][s]["ms"])
-    ds = R["stage"][dom]
-    alu = {"bound": "alu", "achieved": ds["tflops"], "peak": FP64_PEAK_TFLOPS,
-           "unit": "TFLOP/s", "frac": round(ds["tflops"] / FP64_PEAK_TFLOPS, 4),
-           "traffic": None, "kernel": dom}
-    hbm = {"bound": "hbm", "achieved": ds["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(ds["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom}
-    # The Riemann and tracing stages issue VALU instructions near the chip's
-    # rate (rocprofv3 SQ counters in profiles/), so they are ALU-bound even
-    # when their algorithmic byte rate is the larger fraction; the other
-    # stages are bound by HBM.
-    if dom in ("trace", "riem0", "riem1", "riem2"):
-        roof, other = alu, hbm
-    else:
-        roof, other = hbm, alu
-    t = measured_traffic(dom, chosen, R["tuning"][STAGES.index(dom)])
-    roof["traffic"] = t
-    other["traffic"] = t
+    H, sample, a_pair, dxh = headline_leg(nyx, torch, synth, learn, args.steps, args.warmup, log,
+                                          n=args.n, learned=not args.no_learned)
+    F = H["forms"]
+    base = F["fp64_one_box"]
+    ok = [f for f in F if f not in ("fp64_one_box", "mixed_patches_fp64_stop") and F[f]["finite"]
+          and F[f]["rho_l1_vs_fp64"] <= 1e-3]
+    chosen = max(ok, key=lambda f: F[f]["zone_updates_per_s"]) if ok else "fp64_one_box"
+    R = F[chosen]
+    learned_used = chosen.startswith("learned")
     out = {
         "metric": METRIC,
         "value": R["zone_updates_per_s"],
@@ -861,39 +1152,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if chosen == "fp64" else ("f32+f64+bf16" if chosen.startswith("learned")
-                                                 else "f32+f64"),
+        "dtype": "f32+f64+bf16" if learned_used else ("f64" if chosen == "fp64_one_box" else "f32+f64"),
         "data": "synthetic",
-        "config": {"workload": "box256_smooth: one periodic %d^3 box + 4 ghosts, smooth-flow "
-                               "fields, a 0.25->0.26, CFL 0.5" % args.n,
+        "config": {"workload": "box512_stress: one %d^3 periodic domain (density contrast <= 1e4, "
+                               "Mach <= 30, strong gravity, a 0.10->0.11, one level dt); chosen "
+                               "form %s on %s patches; plain FP64 as one box alongside"
+                               % (args.n, chosen, H["patches"]),
                    "form": chosen, "parallelism": "none"},
-        "forms": {f: {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage",
-                                         "mean_riemann_iters", "finite", "rho_l1_vs_fp64",
-                                         "tuning", "tuning_ms")
-                      if k in v} for f, v in forms.items()},
-        "roofline": roof,
-        "roofline_other": other,
+        "plain_fp64_zone_updates_per_s": base["zone_updates_per_s"],
+        "gain_vs_plain_fp64": R["zone_updates_per_s"] / base["zone_updates_per_s"],
+        "rho_l1_vs_fp64": R.get("rho_l1_vs_fp64"),
+        "roofline": R["roofline"],
+        "hbm_step": R["hbm_step"],
+        "box512_stress": H,
     }
-    for lf in ("learned", "learned01"):
-        if lf in forms:
-            out["forms"][lf]["rho_l1_vs_mixed"] = forms[lf].get("rho_l1_vs_mixed")
-            out["forms"][lf]["fallback_rate"] = forms[lf].get("fallback_rate")
-            out["learned_training"] = extra["learned_training"]
+    log("headline: %s %.3e zone-updates/s (plain FP64 one box %.3e, x%.2f); roofline %s %s %.3f"
+        % (chosen, R["zone_updates_per_s"], base["zone_updates_per_s"],
+           out["gain_vs_plain_fp64"], R["roofline"]["kernel"], R["roofline"]["bound"],
+           R["roofline"]["frac"]))
+    flux = None
+    w = None
+    if not args.no_box256:
+        out["box256"], w = box256_leg(nyx, torch, synth, args.steps256, args.warmup, log)
+        if not args.no_learned:
+            flux, out["learned_training"] = train_learned(nyx, learn, synth, log)
+            out["learned256"] = learned256_leg(nyx, torch, synth, learn, flux, args.steps256,
+                                               args.warmup, log)
     if not args.no_level:
-        out["level4096"] = level_leg(nyx, torch, synth, max(args.steps // 2 * 2, 2), log)
+        out["level4096"] = level_leg(nyx, torch, synth, learn, flux, 10, args.warmup, log)
+        out["launch_modes"] = launch_modes_leg(nyx, torch, synth, log)
+    if w is None and not (args.no_variants and args.no_two_level and args.no_gravity):
+        w = synth.config2(n=256)
     if not args.no_variants:
-        out["variants"] = variants_leg(nyx, torch, w, args.steps, args.warmup, log)
+        out["variants"] = variants_leg(nyx, torch, w, 10, args.warmup, log)
     if not args.no_fill:
         out["level_fill"] = level_fill_leg(nyx, torch, log)
     if not args.no_two_level:
         out["two_level"] = two_level_leg(nyx, torch, synth, w, log)
     if not args.no_gravity:
         out["gravity"] = gravity_leg(nyx, torch, synth, w, log)
-    if not args.no_stress:
-        out["box512_stress"] = stress_leg(nyx, torch, synth, learn,
-                                          flux, 10, log)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(sample, a_pair, dxh, H["dt_first"])
+        log("cpu baseline: %.3e zone-updates/s on %d threads (one thread %.3e)"
+            % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"],
+               out["cpu_baseline"]["single_thread"]["value"]))
     print(json.dumps(out))
 
 

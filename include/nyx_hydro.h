@@ -108,6 +108,11 @@ typedef struct {
                                 * the update of the kinetic energy the gravity
                                 * momentum terms cause */
   const void* mlp_weights;     /* (device) packed learned-flux weights, or NULL */
+  double mixed_riemann_stop;   /* FP32-mixed: relative Newton step below which the
+                                * two-shock iteration stops; 0 selects the default
+                                * max(sqrt(riemann_tol), 2^-12) (the star state is
+                                * stored in FP32); riemann_tol gives the FP64 form's
+                                * own rule */
 } nyx_params;
 
 typedef struct {
@@ -222,6 +227,37 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
                            const double* dt, double a_old, double a_new,
                            double* state_out, double* dt_next, nyx_stats* stats,
                            void* stream);
+
+/* ---------------- launch mode of a plan ----------------
+ * NYX_LAUNCH_STAGED (the default): every stage of a group is its own launch
+ * over all boxes of the group.  NYX_LAUNCH_PERSISTENT: the seven stages of a
+ * group run as one launch of as many workgroups as the device keeps
+ * resident at once; per stage, the work items (the blocks of the staged
+ * launch) are taken from atomic queues, one per eighth of the stage's walk,
+ * which the workgroups of one XCD drain first, and a grid barrier separates
+ * the stages.  Each item runs the staged kernel's code, so every box's result
+ * is bit for bit that of the staged launches.  The barrier gives up after 5 s
+ * of wall clock if some workgroup never became resident (another kernel
+ * holding the device); the launch then ends early, and
+ * nyx_batch_persistent_aborted reports it.  Available for plain steps in
+ * both precisions and for the learned flux on all three stages; a plan that
+ * harvests training records runs staged.  Stage timing (nyx_profile_*) sees
+ * only staged launches. */
+enum { NYX_LAUNCH_STAGED = 0, NYX_LAUNCH_PERSISTENT = 1 };
+/* NYX_E_UNSUPPORTED when the persistent mode is not available for the
+ * plan's parameters. */
+int nyx_batch_set_launch_mode(nyx_batch* plan, int mode);
+int nyx_batch_get_launch_mode(const nyx_batch* plan, int* mode);
+/* *aborted = 1 if the last persistent launch of the plan gave up at a grid
+ * barrier (synchronises `stream`). */
+int nyx_batch_persistent_aborted(nyx_batch* plan, int* aborted, void* stream);
+/* Times `reps` whole steps (after one untimed) in each available mode with
+ * the plan's current launch orders and keeps the faster; ms_out[2] (host,
+ * or NULL) receives the best step time of each mode (-1: not available);
+ * *mode_out (or NULL) the mode kept.  Synchronises `stream`. */
+int nyx_batch_autotune_mode(nyx_batch* plan, const double* state_in, const void* grav,
+                            const double* dt, double a_old, double a_new, double* state_out,
+                            int reps, float* ms_out, int* mode_out, void* stream);
 
 /* ---------------- launch-order autotuning of a plan ----------------
  * Each of the NYX_NSTAGES stage kernels of a plan's step walks its cells in

@@ -10,11 +10,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (NYX_FP64, NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMANN_LEARNED,
+from ._lib import (NYX_FP64, NYX_LAUNCH_PERSISTENT, NYX_LAUNCH_STAGED, NYX_MIXED,
+                   NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMANN_LEARNED,
                    NYX_RIEMANN_LINEARIZED, NYX_RIEMANN_TWOSHOCK, STATS_FIELDS, Box, NyxError,
                    Params, Stats, check, lib)
 
-__all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_RIEMANN_TWOSHOCK",
+__all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_LAUNCH_STAGED",
+           "NYX_LAUNCH_PERSISTENT", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
            "hydro_step", "hydro_step_noalloc", "noalloc_max_bytes", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "cic_deposit", "PoissonSolver",
@@ -110,6 +112,19 @@ def stats_dict(t) -> dict:
     return dict(zip(STATS_FIELDS, vals))
 
 
+def tie_break_by_traffic(table, tune, traffic, tie=0.03):
+    """Launch orders of a plan re-picked where counters are known: for each
+    stage i in `traffic` ({i: HBM bytes per launch of each candidate}), the
+    candidate with the least traffic among those whose time table[i][c] is
+    within `tie` of the stage's fastest; other stages keep `tune`."""
+    out = list(tune)
+    for i, per_cand in traffic.items():
+        fastest = min(table[i])
+        near = [c for c in range(len(table[i])) if table[i][c] <= fastest * (1.0 + tie)]
+        out[i] = min(near, key=lambda c: (per_cand[c], table[i][c]))
+    return out
+
+
 class Batch:
     """A batched plan (nyx_batch_*) over boxes in shared state/gravity buffers."""
 
@@ -173,10 +188,13 @@ class Batch:
             self.num_groups, h)
 
     def autotune(self, state_in, grav, dt, a_old, a_new, state_out, dt_next=None, reps=3,
-                 cache=None, stream=None):
+                 cache=None, stream=None, traffic=None, tie=0.03):
         """Pick each stage's launch order (nyx_batch_autotune).  With a cache
         file (JSON), a stored choice for the same key is applied without
-        timing, and a new one is stored.  Returns (tune, ms or None)."""
+        timing, and a new one is stored.  traffic: optional {stage index:
+        [HBM bytes per launch of each candidate]} (measured counters); among
+        the candidates whose time is within `tie` of a stage's fastest, the
+        one with the least traffic is kept.  Returns (tune, ms or None)."""
         import json
         import os
         key = None
@@ -197,6 +215,9 @@ class Batch:
             _ptr(state_out), _ptr(dt_next), int(reps), ms, t, _stream(stream)))
         tune = list(t)
         table = [[round(float(ms[i * nc + c]), 4) for c in range(nc)] for i in range(nst)]
+        if traffic:
+            tune = tie_break_by_traffic(table, tune, traffic, tie)
+            self.set_tuning(tune)
         if cache is not None:
             db = {}
             if os.path.exists(cache):
@@ -208,6 +229,32 @@ class Batch:
                 json.dump(db, fh, indent=1)
             os.replace(tmp, cache)
         return tune, table
+
+    @property
+    def launch_mode(self) -> int:
+        m = ctypes.c_int(0)
+        check("nyx_batch_get_launch_mode", lib().nyx_batch_get_launch_mode(self.handle,
+                                                                           ctypes.byref(m)))
+        return m.value
+
+    def set_launch_mode(self, mode: int):
+        check("nyx_batch_set_launch_mode", lib().nyx_batch_set_launch_mode(self.handle, int(mode)))
+
+    def persistent_aborted(self, stream=None) -> bool:
+        a = ctypes.c_int(0)
+        check("nyx_batch_persistent_aborted", lib().nyx_batch_persistent_aborted(
+            self.handle, ctypes.byref(a), _stream(stream)))
+        return bool(a.value)
+
+    def autotune_mode(self, state_in, grav, dt, a_old, a_new, state_out, reps=3, stream=None):
+        """Keep the faster launch mode (nyx_batch_autotune_mode); returns
+        (mode, [staged ms, persistent ms or -1])."""
+        ms = (ctypes.c_float * 2)()
+        m = ctypes.c_int(0)
+        check("nyx_batch_autotune_mode", lib().nyx_batch_autotune_mode(
+            self.handle, _ptr(state_in), _ptr(grav), _ptr(dt), float(a_old), float(a_new),
+            _ptr(state_out), int(reps), ms, ctypes.byref(m), _stream(stream)))
+        return m.value, [round(float(ms[0]), 4), round(float(ms[1]), 4)]
 
     def set_flux_register(self, sync, level, reg):
         """Feed a two-level sync plan's register (device FP64, 6 x faces) from

@@ -17,6 +17,8 @@ NYX_RIEMANN_LEARNED = 1
 NYX_RIEMANN_LINEARIZED = 2
 NYX_RECON_PPM = 0
 NYX_RECON_PLM = 1
+NYX_LAUNCH_STAGED = 0
+NYX_LAUNCH_PERSISTENT = 1
 
 STATUS = {0: "NYX_OK", -1: "NYX_E_NULL", -2: "NYX_E_SHAPE", -3: "NYX_E_PARAM",
           -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE",
@@ -39,6 +41,7 @@ class Params(ctypes.Structure):
         ("recon", ctypes.c_int32),
         ("grav_energy_form", ctypes.c_int32),
         ("mlp_weights", ctypes.c_void_p),
+        ("mixed_riemann_stop", ctypes.c_double),
     ]
 
 
@@ -109,6 +112,11 @@ def lib():
             "nyx_batch_autotune": (i, [vp, vp, vp, vp, d, d, vp, vp, i, ctypes.POINTER(ctypes.c_float),
                                        ctypes.POINTER(i), vp]),
             "nyx_batch_set_tuning": (i, [vp, ctypes.POINTER(i)]),
+            "nyx_batch_set_launch_mode": (i, [vp, i]),
+            "nyx_batch_get_launch_mode": (i, [vp, ctypes.POINTER(i)]),
+            "nyx_batch_persistent_aborted": (i, [vp, ctypes.POINTER(i), vp]),
+            "nyx_batch_autotune_mode": (i, [vp, vp, vp, vp, d, d, vp, i, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(i), vp]),
             "nyx_fill_plan_bytes": (i, [i, B, ctypes.POINTER(i), ctypes.POINTER(i), i, B,
                                         ctypes.POINTER(i), ctypes.POINTER(sz)]),
             "nyx_fill_plan_create": (i, [i, B, ctypes.POINTER(i), ctypes.POINTER(i), i, B,
@@ -165,7 +173,8 @@ def exported_symbols():
             "nyx_sync_plan_destroy", "nyx_batch_set_flux_register", "nyx_reflux",
             "nyx_average_down", "nyx_cic_deposit", "nyx_poisson_workspace_bytes",
             "nyx_poisson_solve", "nyx_gravity_from_phi", "nyx_hydro_step_noalloc",
-            "nyx_noalloc_max_bytes"]
+            "nyx_noalloc_max_bytes", "nyx_batch_set_launch_mode", "nyx_batch_get_launch_mode",
+            "nyx_batch_persistent_aborted", "nyx_batch_autotune_mode"]
 
 TUNE_CANDIDATES = 16
 MLP_NPARAM = 9349

@@ -44,6 +44,7 @@ int check_params(const nyx_params* p) {
   if (!finite_pos(p->small_dens) || !finite_pos(p->small_pres)) return NYX_E_PARAM;
   if (!finite_pos(p->riemann_tol)) return NYX_E_PARAM;
   if (!finite_pos(p->cfl)) return NYX_E_PARAM;
+  if (!(std::isfinite(p->mixed_riemann_stop) && p->mixed_riemann_stop >= 0.0)) return NYX_E_PARAM;
   if (p->riemann_maxiter < 1 || p->riemann_maxiter > 64) return NYX_E_PARAM;
   if (p->precision != NYX_FP64 && p->precision != NYX_MIXED) return NYX_E_PARAM;
   if (p->riemann != NYX_RIEMANN_TWOSHOCK && p->riemann != NYX_RIEMANN_LEARNED &&
@@ -107,7 +108,8 @@ void fill_physics(StepArgs& a, const nyx_params* p) {
   // FP32-mixed stopping step: the star state is stored in FP32, so the
   // iteration stops once the next Newton correction would be far below FP32
   // resolution (see two_shock in the mixed build).
-  a.mixed_stop = std::max(std::sqrt(p->riemann_tol), 0x1p-12);
+  a.mixed_stop = p->mixed_riemann_stop > 0.0 ? p->mixed_riemann_stop
+                                               : std::max(std::sqrt(p->riemann_tol), 0x1p-12);
   a.cfl = p->cfl;
   a.maxiter = p->riemann_maxiter;
   const bool learned = p->riemann == NYX_RIEMANN_LEARNED;
@@ -239,6 +241,7 @@ void nyx_default_params(nyx_params* p) {
   p->recon = NYX_RECON_PPM;
   p->grav_energy_form = 1;
   p->mlp_weights = nullptr;
+  p->mixed_riemann_stop = 0.0;
 }
 
 const char* nyx_status_string(int s) {
@@ -365,6 +368,10 @@ struct nyx_batch {
   std::vector<long long> reg_prefix;  // per box, host
   double* reg = nullptr;
   long long reg_slots = 0;
+  // persistent launch mode: control block (device) and barrier time limit
+  unsigned long long* ctl = nullptr;
+  unsigned long long barrier_ticks = 0;
+  int mode = NYX_LAUNCH_STAGED;
 };
 
 namespace {
@@ -375,7 +382,7 @@ size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 size_t table_bytes(int nbox, int ngroups) {
   return round256(sizeof(BoxDev) * (size_t)nbox) + round256(sizeof(int) * 3 * (size_t)(nbox + ngroups)) +
          round256(sizeof(unsigned long long) * (size_t)nbox) + round256(kSlotBytes) +
-         round256(sizeof(StepC) * (size_t)nbox);
+         round256(sizeof(StepC) * (size_t)nbox) + round256(sizeof(unsigned long long) * kCtlWords);
 }
 
 int check_boxes(const nyx_params* p, int nbox, const nyx_box* boxes) {
@@ -468,7 +475,17 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
   plan->smax = (unsigned long long*)((char*)pre_dev + round256(sizeof(int) * 3 * (size_t)(nbox + nbox)));
   plan->slots = (unsigned long long*)((char*)plan->smax + round256(sizeof(unsigned long long) * (size_t)nbox));
   plan->consts = (StepC*)((char*)plan->slots + round256(kSlotBytes));
+  plan->ctl = (unsigned long long*)((char*)plan->consts + round256(sizeof(StepC) * (size_t)nbox));
   plan->stage = w + tbytes;
+  {
+    // the persistent step's grid barrier gives up after 5 s of wall clock
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      plan->barrier_ticks = (unsigned long long)khz * 5000ull;
+    else
+      plan->barrier_ticks = 500000000ull;  // 5 s at 100 MHz
+  }
   plan->state_span = span;
   for (auto& g : plan->groups)
     for (int s = 0; s < 3; ++s) g.prefix[s] = pre_dev + (size_t)g.prefix[s];
@@ -477,6 +494,7 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
                      st) != hipSuccess ||
       hipMemcpyAsync(pre_dev, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice,
                      st) != hipSuccess ||
+      launch_zero_u64(plan->ctl, kCtlWords, st) != hipSuccess ||  // no abort before any launch
       hipStreamSynchronize(st) != hipSuccess) {
     delete plan;
     return NYX_E_HIP;
@@ -515,6 +533,8 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   A.harvest_keep = plan->harvest_keep;
   A.harvest_seed = plan->harvest_seed;
   for (int i = 0; i < kStages; ++i) A.tune[i] = plan->tune[i];
+  A.ctl = plan->ctl;
+  A.barrier_ticks = plan->barrier_ticks;
   return A;
 }
 
@@ -586,6 +606,9 @@ int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, c
     if (group_ev) {
       A.ev = group_ev[&g - plan->groups.data()];
       e = plan->prm.precision == NYX_MIXED ? mixed::launch_step(A, s) : fp64::launch_step(A, s);
+    } else if (plan->mode == NYX_LAUNCH_PERSISTENT && !plan->harvest) {
+      e = plan->prm.precision == NYX_MIXED ? mixed::launch_step_persistent(A, s)
+                                           : fp64::launch_step_persistent(A, s);
     } else {
       e = run_stages(&plan->prm, A, s);
     }
@@ -641,6 +664,37 @@ int nyx_batch_set_tuning(nyx_batch* plan, const int* tune) {
 int nyx_batch_get_tuning(const nyx_batch* plan, int* tune) {
   if (!plan || !tune) return NYX_E_NULL;
   for (int i = 0; i < kStages; ++i) tune[i] = plan->tune[i];
+  return NYX_OK;
+}
+
+int nyx_batch_set_launch_mode(nyx_batch* plan, int mode) {
+  if (!plan) return NYX_E_NULL;
+  if (mode != NYX_LAUNCH_STAGED && mode != NYX_LAUNCH_PERSISTENT) return NYX_E_PARAM;
+  if (mode == NYX_LAUNCH_PERSISTENT) {
+    if (plan->groups.empty()) return NYX_E_UNSUPPORTED;
+    StepArgs A = group_args(plan, plan->groups[0]);
+    const int grid = plan->prm.precision == NYX_MIXED ? mixed::persistent_grid(A)
+                                                      : fp64::persistent_grid(A);
+    if (grid <= 0) return NYX_E_UNSUPPORTED;
+  }
+  plan->mode = mode;
+  return NYX_OK;
+}
+
+int nyx_batch_get_launch_mode(const nyx_batch* plan, int* mode) {
+  if (!plan || !mode) return NYX_E_NULL;
+  *mode = plan->mode;
+  return NYX_OK;
+}
+
+int nyx_batch_persistent_aborted(nyx_batch* plan, int* aborted, void* stream) {
+  if (!plan || !aborted) return NYX_E_NULL;
+  unsigned long long v = 0;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(&v, plan->ctl + kCtlAbort, sizeof v, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return NYX_E_HIP;
+  *aborted = v ? 1 : 0;
   return NYX_OK;
 }
 
@@ -704,6 +758,51 @@ int nyx_batch_autotune(nyx_batch* plan, const double* state_in, const void* grav
     if (ms_out)
       for (int c = 0; c < kTuneCandidates; ++c) ms_out[i * kTuneCandidates + c] = (float)best_ms[c][i];
   }
+  return NYX_OK;
+}
+
+int nyx_batch_autotune_mode(nyx_batch* plan, const double* state_in, const void* grav,
+                            const double* dt, double a_old, double a_new, double* state_out,
+                            int reps, float* ms_out, int* mode_out, void* stream) {
+  int rc = check_step_args(plan, state_in, grav, dt, a_old, a_new, state_out);
+  if (rc) return rc;
+  if (reps < 1 || reps > 1000) return NYX_E_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return NYX_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return NYX_E_HIP;
+  }
+  const int saved = plan->mode;
+  float best[2] = {-1.f, -1.f};
+  for (int mode = NYX_LAUNCH_STAGED; mode <= NYX_LAUNCH_PERSISTENT && rc == NYX_OK; ++mode) {
+    if (nyx_batch_set_launch_mode(plan, mode) != NYX_OK) continue;  // not available
+    for (int r = 0; r <= reps && rc == NYX_OK; ++r) {  // r = 0 warms up
+      if (hipEventRecord(e0, s) != hipSuccess) rc = NYX_E_HIP;
+      if (rc == NYX_OK)
+        rc = enqueue_batched(plan, state_in, grav, dt, a_old, a_new, state_out, nullptr, nullptr,
+                             s, nullptr, false);
+      float t = 0.f;
+      if (rc == NYX_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        rc = NYX_E_HIP;
+      if (rc == NYX_OK && r > 0 && (best[mode] < 0.f || t < best[mode])) best[mode] = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NYX_OK) {
+    plan->mode = saved;
+    return rc;
+  }
+  plan->mode = (best[1] >= 0.f && best[1] < best[0]) ? NYX_LAUNCH_PERSISTENT : NYX_LAUNCH_STAGED;
+  if (ms_out) {
+    ms_out[0] = best[0];
+    ms_out[1] = best[1];
+  }
+  if (mode_out) *mode_out = plan->mode;
   return NYX_OK;
 }
 

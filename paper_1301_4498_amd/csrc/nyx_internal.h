@@ -215,6 +215,14 @@ constexpr int kTuneHwOrder = 2;
 constexpr int kTuneSlabShift = 2;
 constexpr int kTuneCandidates = 16;
 
+// Control block of the persistent step (device, zeroed before each launch):
+// per stage the heads of 8 work queues (one per eighth of the stage's walk,
+// drained first by the workgroups of one XCD), then the grid barrier's
+// arrival count and the abort flag a barrier that timed out raises.
+constexpr int kCtlBarrier = kStages * 8;
+constexpr int kCtlAbort = kCtlBarrier + 1;
+constexpr int kCtlWords = kCtlAbort + 1;
+
 // Launch-wide arguments of a step.
 struct StepArgs {
   // box selection: a device table + block prefix per Space (the single-box
@@ -259,6 +267,10 @@ struct StepArgs {
   int grav_form;           // energy gravity term, 1 or 2
   int linear_riemann;      // 1: linearised solver instead of the two-shock one
   int expansion;           // 1: gamma != 5/3, apply the a adot (2 - 3(gamma-1)) rho e term
+  // persistent step: control block (kCtlWords, zeroed before the launch)
+  // and the grid barrier's time limit in wall-clock ticks
+  unsigned long long* ctl;
+  unsigned long long barrier_ticks;
 };
 
 
@@ -289,13 +301,21 @@ struct SyncLevelView {
 };
 
 // The two precision builds of the stage kernels.
+// launch_step_persistent: the seven stages of a group as one launch of
+// co-resident workgroups (NYX_E_UNSUPPORTED-worthy cases return
+// hipErrorNotSupported: harvesting, or a learned-stage mask other than 0 or
+// 7); persistent_grid: the workgroups it launches on the current device.
 namespace fp64 {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_step_persistent(const StepArgs& a, hipStream_t s);
+int persistent_grid(const StepArgs& a);
 hipError_t launch_flux_record(const StepArgs& a, const BoxDev* table, const FluxRec* recs,
                               long long nrec, double* reg, long long nslots, hipStream_t s);
 }
 namespace mixed {
 hipError_t launch_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_step_persistent(const StepArgs& a, hipStream_t s);
+int persistent_grid(const StepArgs& a);
 hipError_t launch_flux_record(const StepArgs& a, const BoxDev* table, const FluxRec* recs,
                               long long nrec, double* reg, long long nslots, hipStream_t s);
 }

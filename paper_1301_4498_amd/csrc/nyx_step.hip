@@ -1378,6 +1378,7 @@ __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* d
     for (int i = 1; i < kBlock / 64; ++i) m = vmax(m, red[i]);
     if (m > 0.0) max_bits(dst, m);
   }
+  __syncthreads();  // red is free again when the block's next item reduces
 }
 
 // ---------------------------------------------------------------------------
@@ -1576,6 +1577,191 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   mark(6);
   hipLaunchKernelGGL(k_update, dim3(a.nblocks[kSpaceV]), blk, 0, s, a);
   mark(7);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// persistent step: the seven stages of a group in one launch.  The grid holds
+// as many workgroups as the device keeps resident at once; each stage's
+// work items (the blocks of its own launch) are handed out by atomic queues,
+// and a grid barrier separates the stages (a stage reads its neighbours'
+// results of the previous one).  Every item runs the same stage body as the
+// stage's own kernel, so the results are those of the staged launches, bit
+// for bit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int stage_space(int s) {
+  return s == kStPrim ? kSpaceP : (s == kStUpdate ? kSpaceV : kSpaceE);
+}
+__device__ __forceinline__ unsigned stage_rows(int s, bool learned1) {
+  if (s == kStPrim || s == kStFlat || s == kStUpdate) return 1u;
+  return (s == kStRiem1 && learned1) ? 6u : 3u;
+}
+
+template <int LMASK>
+__device__ __forceinline__ void run_item(const StepArgs& A, int s, const Item& it, __bf16* mlp,
+                                         double* park) {
+  switch (s) {
+    case kStPrim: prim_body(A, it); break;
+    case kStFlat: flat_body(A, it); break;
+    case kStTrace: trace_body(A, it); break;
+    case kStRiem0: riem0_body<(LMASK & 1) != 0>(A, it, mlp); break;
+    case kStRiem1: riem1_body<(LMASK & 2) != 0>(A, it, mlp, park); break;
+    case kStRiem2: riem2_body<(LMASK & 4) ? 1 : 0>(A, it, mlp); break;
+    default: update_body(A, it); break;
+  }
+}
+
+// Next chunk [b0, b1) of a stage's n work items, taken by one thread.  The
+// walk is cut into 8 contiguous ranges (1 with the hardware-order tuning
+// bit), each with its own queue head; a workgroup drains the range of its
+// XCD first (workgroups are dispatched to the XCDs round-robin), so that
+// neighbouring items are read through one L2, then takes from the others.
+// *done marks ranges found empty.
+__device__ __forceinline__ bool grab(unsigned long long* head, unsigned n, unsigned nr,
+                                     unsigned home, unsigned chunk, unsigned* done,
+                                     unsigned* b0, unsigned* b1) {
+  for (unsigned k = 0; k < nr; ++k) {
+    const unsigned r = (home + k) % nr;
+    if (*done >> r & 1u) continue;
+    const unsigned lo = (unsigned)((unsigned long long)n * r / nr);
+    const unsigned hi = (unsigned)((unsigned long long)n * (r + 1) / nr);
+    const unsigned long long v = lo < hi ? atomicAdd(head + r, (unsigned long long)chunk) : 0ull;
+    if (lo < hi && (unsigned long long)lo + v < hi) {
+      *b0 = lo + (unsigned)v;
+      *b1 = hi - *b0 < chunk ? hi : *b0 + chunk;
+      return true;
+    }
+    *done |= 1u << r;
+  }
+  return false;
+}
+
+// Grid barrier for the stage boundary `target` (arrivals so far, all
+// workgroups).  The fences make every workgroup's stage results visible to
+// every XCD before any workgroup goes on.  A barrier that has not filled
+// after `ticks` of the wall clock (a workgroup that never became resident)
+// raises the abort flag; every workgroup that sees it leaves, so each wait
+// ends.  Returns false on abort.
+__device__ __forceinline__ bool grid_barrier(unsigned long long* ctl, unsigned long long target,
+                                             unsigned long long ticks) {
+  __shared__ int ok_sh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(ctl + kCtlBarrier, 1ull);
+    const unsigned long long t0 = (unsigned long long)wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(ctl + kCtlBarrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           target) {
+      if (__hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if ((unsigned long long)wall_clock64() - t0 > ticks) {
+        atomicExch(ctl + kCtlAbort, 1ull);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    ok_sh = ok;
+  }
+  __syncthreads();
+  return ok_sh != 0;
+}
+
+// Waves per SIMD the persistent kernel is compiled for: with all seven stage
+// bodies inlined it needs 132 VGPRs in the FP32-mixed build (3 waves); asking
+// for 4 fits it in 128 with a 12-byte spill.  The FP64 build keeps the
+// compiler's choice (186 VGPRs, 2 waves; 4 waves would spill 148 bytes).
+#if defined(NYX_PREC_MIXED)
+constexpr int kPersistWaves = 4;
+#else
+constexpr int kPersistWaves = 2;
+#endif
+template <int LMASK>
+__global__ __launch_bounds__(kBlock, kPersistWaves) void k_step_persistent(StepArgs A) {
+  __shared__ __bf16 mlp_lds[LMASK ? (kBlock / 64) * kMlpWaveLds : 1];
+  __shared__ double park[(LMASK & 2) ? 1 : kPark * kBlock];
+  __shared__ unsigned q_sh[3];
+  unsigned long long* ctl = A.ctl;
+  const unsigned home = blockIdx.x & 7u;
+  for (int s = 0; s < kStages; ++s) {
+    const unsigned gx = (unsigned)A.nblocks[stage_space(s)];
+    const unsigned gy = stage_rows(s, (LMASK & 2) != 0);
+    const unsigned n = gx * gy;
+    const unsigned nr = (A.tune[s] & kTuneHwOrder) ? 1u : 8u;
+    // about 16 takes per workgroup and stage, at most 64 items each
+    unsigned chunk = n / (16u * gridDim.x);
+    chunk = chunk < 1u ? 1u : (chunk > 64u ? 64u : chunk);
+    unsigned done = 0;
+    for (;;) {
+      if (threadIdx.x == 0) {
+        unsigned b0 = 0, b1 = 0;
+        const bool got = grab(ctl + 8 * s, n, nr, home, chunk, &done, &b0, &b1);
+        q_sh[0] = b0;
+        q_sh[1] = b1;
+        q_sh[2] = got ? 1u : 0u;
+      }
+      __syncthreads();
+      const unsigned b0 = q_sh[0], b1 = q_sh[1];
+      const bool got = q_sh[2] != 0;
+      __syncthreads();  // every thread has read q_sh before the next take
+      if (!got) break;
+      // items need no barrier between them: a body's block-wide scratch
+      // (counter and maximum reductions) synchronises itself, the parked
+      // states are per thread and the network's tiles per wave
+      for (unsigned lin = b0; lin < b1; ++lin) run_item<LMASK>(A, s, Item{lin, gx, gy}, mlp_lds, park);
+    }
+    if (s + 1 < kStages &&
+        !grid_barrier(ctl, (unsigned long long)(s + 1) * gridDim.x, A.barrier_ticks))
+      return;
+  }
+}
+
+namespace {
+template <int LMASK>
+int resident_grid() {
+  // per device: workgroups of this kernel the device keeps resident at once
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!cache[dev]) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<LMASK>, kBlock,
+                                                     0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev] = per_cu * cus;
+  }
+  return cache[dev];
+}
+int lmask_of(const StepArgs& a) { return kHasLearned && a.mlp ? a.learned_mask : 0; }
+}  // namespace
+
+int persistent_grid(const StepArgs& a) {
+  if (a.harvest) return 0;
+  const int m = lmask_of(a);
+  if (m == 0) return resident_grid<0>();
+#if defined(NYX_PREC_MIXED)
+  if (m == 7) return resident_grid<7>();
+#endif
+  return 0;
+}
+
+hipError_t launch_step_persistent(const StepArgs& a, hipStream_t s) {
+  const int grid = persistent_grid(a);
+  if (grid <= 0) return hipErrorNotSupported;
+  if (!a.ctl) return hipErrorInvalidValue;
+  hipError_t e = launch_zero_u64(a.ctl, kCtlWords, s);
+  if (e != hipSuccess) return e;
+  if (lmask_of(a) == 0)
+    hipLaunchKernelGGL(k_step_persistent<0>, dim3(grid), dim3(kBlock), 0, s, a);
+#if defined(NYX_PREC_MIXED)
+  else
+    hipLaunchKernelGGL(k_step_persistent<7>, dim3(grid), dim3(kBlock), 0, s, a);
+#endif
   return hipGetLastError();
 }
 

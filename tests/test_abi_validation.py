@@ -96,7 +96,8 @@ def test_argument_errors(nyx):
     assert _step(nyx, p, b2) == -2
     for field, val in (("gamma", 1.0), ("riemann_maxiter", 0), ("precision", 7), ("cfl", 0.0),
                        ("small_pres", 0.0), ("riemann", 5), ("recon", 2),
-                       ("grav_energy_form", 0), ("grav_energy_form", 3)):
+                       ("grav_energy_form", 0), ("grav_energy_form", 3),
+                       ("mixed_riemann_stop", -1.0), ("mixed_riemann_stop", float("nan"))):
         q = nyx.default_params(**{field: val})
         assert _step(nyx, q, b) == -3, field
 

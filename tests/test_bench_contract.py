@@ -18,14 +18,24 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""
 
 
-def test_traffic_record_matches_the_kernel_sources():
+def test_traffic_records_are_used_only_for_their_kernel_sources():
+    # a committed counter record holds one value per launch-order candidate
+    # and is used only while it was taken on the current kernel code
+    import glob
+
     import bench
-    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_riem1_box256_mixed.json")))
-    assert rec["sources_sha256"] == bench.kernel_source_hash()
-    assert len(rec["bytes_per_launch_by_candidate"]) == 16
-    for c in range(16):
-        t = bench.measured_traffic("riem1", "mixed", c)
-        assert t is not None and t > 0
+    paths = glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))
+    assert paths
+    for path in paths:
+        rec = json.load(open(path))
+        assert len(rec["bytes_per_launch_by_candidate"]) == 16
+        current = rec["sources_sha256"] == bench.kernel_source_hash()
+        for c in range(16):
+            t = bench.measured_traffic(rec["kernel"], rec["form"], c, rec.get("workload"))
+            if current:
+                assert t == rec["bytes_per_launch_by_candidate"][c] and t > 0
+            else:
+                assert t is None
     assert bench.measured_traffic("riem1", "fp64", 0) is None
 
 

@@ -42,3 +42,16 @@ def test_stress_fields_distributions():
     assert abs(G[:, 4:-4, 4:-4, 4:-4].std() - 0.2) < 0.01
     # ghosts are periodic copies
     assert np.array_equal(U[:, :4], U[:, n:n + 4])
+
+
+def test_autotune_tie_break_by_traffic():
+    from paper_1301_4498_amd import tie_break_by_traffic
+    table = [[1.00, 1.02, 1.10, 1.01], [2.0, 1.5, 1.6, 3.0]]
+    tune = [0, 1]
+    # stage 0: candidates 0, 1, 3 are within 3% of the fastest; 3 moves the
+    # fewest bytes; stage 1 has no record and keeps its fastest
+    assert tie_break_by_traffic(table, tune, {0: [9e9, 8e9, 1e9, 5e9]}) == [3, 1]
+    # equal traffic: the faster of the tied candidates
+    assert tie_break_by_traffic(table, tune, {0: [5e9, 5e9, 5e9, 5e9]}) == [0, 1]
+    # a much faster order is never traded for traffic
+    assert tie_break_by_traffic(table, tune, {1: [1.0, 9e9, 1.0, 1.0]}) == [0, 1]
