@@ -216,11 +216,14 @@ constexpr int kTuneSlabShift = 2;
 constexpr int kTuneCandidates = 16;
 
 // Control block of the persistent step (device, zeroed before each launch):
-// per stage the heads of 8 work queues (one per eighth of the stage's walk,
-// drained first by the workgroups of one XCD), then the grid barrier's
-// arrival count and the abort flag a barrier that timed out raises.
-constexpr int kCtlBarrier = kStages * 8;
-constexpr int kCtlAbort = kCtlBarrier + 1;
+// per stage the heads of 8 work queues (one per eighth of the part of the
+// stage's walk that is not handed out statically, drained first by the
+// workgroups of one XCD); per stage boundary the arrival counts of the 8 XCD
+// groups of workgroups and the count of XCD groups complete; the abort flag
+// a barrier that timed out raises.
+constexpr int kCtlXcdBar = kStages * 8;
+constexpr int kCtlBarrier = kCtlXcdBar + kStages * 8;
+constexpr int kCtlAbort = kCtlBarrier + kStages;
 constexpr int kCtlWords = kCtlAbort + 1;
 
 // Launch-wide arguments of a step.

@@ -1611,24 +1611,54 @@ __device__ __forceinline__ void run_item(const StepArgs& A, int s, const Item& i
   }
 }
 
-// Next chunk [b0, b1) of a stage's n work items, taken by one thread.  The
-// walk is cut into 8 contiguous ranges (1 with the hardware-order tuning
-// bit), each with its own queue head; a workgroup drains the range of its
-// XCD first (workgroups are dispatched to the XCDs round-robin), so that
-// neighbouring items are read through one L2, then takes from the others.
-// *done marks ranges found empty.
-__device__ __forceinline__ bool grab(unsigned long long* head, unsigned n, unsigned nr,
-                                     unsigned home, unsigned chunk, unsigned* done,
-                                     unsigned* b0, unsigned* b1) {
-  for (unsigned k = 0; k < nr; ++k) {
-    const unsigned r = (home + k) % nr;
+// Walk position of workgroup w among G when the workgroups of each XCD
+// (dispatched round-robin, w mod 8) take one contiguous range: the same
+// numbering the staged launches use.
+__device__ __forceinline__ unsigned xcd_position(unsigned w, unsigned G) {
+  const unsigned q = G >> 3, r = G & 7;
+  const unsigned x = w & 7, k = w >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// How a stage's n work items are handed out to G workgroups.  The first
+// S = min(n, G c0) items are split statically: the workgroup at XCD
+// position p takes [p c0, (p + 1) c0), c0 = max(1, n / 2G), so a stage with
+// no more items than workgroups needs no atomic at all.  The rest [S, n) is
+// cut into nr contiguous ranges (8, or 1 with the hardware-order tuning bit
+// or when it is small), each with an atomic queue head; a workgroup drains
+// the range of its own XCD first, then takes from the others, `chunk` items
+// at a time.
+struct Share {
+  unsigned S, c0, nr, chunk;
+};
+__device__ __forceinline__ Share share_of(unsigned n, unsigned G, bool hw_order) {
+  Share h;
+  h.c0 = n / (2u * G);
+  h.c0 = h.c0 < 1u ? 1u : h.c0;
+  const unsigned long long s = (unsigned long long)G * h.c0;
+  h.S = s < n ? (unsigned)s : n;
+  const unsigned rest = n - h.S;
+  h.nr = (hw_order || rest < 64u * G) ? 1u : 8u;
+  h.chunk = rest / (16u * G);
+  h.chunk = h.chunk < 1u ? 1u : (h.chunk > 64u ? 64u : h.chunk);
+  return h;
+}
+// Next chunk [b0, b1) of the queued part, taken by one thread; *done marks
+// ranges found empty.
+__device__ __forceinline__ bool grab(unsigned long long* head, unsigned n, const Share& h,
+                                     unsigned home, unsigned* done, unsigned* b0,
+                                     unsigned* b1) {
+  const unsigned rest = n - h.S;
+  for (unsigned k = 0; k < h.nr; ++k) {
+    const unsigned r = (home + k) % h.nr;
     if (*done >> r & 1u) continue;
-    const unsigned lo = (unsigned)((unsigned long long)n * r / nr);
-    const unsigned hi = (unsigned)((unsigned long long)n * (r + 1) / nr);
-    const unsigned long long v = lo < hi ? atomicAdd(head + r, (unsigned long long)chunk) : 0ull;
+    const unsigned lo = h.S + (unsigned)((unsigned long long)rest * r / h.nr);
+    const unsigned hi = h.S + (unsigned)((unsigned long long)rest * (r + 1) / h.nr);
+    const unsigned long long v =
+        lo < hi ? atomicAdd(head + r, (unsigned long long)h.chunk) : 0ull;
     if (lo < hi && (unsigned long long)lo + v < hi) {
       *b0 = lo + (unsigned)v;
-      *b1 = hi - *b0 < chunk ? hi : *b0 + chunk;
+      *b1 = hi - *b0 < h.chunk ? hi : *b0 + h.chunk;
       return true;
     }
     *done |= 1u << r;
@@ -1636,23 +1666,28 @@ __device__ __forceinline__ bool grab(unsigned long long* head, unsigned n, unsig
   return false;
 }
 
-// Grid barrier for the stage boundary `target` (arrivals so far, all
-// workgroups).  The fences make every workgroup's stage results visible to
-// every XCD before any workgroup goes on.  A barrier that has not filled
-// after `ticks` of the wall clock (a workgroup that never became resident)
-// raises the abort flag; every workgroup that sees it leaves, so each wait
-// ends.  Returns false on abort.
-__device__ __forceinline__ bool grid_barrier(unsigned long long* ctl, unsigned long long target,
+// Grid barrier after stage s.  Each workgroup counts itself in its XCD
+// group's counter; the last of a group counts the group as complete; all
+// wait for every group.  The fences make every workgroup's stage results
+// visible to every XCD before any workgroup goes on.  A barrier that has not
+// filled after `ticks` of the wall clock (a workgroup that never became
+// resident) raises the abort flag; every workgroup that sees it leaves, so
+// each wait ends.  Returns false on abort.
+__device__ __forceinline__ bool grid_barrier(unsigned long long* ctl, int s,
                                              unsigned long long ticks) {
   __shared__ int ok_sh;
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    atomicAdd(ctl + kCtlBarrier, 1ull);
+    const unsigned G = gridDim.x, x = blockIdx.x & 7u;
+    const unsigned long long members = (G + 7u - x) / 8u;
+    const unsigned long long groups = G < 8u ? G : 8u;
+    if (atomicAdd(ctl + kCtlXcdBar + 8 * s + x, 1ull) + 1ull == members)
+      atomicAdd(ctl + kCtlBarrier + s, 1ull);
     const unsigned long long t0 = (unsigned long long)wall_clock64();
     int ok = 1;
-    while (__hip_atomic_load(ctl + kCtlBarrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-           target) {
+    while (__hip_atomic_load(ctl + kCtlBarrier + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           groups) {
       if (__hip_atomic_load(ctl + kCtlAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         ok = 0;
         break;
@@ -1662,7 +1697,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long* ctl, unsigned l
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
     __threadfence();
     ok_sh = ok;
@@ -1672,34 +1707,42 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long* ctl, unsigned l
 }
 
 // Waves per SIMD the persistent kernel is compiled for: with all seven stage
-// bodies inlined it needs 132 VGPRs in the FP32-mixed build (3 waves); asking
-// for 4 fits it in 128 with a 12-byte spill.  The FP64 build keeps the
-// compiler's choice (186 VGPRs, 2 waves; 4 waves would spill 148 bytes).
+// bodies inlined the plain FP32-mixed build needs 132 VGPRs (3 waves), and
+// asking for 4 fits it in 128 with a 12-byte spill.  The FP64 build (171
+// VGPRs; 4 waves would spill) and the learned form (4 waves would spill 472
+// bytes) keep 2.
 #if defined(NYX_PREC_MIXED)
 constexpr int kPersistWaves = 4;
 #else
 constexpr int kPersistWaves = 2;
 #endif
 template <int LMASK>
-__global__ __launch_bounds__(kBlock, kPersistWaves) void k_step_persistent(StepArgs A) {
+__global__ __launch_bounds__(kBlock, LMASK ? 2 : kPersistWaves) void k_step_persistent(StepArgs A) {
   __shared__ __bf16 mlp_lds[LMASK ? (kBlock / 64) * kMlpWaveLds : 1];
   __shared__ double park[(LMASK & 2) ? 1 : kPark * kBlock];
   __shared__ unsigned q_sh[3];
   unsigned long long* ctl = A.ctl;
+  const unsigned G = gridDim.x;
   const unsigned home = blockIdx.x & 7u;
+  const unsigned pos = xcd_position(blockIdx.x, G);
   for (int s = 0; s < kStages; ++s) {
     const unsigned gx = (unsigned)A.nblocks[stage_space(s)];
     const unsigned gy = stage_rows(s, (LMASK & 2) != 0);
     const unsigned n = gx * gy;
-    const unsigned nr = (A.tune[s] & kTuneHwOrder) ? 1u : 8u;
-    // about 16 takes per workgroup and stage, at most 64 items each
-    unsigned chunk = n / (16u * gridDim.x);
-    chunk = chunk < 1u ? 1u : (chunk > 64u ? 64u : chunk);
+    const Share h = share_of(n, G, (A.tune[s] & kTuneHwOrder) != 0);
+    // the static share (uniform over the workgroup)
+    const unsigned long long f0 = (unsigned long long)pos * h.c0;
+    const unsigned s0 = f0 < h.S ? (unsigned)f0 : h.S;
+    const unsigned s1 = f0 + h.c0 < h.S ? (unsigned)(f0 + h.c0) : h.S;
+    // items need no barrier between them: a body's block-wide scratch
+    // (counter and maximum reductions) synchronises itself, the parked
+    // states are per thread and the network's tiles per wave
+    for (unsigned lin = s0; lin < s1; ++lin) run_item<LMASK>(A, s, Item{lin, gx, gy}, mlp_lds, park);
     unsigned done = 0;
-    for (;;) {
+    while (h.S < n) {
       if (threadIdx.x == 0) {
         unsigned b0 = 0, b1 = 0;
-        const bool got = grab(ctl + 8 * s, n, nr, home, chunk, &done, &b0, &b1);
+        const bool got = grab(ctl + 8 * s, n, h, home, &done, &b0, &b1);
         q_sh[0] = b0;
         q_sh[1] = b1;
         q_sh[2] = got ? 1u : 0u;
@@ -1709,14 +1752,9 @@ __global__ __launch_bounds__(kBlock, kPersistWaves) void k_step_persistent(StepA
       const bool got = q_sh[2] != 0;
       __syncthreads();  // every thread has read q_sh before the next take
       if (!got) break;
-      // items need no barrier between them: a body's block-wide scratch
-      // (counter and maximum reductions) synchronises itself, the parked
-      // states are per thread and the network's tiles per wave
       for (unsigned lin = b0; lin < b1; ++lin) run_item<LMASK>(A, s, Item{lin, gx, gy}, mlp_lds, park);
     }
-    if (s + 1 < kStages &&
-        !grid_barrier(ctl, (unsigned long long)(s + 1) * gridDim.x, A.barrier_ticks))
-      return;
+    if (s + 1 < kStages && !grid_barrier(ctl, s, A.barrier_ticks)) return;
   }
 }
 
@@ -1751,8 +1789,18 @@ int persistent_grid(const StepArgs& a) {
 }
 
 hipError_t launch_step_persistent(const StepArgs& a, hipStream_t s) {
-  const int grid = persistent_grid(a);
+  int grid = persistent_grid(a);
   if (grid <= 0) return hipErrorNotSupported;
+  // no more workgroups than the largest stage has items
+  long long most = 0;
+  const bool l1 = (lmask_of(a) & 2) != 0;
+  const long long rows[kStages] = {1, 1, 3, 3, l1 ? 6 : 3, 3, 1};
+  const int space[kStages] = {kSpaceP, kSpaceE, kSpaceE, kSpaceE, kSpaceE, kSpaceE, kSpaceV};
+  for (int st = 0; st < kStages; ++st) {
+    const long long n = (long long)a.nblocks[space[st]] * rows[st];
+    most = n > most ? n : most;
+  }
+  if (most < grid) grid = (int)(most > 0 ? most : 1);
   if (!a.ctl) return hipErrorInvalidValue;
   hipError_t e = launch_zero_u64(a.ctl, kCtlWords, s);
   if (e != hipSuccess) return e;
