@@ -51,6 +51,7 @@ METRIC = "zone-updates/s (plain FP64 vs FP32+batched+learned flux) + % HBM roofl
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, FP64 and FP32
 STAGES = ("prim", "flat", "trace", "riem0", "riem1", "riem2", "update")
+MODE_NAMES = ("staged", "persistent", "fused")  # NYX_LAUNCH_* 0, 1, 2
 RIEMANN = ("riem0", "riem1", "riem2")
 OPCOUNTS = os.path.join(ROOT, "profiles", "opcounts_step.json")
 OPCOUNT_KEYS = {"box256": "box256_smooth fields (64^3 box of the same distributions, seed 2)",
@@ -131,22 +132,23 @@ def step_bytes(shapes, grav_bytes):
 
 
 def roofline_of(stage_ms, table, shapes, iters, step_ms, grav_bytes, form, workload,
-                tune=None, persistent_ms=None):
+                tune=None, persistent_ms=None, fused=False):
     """The dominant kernel's figures: algorithmic TFLOP/s against the vector
-    ALU peak (the dominant stage kernel, or the persistent step kernel, which
-    runs every stage), and the whole step's algorithmic bytes against HBM."""
+    ALU peak (the dominant stage kernel, the fused final-stage kernel, or the
+    persistent step kernel, which runs every stage), and the whole step's
+    algorithmic bytes against HBM."""
     if persistent_ms is not None:
         dom, ms = "step_persistent", persistent_ms
         fl = sum(stage_flops(table, st, shapes, iters) for st in STAGES)
     else:
-        dom = max(STAGES, key=lambda s: stage_ms[s])
-        ms = stage_ms[dom]
-        fl = stage_flops(table, dom, shapes, iters)
+        dom = max(kernel_stages(fused), key=lambda s: kernel_ms(stage_ms, s))
+        ms = kernel_ms(stage_ms, dom)
+        fl = kernel_flops(table, dom, shapes, iters)
     ach = fl / (ms * 1e-3) / 1e12
     t = None
-    if tune is not None and persistent_ms is None:
+    if tune is not None and persistent_ms is None and dom in STAGES:
         t = measured_traffic(dom, form, tune[STAGES.index(dom)], workload)
-    roof = {"bound": "alu" if dom in RIEMANN + ("trace", "step_persistent") else "hbm",
+    roof = {"bound": "alu" if dom in RIEMANN + ("trace", "step_persistent", "final") else "hbm",
             "kernel": dom, "ms_per_launch": round(ms, 4),
             "flops_per_launch": fl, "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 4), "traffic": t}
@@ -162,12 +164,32 @@ def roofline_of(stage_ms, table, shapes, iters, step_ms, grav_bytes, form, workl
     return roof, hbm
 
 
-def stage_rates(stage_ms, table, shapes, iters):
-    """Per-stage ms, algorithmic TFLOP/s (oracle op counts)."""
+FUSED_STAGES = STAGES[:5] + ("final",)  # riem2 + update as one launch (k_final)
+
+
+def kernel_stages(fused):
+    return FUSED_STAGES if fused else STAGES
+
+
+def kernel_ms(stage_ms, stage):
+    """ms of a stage kernel; "final" is the fused launch, which the library's
+    events report as stage riem2 (update's interval is empty)."""
+    return stage_ms["riem2"] + stage_ms["update"] if stage == "final" else stage_ms[stage]
+
+
+def kernel_flops(table, stage, shapes, iters):
+    if stage == "final":
+        return (stage_flops(table, "riem2", shapes, iters) +
+                stage_flops(table, "update", shapes, iters))
+    return stage_flops(table, stage, shapes, iters)
+
+
+def stage_rates(stage_ms, table, shapes, iters, fused=False):
+    """Per-kernel ms, algorithmic TFLOP/s (oracle op counts)."""
     out = {}
-    for s in STAGES:
-        ms = stage_ms[s]
-        fl = stage_flops(table, s, shapes, iters)
+    for s in kernel_stages(fused):
+        ms = kernel_ms(stage_ms, s)
+        fl = kernel_flops(table, s, shapes, iters)
         out[s] = {"ms": round(ms, 4), "tflops": round(fl / max(ms, 1e-9) / 1e9, 3)}
     return out
 KERNEL_SOURCES = ("paper_1301_4498_amd/csrc/nyx_step.hip", "paper_1301_4498_amd/csrc/nyx_internal.h",
@@ -291,6 +313,10 @@ def run_box(nyx, torch, w, prm, steps, warmup, table):
     # launch orders per stage from the library's autotuner (untimed)
     tune, tune_ms = plan.autotune(U, G, dts[0:1], w.a_at(0), w.a_at(1), Uo, dt_next=dts[1:2],
                                   reps=3)
+    # launch mode by time (the fused final stage where the form allows it)
+    mode, mode_ms = plan.autotune_mode(U, G, dts[0:1], w.a_at(0), w.a_at(1), Uo, reps=3)
+    persistent = mode == nyx.NYX_LAUNCH_PERSISTENT
+    fused = mode == nyx.NYX_LAUNCH_FUSED and not (prm.learned_stages_mask & 4)
     st = torch.zeros(10, dtype=torch.int64, device="cuda")
     bufs = [U, Uo]
     k = 0
@@ -329,9 +355,13 @@ def run_box(nyx, torch, w, prm, steps, warmup, table):
     torch.cuda.empty_cache()
     mixed = prm.precision != nyx.NYX_FP64
     roof, hbm = roofline_of(stage_ms, table, [w.n], it, ms / steps, 4 if mixed else 8,
-                            "fp64" if not mixed else "mixed", "box256_smooth", tune)
+                            "fp64" if not mixed else "mixed", "box256_smooth", tune,
+                            persistent_ms=ms / steps if persistent else None,  # with the fill
+                            fused=fused)
     return {"zone_updates_per_s": n ** 3 * steps / (ms * 1e-3), "ms_per_step": ms / steps,
-            "stage": stage_rates(stage_ms, table, [w.n], it), "mean_riemann_iters": it,
+            "launch_mode": MODE_NAMES[mode], "mode_step_ms": dict(zip(MODE_NAMES, mode_ms)),
+            "stage": None if persistent else stage_rates(stage_ms, table, [w.n], it, fused),
+            "mean_riemann_iters": it,
             "stats_first_step": stats, "finite": finite, "rho": rho, "tuning": tune,
             "tuning_ms": tune_ms, "roofline": roof, "hbm_step": hbm}
 
@@ -422,17 +452,25 @@ def headline_leg(nyx, torch, synth, learn, steps, warmup, log, n=512, m=64, lear
     dts = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
     plan.estimate_dt(A0, a0, 0.5, dts[0:1])
     tune, _ = plan.autotune(A0, grav, dts[0:1], a_at(0), a_at(1), bufs[1], reps=2)
+    # the plain step in its fastest launch mode too
+    mode, mode_ms = plan.autotune_mode(A0, grav, dts[0:1], a_at(0), a_at(1), bufs[1], reps=2)
+    persistent = mode == nyx.NYX_LAUNCH_PERSISTENT
+    fused = mode == nyx.NYX_LAUNCH_FUSED
     ms, stage_ms, st, fin = run_plan(nyx, torch, plan, A0, bufs, grav, steps, warmup,
                                      lambda k: dts[k:k + 1], a_at, plan.fill_ghosts,
                                      dt_next_of=lambda k: dts[k + 1:k + 2])
+    if persistent:
+        assert not plan.persistent_aborted()
     rho64 = fin[0, 4:-4, 4:-4, 4:-4].contiguous()
     it = iters_per_face(st)
     roof, hbm = roofline_of(stage_ms, table, [(n, n, n)], it, ms, 8, "fp64", "box512_stress",
-                            tune)
+                            tune, persistent_ms=stage_ms["step_call"] if persistent else None,
+                            fused=fused)
     out["forms"]["fp64_one_box"] = {
         "zone_updates_per_s": zones / (ms * 1e-3), "ms_per_step": ms,
-        "stage": stage_rates(stage_ms, table, [(n, n, n)], it), "mean_riemann_iters": it,
-        "stats": st, "tuning": tune, "roofline": roof, "hbm_step": hbm,
+        "launch_mode": MODE_NAMES[mode], "mode_step_ms": dict(zip(MODE_NAMES, mode_ms)),
+        "stage": None if persistent else stage_rates(stage_ms, table, [(n, n, n)], it, fused),
+        "mean_riemann_iters": it, "stats": st, "tuning": tune, "roofline": roof, "hbm_step": hbm,
         "finite": bool(torch.isfinite(fin).all().item())}
     log("stress fp64 one box: %.3e zone-updates/s" % (zones / (ms * 1e-3)))
     dt_host = dts.cpu().tolist()
@@ -473,9 +511,10 @@ def headline_leg(nyx, torch, synth, learn, steps, warmup, log, n=512, m=64, lear
                 traffic[i] = per
         tune, _ = plan.autotune(A0, G32, dtp[0], a_at(0), a_at(1), bufs[1], reps=2,
                                 traffic=(traffic or None) if name == "mixed_patches" else None)
-        # staged or persistent launch, whichever is faster for this plan
+        # staged, persistent or fused-final launch, whichever is fastest
         mode, mode_ms = plan.autotune_mode(A0, G32, dtp[0], a_at(0), a_at(1), bufs[1], reps=2)
         persistent = mode == nyx.NYX_LAUNCH_PERSISTENT
+        fused = mode == nyx.NYX_LAUNCH_FUSED and not name.startswith("learned")
 
         def fill(s):
             plan.fill_ghosts(s, mode=1, grid=grid)
@@ -489,12 +528,13 @@ def headline_leg(nyx, torch, synth, learn, steps, warmup, log, n=512, m=64, lear
         it = iters_per_face(st)
         roof, hbm = roofline_of(stage_ms, table, shapes, it, ms, 4, "mixed",
                                 "box512_stress_patches", tune,
-                                persistent_ms=stage_ms["step_call"] if persistent else None)
+                                persistent_ms=stage_ms["step_call"] if persistent else None,
+                                fused=fused)
         r = {"zone_updates_per_s": zones / (ms * 1e-3), "ms_per_step": ms,
              "rho_l1_vs_fp64": l1, "finite": bool(torch.isfinite(fin).all().item()),
-             "launch_mode": "persistent" if persistent else "staged",
-             "mode_step_ms": {"staged": mode_ms[0], "persistent": mode_ms[1]},
-             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it),
+             "launch_mode": MODE_NAMES[mode],
+             "mode_step_ms": dict(zip(MODE_NAMES, mode_ms)),
+             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it, fused),
              "step_call_ms": stage_ms["step_call"], "mean_riemann_iters": it,
              "stats": st, "tuning": tune, "roofline": roof, "hbm_step": hbm}
         if name.startswith("learned"):
@@ -597,6 +637,7 @@ def level_leg(nyx, torch, synth, learn, flux, steps, warmup, log):
             mode, mode_ms = plan.autotune_mode(state, grav, dt_seq[0], a_at(0), a_at(1), bufs[1],
                                                reps=2)
         persistent = plan.launch_mode == nyx.NYX_LAUNCH_PERSISTENT
+        fused = plan.launch_mode == nyx.NYX_LAUNCH_FUSED and form != "learned"
         ms, stage_ms, st, fin = run_plan(nyx, torch, plan, state, bufs, grav, steps, warmup,
                                          lambda k: dt_seq[k], a_at, plan.fill_ghosts,
                                          dt_next_of=dt_next_of)
@@ -623,12 +664,13 @@ def level_leg(nyx, torch, synth, learn, flux, steps, warmup, log):
             rho64 = rho_boxes
         roof, hbm = roofline_of(stage_ms, table, shapes, it, ms, 8 if form == "fp64" else 4,
                                 form, "level4096", tune,
-                                persistent_ms=stage_ms["step_call"] if persistent else None)
+                                persistent_ms=stage_ms["step_call"] if persistent else None,
+                                fused=fused)
         r = {"batched_zone_updates_per_s": V / (ms * 1e-3), "batched_ms_per_step": ms,
              "groups": plan.num_groups, "tuning": tune, "finite": finite,
-             "launch_mode": "persistent" if persistent else "staged",
-             "mode_step_ms": mode_ms,
-             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it),
+             "launch_mode": MODE_NAMES[plan.launch_mode],
+             "mode_step_ms": dict(zip(MODE_NAMES, mode_ms)) if mode_ms else None,
+             "stage": None if persistent else stage_rates(stage_ms, table, shapes, it, fused),
              "mean_riemann_iters": it, "roofline": roof, "hbm_step": hbm}
         if form != "fp64":
             r["rho_l1_vs_fp64"] = float(num / den)
@@ -997,11 +1039,11 @@ def gravity_leg(nyx, torch, synth, w, log, reps=3):
 
 
 def launch_modes_leg(nyx, torch, synth, log):
-    """Staged against persistent launches of FP32-mixed batched plans on
-    small workloads, where launch overhead weighs most: the 32^3 box of the
-    smallest configuration, and a level of 512 boxes of 16^3 (smooth-flow
-    fields).  Both modes from nyx_batch_autotune_mode (best of 5 steps after
-    one untimed, launch orders autotuned first)."""
+    """Staged, persistent and fused-final launches of FP32-mixed batched
+    plans on small workloads, where launch overhead weighs most: the 32^3
+    box of the smallest configuration, and a level of 512 boxes of 16^3
+    (smooth-flow fields).  Every mode from nyx_batch_autotune_mode (best of 5
+    steps after one untimed, launch orders autotuned first)."""
     out = {}
     cases = {"box32_plain (one 32^3 box)": [(32, 32, 32)], "level of 512 boxes of 16^3": [(16, 16, 16)] * 512}
     for name, shapes in cases.items():
@@ -1026,11 +1068,12 @@ def launch_modes_leg(nyx, torch, synth, log):
         plan.autotune(state, grav, dt, a0, a0 * 1.001, other, reps=2)
         mode, ms = plan.autotune_mode(state, grav, dt, a0, a0 * 1.001, other, reps=5)
         V = sum(a * b * c for a, b, c in shapes)
-        out[name] = {"staged_ms": ms[0], "persistent_ms": ms[1],
-                     "staged_zone_updates_per_s": V / (ms[0] * 1e-3),
-                     "persistent_zone_updates_per_s": V / (ms[1] * 1e-3) if ms[1] > 0 else None,
-                     "kept": "persistent" if mode == nyx.NYX_LAUNCH_PERSISTENT else "staged"}
-        log("launch modes, %s: staged %.4f ms, persistent %.4f ms" % (name, ms[0], ms[1]))
+        out[name] = {"%s_ms" % m: v for m, v in zip(MODE_NAMES, ms)}
+        out[name].update({"%s_zone_updates_per_s" % m: V / (v * 1e-3) if v > 0 else None
+                          for m, v in zip(MODE_NAMES, ms)})
+        out[name]["kept"] = MODE_NAMES[mode]
+        log("launch modes, %s: staged %.4f ms, persistent %.4f ms, fused %.4f ms"
+            % (name, ms[0], ms[1], ms[2]))
         plan.close()
         del plan, ws, state, grav, other
         torch.cuda.empty_cache()

@@ -242,8 +242,19 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  * nyx_batch_persistent_aborted reports it.  Available for plain steps in
  * both precisions and for the learned flux on all three stages; a plan that
  * harvests training records runs staged.  Stage timing (nyx_profile_*) sees
- * only staged launches. */
-enum { NYX_LAUNCH_STAGED = 0, NYX_LAUNCH_PERSISTENT = 1 };
+ * only staged launches.
+ * NYX_LAUNCH_FUSED: staged launches, except that the last two stages (the
+ * final Riemann solves of Sec. 3.2 and the conservative update with the
+ * gravity corrector and the dual-energy sync of Sec. 3.6, Steps 2 and 6)
+ * run as one launch: a workgroup takes a tile of cell columns of a box and
+ * marches up the box in z, solving each final face once (plus the faces past
+ * the tile's last column and row) and updating every cell as soon as its six
+ * faces are known, so the final face states never reach HBM.  Bit for bit the
+ * result of the staged launches.  A plan that uses the learned flux on the
+ * final stage, harvests training records or feeds flux registers runs those
+ * two stages staged; nyx_profile_* reports the fused launch as stage 6 and a
+ * zero-length stage 7. */
+enum { NYX_LAUNCH_STAGED = 0, NYX_LAUNCH_PERSISTENT = 1, NYX_LAUNCH_FUSED = 2 };
 /* NYX_E_UNSUPPORTED when the persistent mode is not available for the
  * plan's parameters. */
 int nyx_batch_set_launch_mode(nyx_batch* plan, int mode);
@@ -252,7 +263,7 @@ int nyx_batch_get_launch_mode(const nyx_batch* plan, int* mode);
  * barrier (synchronises `stream`). */
 int nyx_batch_persistent_aborted(nyx_batch* plan, int* aborted, void* stream);
 /* Times `reps` whole steps (after one untimed) in each available mode with
- * the plan's current launch orders and keeps the faster; ms_out[2] (host,
+ * the plan's current launch orders and keeps the fastest; ms_out[3] (host,
  * or NULL) receives the best step time of each mode (-1: not available);
  * *mode_out (or NULL) the mode kept.  Synchronises `stream`. */
 int nyx_batch_autotune_mode(nyx_batch* plan, const double* state_in, const void* grav,

@@ -10,13 +10,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (NYX_FP64, NYX_LAUNCH_PERSISTENT, NYX_LAUNCH_STAGED, NYX_MIXED,
-                   NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMANN_LEARNED,
+from ._lib import (NYX_FP64, NYX_LAUNCH_FUSED, NYX_LAUNCH_PERSISTENT, NYX_LAUNCH_STAGED,
+                   NYX_MIXED, NYX_RECON_PLM, NYX_RECON_PPM, NYX_RIEMANN_LEARNED,
                    NYX_RIEMANN_LINEARIZED, NYX_RIEMANN_TWOSHOCK, STATS_FIELDS, Box, NyxError,
                    Params, Stats, check, lib)
 
 __all__ = ["Box", "Params", "Stats", "NyxError", "NYX_FP64", "NYX_MIXED", "NYX_LAUNCH_STAGED",
-           "NYX_LAUNCH_PERSISTENT", "NYX_RIEMANN_TWOSHOCK",
+           "NYX_LAUNCH_PERSISTENT", "NYX_LAUNCH_FUSED", "NYX_RIEMANN_TWOSHOCK",
            "NYX_RIEMANN_LEARNED", "NYX_RIEMANN_LINEARIZED", "NYX_RECON_PPM", "NYX_RECON_PLM",
            "default_params", "make_box", "workspace_bytes", "estimate_dt",
            "hydro_step", "hydro_step_noalloc", "noalloc_max_bytes", "fill_ghosts_periodic", "Batch", "FillPlan", "SyncPlan", "cic_deposit", "PoissonSolver",
@@ -247,14 +247,14 @@ class Batch:
         return bool(a.value)
 
     def autotune_mode(self, state_in, grav, dt, a_old, a_new, state_out, reps=3, stream=None):
-        """Keep the faster launch mode (nyx_batch_autotune_mode); returns
-        (mode, [staged ms, persistent ms or -1])."""
-        ms = (ctypes.c_float * 2)()
+        """Keep the fastest launch mode (nyx_batch_autotune_mode); returns
+        (mode, [staged ms, persistent ms, fused ms], -1 where not available)."""
+        ms = (ctypes.c_float * 3)()
         m = ctypes.c_int(0)
         check("nyx_batch_autotune_mode", lib().nyx_batch_autotune_mode(
             self.handle, _ptr(state_in), _ptr(grav), _ptr(dt), float(a_old), float(a_new),
             _ptr(state_out), int(reps), ms, ctypes.byref(m), _stream(stream)))
-        return m.value, [round(float(ms[0]), 4), round(float(ms[1]), 4)]
+        return m.value, [round(float(v), 4) for v in ms]
 
     def set_flux_register(self, sync, level, reg):
         """Feed a two-level sync plan's register (device FP64, 6 x faces) from

@@ -19,6 +19,7 @@ NYX_RECON_PPM = 0
 NYX_RECON_PLM = 1
 NYX_LAUNCH_STAGED = 0
 NYX_LAUNCH_PERSISTENT = 1
+NYX_LAUNCH_FUSED = 2
 
 STATUS = {0: "NYX_OK", -1: "NYX_E_NULL", -2: "NYX_E_SHAPE", -3: "NYX_E_PARAM",
           -4: "NYX_E_ALIAS", -5: "NYX_E_HIP", -6: "NYX_E_UNSUPPORTED", -7: "NYX_E_WORKSPACE",

@@ -84,6 +84,7 @@ void set_blocks(const BoxDev& b, int* nb) {
   nb[kSpaceP] = (int)blocks_for(b.P);
   nb[kSpaceE] = (int)blocks_for(b.E);
   nb[kSpaceV] = (int)blocks_for(b.V);
+  nb[kSpaceT] = b.ntiles;
 }
 
 // [a0, a0 + alen) and [b0, b0 + blen) in bytes
@@ -205,7 +206,7 @@ int step_one_box(const nyx_params* p, const nyx_box* box, const double* state_in
   if (launch_prologue(A, 1, cst, tab, pre, s) != hipSuccess) return NYX_E_HIP;
   A.table = tab;
   A.nb = 1;
-  for (int k = 0; k < 3; ++k) A.prefix[k] = pre + 2 * k;
+  for (int k = 0; k < kSpaces; ++k) A.prefix[k] = pre + 2 * k;
   A.consts = cst;
   // the running CFL maximum and the partial counters start from zero (fill
   // kernels, so that a captured graph holds no memset node)
@@ -346,8 +347,8 @@ struct nyx_batch {
   std::vector<nyx_box> boxes;
   struct Group {
     int b0, b1;
-    int nblocks[3];
-    const int* prefix[3];  // device
+    int nblocks[kSpaces];
+    const int* prefix[kSpaces];  // device
   };
   std::vector<Group> groups;
   BoxDev* table;                 // device, nbox entries in box order
@@ -380,7 +381,8 @@ size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
 // bytes of the table region for a plan with `ngroups` groups
 size_t table_bytes(int nbox, int ngroups) {
-  return round256(sizeof(BoxDev) * (size_t)nbox) + round256(sizeof(int) * 3 * (size_t)(nbox + ngroups)) +
+  return round256(sizeof(BoxDev) * (size_t)nbox) +
+         round256(sizeof(int) * kSpaces * (size_t)(nbox + ngroups)) +
          round256(sizeof(unsigned long long) * (size_t)nbox) + round256(kSlotBytes) +
          round256(sizeof(StepC) * (size_t)nbox) + round256(sizeof(unsigned long long) * kCtlWords);
 }
@@ -451,11 +453,15 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
       nyx_batch::Group g{};
       g.b0 = g0;
       g.b1 = i;
-      for (int s = 0; s < 3; ++s) {
+      for (int s = 0; s < kSpaces; ++s) {
         g.prefix[s] = (const int*)(size_t)prefix.size();  // host offset for now
         int acc = 0;
         for (int b = g0; b < i; ++b) {
           prefix.push_back(acc);
+          if (s == kSpaceT) {
+            acc += host[b].ntiles;
+            continue;
+          }
           long long cnt = s == kSpaceP ? host[b].P : (s == kSpaceE ? host[b].E : host[b].V);
           acc += (int)blocks_for(cnt);
         }
@@ -472,7 +478,8 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
   char* w = (char*)workspace;
   plan->table = (BoxDev*)w;
   int* pre_dev = (int*)(w + round256(sizeof(BoxDev) * (size_t)nbox));
-  plan->smax = (unsigned long long*)((char*)pre_dev + round256(sizeof(int) * 3 * (size_t)(nbox + nbox)));
+  plan->smax = (unsigned long long*)((char*)pre_dev +
+                                     round256(sizeof(int) * kSpaces * (size_t)(nbox + nbox)));
   plan->slots = (unsigned long long*)((char*)plan->smax + round256(sizeof(unsigned long long) * (size_t)nbox));
   plan->consts = (StepC*)((char*)plan->slots + round256(kSlotBytes));
   plan->ctl = (unsigned long long*)((char*)plan->consts + round256(sizeof(StepC) * (size_t)nbox));
@@ -488,7 +495,7 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
   }
   plan->state_span = span;
   for (auto& g : plan->groups)
-    for (int s = 0; s < 3; ++s) g.prefix[s] = pre_dev + (size_t)g.prefix[s];
+    for (int s = 0; s < kSpaces; ++s) g.prefix[s] = pre_dev + (size_t)g.prefix[s];
   hipStream_t st = (hipStream_t)stream;
   if (hipMemcpyAsync(plan->table, host.data(), sizeof(BoxDev) * (size_t)nbox, hipMemcpyHostToDevice,
                      st) != hipSuccess ||
@@ -517,7 +524,7 @@ namespace {
 StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   StepArgs A{};
   A.table = plan->table + g.b0;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < kSpaces; ++s) {
     A.prefix[s] = g.prefix[s];
     A.nblocks[s] = g.nblocks[s];
   }
@@ -602,6 +609,10 @@ int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, c
     A.a_new = a_new;
     A.stats = stats;
     A.dt_next = dt_next;
+    // the fused final stage where the plan allows it (flux registers read
+    // the final face states the fused kernel does not store); the launch-
+    // order sweep times the staged kernels
+    A.fuse_final = plan->mode == NYX_LAUNCH_FUSED && !plan->reg && !group_ev ? 1 : 0;
     hipError_t e;
     if (group_ev) {
       A.ev = group_ev[&g - plan->groups.data()];
@@ -669,7 +680,8 @@ int nyx_batch_get_tuning(const nyx_batch* plan, int* tune) {
 
 int nyx_batch_set_launch_mode(nyx_batch* plan, int mode) {
   if (!plan) return NYX_E_NULL;
-  if (mode != NYX_LAUNCH_STAGED && mode != NYX_LAUNCH_PERSISTENT) return NYX_E_PARAM;
+  if (mode != NYX_LAUNCH_STAGED && mode != NYX_LAUNCH_PERSISTENT && mode != NYX_LAUNCH_FUSED)
+    return NYX_E_PARAM;
   if (mode == NYX_LAUNCH_PERSISTENT) {
     if (plan->groups.empty()) return NYX_E_UNSUPPORTED;
     StepArgs A = group_args(plan, plan->groups[0]);
@@ -775,8 +787,8 @@ int nyx_batch_autotune_mode(nyx_batch* plan, const double* state_in, const void*
     return NYX_E_HIP;
   }
   const int saved = plan->mode;
-  float best[2] = {-1.f, -1.f};
-  for (int mode = NYX_LAUNCH_STAGED; mode <= NYX_LAUNCH_PERSISTENT && rc == NYX_OK; ++mode) {
+  float best[3] = {-1.f, -1.f, -1.f};
+  for (int mode = NYX_LAUNCH_STAGED; mode <= NYX_LAUNCH_FUSED && rc == NYX_OK; ++mode) {
     if (nyx_batch_set_launch_mode(plan, mode) != NYX_OK) continue;  // not available
     for (int r = 0; r <= reps && rc == NYX_OK; ++r) {  // r = 0 warms up
       if (hipEventRecord(e0, s) != hipSuccess) rc = NYX_E_HIP;
@@ -797,11 +809,12 @@ int nyx_batch_autotune_mode(nyx_batch* plan, const double* state_in, const void*
     plan->mode = saved;
     return rc;
   }
-  plan->mode = (best[1] >= 0.f && best[1] < best[0]) ? NYX_LAUNCH_PERSISTENT : NYX_LAUNCH_STAGED;
-  if (ms_out) {
-    ms_out[0] = best[0];
-    ms_out[1] = best[1];
-  }
+  int keep = NYX_LAUNCH_STAGED;
+  for (int mode = NYX_LAUNCH_PERSISTENT; mode <= NYX_LAUNCH_FUSED; ++mode)
+    if (best[mode] >= 0.f && best[mode] < best[keep]) keep = mode;
+  plan->mode = keep;
+  if (ms_out)
+    for (int mode = 0; mode < 3; ++mode) ms_out[mode] = best[mode];
   if (mode_out) *mode_out = plan->mode;
   return NYX_OK;
 }

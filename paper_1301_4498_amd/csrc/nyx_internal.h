@@ -10,6 +10,10 @@
 namespace nyx {
 
 constexpr int kBlock = 256;  // threads per block: 4 wavefronts of 64
+// Threads per workgroup of the fused final-stage kernel (8 wavefronts): a
+// tile of TX x TY cell columns of a box, TX = min(n_x, 64), TY = min(n_y,
+// kFinBlock / TX).
+constexpr int kFinBlock = 512;
 // Stored per face: the Godunov state (rho_g, u_g normal, v_g, w_g transverse,
 // p_g) in the face's rotated frame; every flux is recomputed from it.
 constexpr int kGod = 5;
@@ -47,6 +51,7 @@ struct BoxDev {
   FastDiv dz[3];           // per Space: number of planes
   unsigned sy[3];          // per Space: rows per plane
   unsigned sc[3];          // per Space: cell count (< 2^31)
+  int tx, ty, ntx, ntiles; // fused final stage: tile shape, tiles along x, tiles
 };
 
 // Stage-array element count for a box (before alignment padding).
@@ -95,6 +100,10 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   d.sc[0] = (unsigned)d.P;
   d.sc[1] = (unsigned)d.E;
   d.sc[2] = (unsigned)d.V;
+  d.tx = b.n[0] < 64 ? b.n[0] : 64;
+  d.ty = b.n[1] < kFinBlock / d.tx ? b.n[1] : kFinBlock / d.tx;
+  d.ntx = (b.n[0] + d.tx - 1) / d.tx;
+  d.ntiles = d.ntx * ((b.n[1] + d.ty - 1) / d.ty);
   if (out) *out = d;
   return o;
 }
@@ -107,8 +116,11 @@ struct StepC {
   double pad_;
 };
 
-// Which cell range a launch walks.
-enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2 };
+// Which cell range a launch walks: padded cells, the [-1, n]^3 range, valid
+// cells, and the column tiles of the fused final stage (counted in tiles,
+// not in blocks of cells; no cell coordinates of their own).
+enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2, kSpaceT = 3 };
+constexpr int kSpaces = 4;
 
 #ifdef __HIPCC__
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -232,9 +244,9 @@ struct StepArgs {
   // entry points write a one-entry table in their prologue)
   BoxDev single;
   const BoxDev* table;     // device, nb entries (batched) or nullptr
-  const int* prefix[3];    // device, nb+1 block prefixes per Space (batched)
+  const int* prefix[kSpaces];  // device, nb+1 block prefixes per Space (batched)
   int nb;
-  int nblocks[3];          // grid size per Space
+  int nblocks[kSpaces];    // grid size per Space
   // physics
   const double* Uin;
   double* Uout;
@@ -274,6 +286,8 @@ struct StepArgs {
   // and the grid barrier's time limit in wall-clock ticks
   unsigned long long* ctl;
   unsigned long long barrier_ticks;
+  // 1: stages riem2 and update run fused (k_final) where the step allows it
+  int fuse_final;
 };
 
 

@@ -125,15 +125,16 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
   return v;
 }
 // Block-wide sum added into one of kStatSlots partial counter blocks; every
-// thread of the block must call it (it synchronises the block).
+// thread of the block (NT threads) must call it (it synchronises the block).
+template <int NT = kBlock>
 __device__ __forceinline__ void count(const StepArgs& A, int field, unsigned v) {
-  __shared__ unsigned red[kBlock / 64];
+  __shared__ unsigned red[NT / 64];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned t = 0;
-    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
     const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % kStatSlots;
     if (t) atomicAdd(A.slots + slot * kStatFields + field, (unsigned long long)t);
   }
@@ -1235,6 +1236,46 @@ __device__ __forceinline__ unsigned face_hash(unsigned long long seed, int box, 
 // ---------------------------------------------------------------------------
 // stage 6: final d-states and comoving fluxes on valid faces
 // ---------------------------------------------------------------------------
+// The final d-states of the face at E-index e (between the cells at E-index
+// e - e_d and e; c[d] >= 1 and the transverse coordinates in [1, n]): both
+// cells' edge states corrected by the t1- and t2-differences of the stage-1
+// states, rotated into the face's frame.  Adds the reverts to *reverts.
+template <int D>
+__device__ __forceinline__ void final_states(const StepArgs& A, const BoxDev& b, const StepC& C,
+                                             unsigned e, double* ql, double* qr,
+                                             unsigned* reverts) {
+  constexpr int d = D;
+  constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+  const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
+  const real* W = (const real*)A.work + b.w_edge;
+  const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
+  const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
+  // both cells' loads are issued before any arithmetic, so a wave waits
+  // once for all of them
+  real qe[2][5];
+  God ga[2][2], gb[2][2];
+  for (int s = 0; s < 2; ++s) {
+    const long long sh = s == 0 ? -sdd : 0;  // cell shift in the bases, offset e
+    const int side = s == 0 ? 1 : 0;
+    for (int v = 0; v < 5; ++v) qe[s][v] = ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
+    ga[s][0] = ld_god(G1a + sh, b.E, e);
+    ga[s][1] = ld_god(G1a + sh + s1, b.E, e);
+    gb[s][0] = ld_god(G1b + sh, b.E, e);
+    gb[s][1] = ld_god(G1b + sh + s2, b.E, e);
+  }
+  double qs[2][5];
+  for (int s = 0; s < 2; ++s) {
+    double q[5];
+    for (int v = 0; v < 5; ++v) q[v] = (double)qe[s][v];
+    double Dc[5], De;
+    tdiff<true>(A, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
+    tdiff<false>(A, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
+    *reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
+  }
+  rotate(d, qs[0], ql);
+  rotate(d, qs[1], qr);
+}
+
 template <int MODE, int D>
 __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, unsigned idx,
                                           __bf16* lds, Tally& T) {
@@ -1247,37 +1288,7 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
   const bool active = idx < b.E && c[d] >= 1 && c[t1] >= 1 && c[t1] <= b.n[t1] && c[t2] >= 1 &&
                       c[t2] <= b.n[t2];
   double ql[5], qr[5];
-  if (active) {
-    const StepC& C = step_consts(A, b);
-    const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
-    const real* W = (const real*)A.work + b.w_edge;
-    const real* G1a = (const real*)A.work + b.w_f1 + (long long)pair_index(t1, t2) * kGod * b.E;
-    const real* G1b = (const real*)A.work + b.w_f1 + (long long)pair_index(t2, t1) * kGod * b.E;
-    // both cells' loads are issued before any arithmetic, so a wave waits
-    // once for all of them
-    real qe[2][5];
-    God ga[2][2], gb[2][2];
-    for (int s = 0; s < 2; ++s) {
-      const long long sh = s == 0 ? -sdd : 0;  // cell shift in the bases, offset e
-      const int side = s == 0 ? 1 : 0;
-      for (int v = 0; v < 5; ++v) qe[s][v] = ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
-      ga[s][0] = ld_god(G1a + sh, b.E, e);
-      ga[s][1] = ld_god(G1a + sh + s1, b.E, e);
-      gb[s][0] = ld_god(G1b + sh, b.E, e);
-      gb[s][1] = ld_god(G1b + sh + s2, b.E, e);
-    }
-    double qs[2][5];
-    for (int s = 0; s < 2; ++s) {
-      double q[5];
-      for (int v = 0; v < 5; ++v) q[v] = (double)qe[s][v];
-      double Dc[5], De;
-      tdiff<true>(A, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
-      tdiff<false>(A, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
-      T.reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
-    }
-    rotate(d, qs[0], ql);
-    rotate(d, qs[1], qr);
-  }
+  if (active) final_states<D>(A, b, step_consts(A, b), e, ql, qr, &T.reverts);
   RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
   if (active) {
     T.calls = 1;
@@ -1368,14 +1379,15 @@ __device__ __forceinline__ double kinetic(const double* m, double rho) {
 #endif
 }
 
+template <int NT = kBlock>
 __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* dst) {
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[NT / 64];
   for (int o = 32; o > 0; o >>= 1) s = vmax(s, __shfl_xor(s, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0];
-    for (int i = 1; i < kBlock / 64; ++i) m = vmax(m, red[i]);
+    for (int i = 1; i < NT / 64; ++i) m = vmax(m, red[i]);
     if (m > 0.0) max_bits(dst, m);
   }
   __syncthreads();  // red is free again when the block's next item reduces
@@ -1384,10 +1396,137 @@ __device__ __forceinline__ void block_max_atomic(double s, unsigned long long* d
 // ---------------------------------------------------------------------------
 // stage 7: conservative update, gravity corrector, dual-energy sync
 // ---------------------------------------------------------------------------
+// The stored state and the gravity of a valid cell (padded index id).
+struct CellIn {
+  double U0, Um[3], UE, Ue, g[3];
+};
+__device__ __forceinline__ CellIn load_cell(const StepArgs& A, const BoxDev& b, unsigned id) {
+  CellIn x;
+  const double* U = A.Uin + b.soff;
+  x.U0 = ldu(U, id);
+  x.Um[0] = ldu(U + b.sstride, id);
+  x.Um[1] = ldu(U + 2 * b.sstride, id);
+  x.Um[2] = ldu(U + 3 * b.sstride, id);
+  x.UE = ldu(U + 4 * b.sstride, id);
+  x.Ue = ldu(U + 5 * b.sstride, id);
+  const real* G = (const real*)A.grav + b.goff;
+  x.g[0] = (double)ldu(G, id);
+  x.g[1] = (double)ldu(G + b.gstride, id);
+  x.g[2] = (double)ldu(G + 2 * b.gstride, id);
+  return x;
+}
+
+// Flux differences D (rho, m, E, e: high minus low face, summed over the
+// directions x, y, z in that order) and the p div u sum Pi of a cell, from
+// the final states of its low and high faces (O9).
+__device__ __forceinline__ void flux_diff(const StepArgs& A, real ah, const God* gl, const God* gh,
+                                          double* D, double& Pi) {
+  Pi = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    real fl[8], fh[8];
+    final_flux(A, d, gl[d], ah, fl);
+    final_flux(A, d, gh[d], ah, fh);
+    for (int c = 0; c < 6; ++c) {
+      double dF = (double)fh[c] - (double)fl[c];
+      D[c] = (d == 0) ? dF : D[c] + dF;
+    }
+    double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
+    Pi = (d == 0) ? pd : Pi + pd;
+  }
+}
+
+struct CellCount {
+  unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
+};
+// Predictor (Step 2), gravity corrector and dual-energy sync (Step 6) of one
+// cell from its flux differences; stores the new state at padded index id
+// and returns its CFL speed (0 when no dt_next is asked for).
+__device__ __forceinline__ double update_apply(const StepArgs& A, const StepC& C, const BoxDev& b,
+                                               unsigned id, const CellIn& x, const double* D,
+                                               double Pi, CellCount& n) {
+  const double U0 = x.U0, UE = x.UE, Ue = x.Ue;
+  const double* Um = x.Um;
+  const double* g = x.g;
+  const double dt = C.dt, kk = C.k;
+  // predictor (Step 2)
+  const double s0 = U0 - kk * D[0];
+  double mh[3], sm[3];
+  for (int d = 0; d < 3; ++d) {
+    mh[d] = Um[d] - kk * D[1 + d];
+    sm[d] = mh[d] + (dt * U0) * g[d];
+  }
+  double sE;
+  if (A.grav_form == 2) {
+    // form 2 (Sec. 3.2): E changes by the kinetic energy the gravity
+    // momentum update causes, at the new density
+    sE = (UE - kk * D[4]) + (kinetic(sm, s0) - kinetic(mh, s0));
+  } else {
+    sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
+  }
+  double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
+  if (A.expansion) {
+    // expansion source of both energy equations (Sec. 2.2), predictor part
+    sE = sE + C.xo * Ue;
+    se = se + C.xo * Ue;
+  }
+  // corrector (Step 6), same g
+  double nm[3];
+  for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
+  double nE;
+  if (A.grav_form == 2) {
+    nE = sE + (kinetic(nm, s0) - kinetic(sm, s0));
+  } else {
+    nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
+                            (sm[2] - Um[2]) * g[2]);
+  }
+  double ne = se;
+  if (A.expansion) {
+    // time-centred expansion source: + (S* - S^n) dt / 2
+    const double cx = 0.5 * (C.xn * se - C.xo * Ue);
+    nE = nE + cx;
+    ne = ne + cx;
+  }
+  // dual-energy sync (Step 6)
+#if defined(NYX_PREC_MIXED)
+  const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) * rcp64(s0);
+#else
+  const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;
+#endif
+  if (nE - ke > A.eta * nE) {
+    ne = nE - ke;
+  } else {
+    nE = ne + ke;
+    n.nsync += 1;
+  }
+  double* O = A.Uout + b.soff;
+  stu(O, id, s0);
+  stu(O + b.sstride, id, nm[0]);
+  stu(O + 2 * b.sstride, id, nm[1]);
+  stu(O + 3 * b.sstride, id, nm[2]);
+  stu(O + 4 * b.sstride, id, nE);
+  stu(O + 5 * b.sstride, id, ne);
+  bool fin = isfinite(s0) && isfinite(nm[0]) && isfinite(nm[1]) && isfinite(nm[2]) &&
+             isfinite(nE) && isfinite(ne);
+  n.nnf += fin ? 0 : 1;
+  n.nnd += s0 <= 0.0 ? 1 : 0;
+  n.nne += ne <= 0.0 ? 1 : 0;
+  return A.dt_next ? cell_speed(A, s0, nm[0], nm[1], nm[2], ne, A.a_new) : 0.0;
+}
+
+template <int NT = kBlock>
+__device__ __forceinline__ void count_cells(const StepArgs& A, const CellCount& n) {
+  if (A.stats) {
+    count<NT>(A, kSyncEfromE, n.nsync);
+    count<NT>(A, kNonfinite, n.nnf);
+    count<NT>(A, kNegDens, n.nnd);
+    count<NT>(A, kNegEint, n.nne);
+  }
+}
+
 __device__ __forceinline__ void update_body(const StepArgs& A, const Item& it) {
   Loc L = locate(A, kStUpdate, kSpaceV, it);
   const BoxDev& b = *L.bd;
-  unsigned nsync = 0, nnf = 0, nnd = 0, nne = 0;
+  CellCount n;
   double smax = 0.0;
   if (L.idx < b.V) {
     int vc[3];
@@ -1397,7 +1536,6 @@ __device__ __forceinline__ void update_body(const StepArgs& A, const Item& it) {
     const unsigned e = ((unsigned)(k + 1) * (unsigned)b.ey + (unsigned)(j + 1)) * (unsigned)b.ex +
                        (unsigned)(i + 1);
     const real* G2 = (const real*)A.work + b.w_f2;
-    const real ah = (real)C.a_h;
     const unsigned id = ((unsigned)(k + b.ng) * (unsigned)b.py + (unsigned)(j + b.ng)) *
                             (unsigned)b.px + (unsigned)(i + b.ng);
     // every load of the cell is issued before any arithmetic
@@ -1407,102 +1545,166 @@ __device__ __forceinline__ void update_body(const StepArgs& A, const Item& it) {
       gl[d] = ld_god(G, b.E, e);
       gh[d] = ld_god(G + (long long)e_stride(b, d), b.E, e);
     }
-    const double* U = A.Uin + b.soff;
-    const double U0 = ldu(U, id);
-    const double Um[3] = {ldu(U + b.sstride, id), ldu(U + 2 * b.sstride, id),
-                          ldu(U + 3 * b.sstride, id)};
-    const double UE = ldu(U + 4 * b.sstride, id), Ue = ldu(U + 5 * b.sstride, id);
-    const real* G = (const real*)A.grav + b.goff;
-    const double g[3] = {(double)ldu(G, id), (double)ldu(G + b.gstride, id),
-                         (double)ldu(G + 2 * b.gstride, id)};
-    double D[6];
-    double Pi = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      real fl[8], fh[8];
-      final_flux(A, d, gl[d], ah, fl);
-      final_flux(A, d, gh[d], ah, fh);
-      for (int c = 0; c < 6; ++c) {
-        double dF = (double)fh[c] - (double)fl[c];
-        D[c] = (d == 0) ? dF : D[c] + dF;
-      }
-      double pd = (0.5 * ((double)fh[6] + (double)fl[6])) * ((double)fh[7] - (double)fl[7]);
-      Pi = (d == 0) ? pd : Pi + pd;
-    }
-    const double dt = C.dt, kk = C.k;
-    // predictor (Step 2)
-    const double s0 = U0 - kk * D[0];
-    double mh[3], sm[3];
-    for (int d = 0; d < 3; ++d) {
-      mh[d] = Um[d] - kk * D[1 + d];
-      sm[d] = mh[d] + (dt * U0) * g[d];
-    }
-    double sE;
-    if (A.grav_form == 2) {
-      // form 2 (Sec. 3.2): E changes by the kinetic energy the gravity
-      // momentum update causes, at the new density
-      sE = (UE - kk * D[4]) + (kinetic(sm, s0) - kinetic(mh, s0));
-    } else {
-      sE = (UE - kk * D[4]) + dt * ((Um[0] * g[0] + Um[1] * g[1]) + Um[2] * g[2]);
-    }
-    double se = (Ue - kk * D[5]) - (kk * C.a_h) * Pi;
-    if (A.expansion) {
-      // expansion source of both energy equations (Sec. 2.2), predictor part
-      sE = sE + C.xo * Ue;
-      se = se + C.xo * Ue;
-    }
-    // corrector (Step 6), same g
-    double nm[3];
-    for (int d = 0; d < 3; ++d) nm[d] = sm[d] + ((0.5 * dt) * (s0 - U0)) * g[d];
-    double nE;
-    if (A.grav_form == 2) {
-      nE = sE + (kinetic(nm, s0) - kinetic(sm, s0));
-    } else {
-      nE = sE + (0.5 * dt) * (((sm[0] - Um[0]) * g[0] + (sm[1] - Um[1]) * g[1]) +
-                              (sm[2] - Um[2]) * g[2]);
-    }
-    double ne = se;
-    if (A.expansion) {
-      // time-centred expansion source: + (S* - S^n) dt / 2
-      const double cx = 0.5 * (C.xn * se - C.xo * Ue);
-      nE = nE + cx;
-      ne = ne + cx;
-    }
-    // dual-energy sync (Step 6)
-#if defined(NYX_PREC_MIXED)
-    const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) * rcp64(s0);
-#else
-    const double ke = (0.5 * ((nm[0] * nm[0] + nm[1] * nm[1]) + nm[2] * nm[2])) / s0;
-#endif
-    if (nE - ke > A.eta * nE) {
-      ne = nE - ke;
-    } else {
-      nE = ne + ke;
-      nsync = 1;
-    }
-    double* O = A.Uout + b.soff;
-    stu(O, id, s0);
-    stu(O + b.sstride, id, nm[0]);
-    stu(O + 2 * b.sstride, id, nm[1]);
-    stu(O + 3 * b.sstride, id, nm[2]);
-    stu(O + 4 * b.sstride, id, nE);
-    stu(O + 5 * b.sstride, id, ne);
-    bool fin = isfinite(s0) && isfinite(nm[0]) && isfinite(nm[1]) && isfinite(nm[2]) &&
-               isfinite(nE) && isfinite(ne);
-    nnf = fin ? 0 : 1;
-    nnd = s0 <= 0.0 ? 1 : 0;
-    nne = ne <= 0.0 ? 1 : 0;
-    if (A.dt_next) smax = cell_speed(A, s0, nm[0], nm[1], nm[2], ne, A.a_new);
+    const CellIn x = load_cell(A, b, id);
+    double D[6], Pi;
+    flux_diff(A, (real)C.a_h, gl, gh, D, Pi);
+    smax = update_apply(A, C, b, id, x, D, Pi, n);
   }
-  if (A.stats) {
-    count(A, kSyncEfromE, nsync);
-    count(A, kNonfinite, nnf);
-    count(A, kNegDens, nnd);
-    count(A, kNegEint, nne);
-  }
+  count_cells(A, n);
   if (A.dt_next) block_max_atomic(smax, A.smax + b.gidx);
 }
 __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
   update_body(A, launch_item(A, kStUpdate));
+}
+
+// ---------------------------------------------------------------------------
+// stages 6 and 7 fused (plain solver, no harvest).  A workgroup takes a tile
+// of TX x TY cell columns of a box and marches up the box in z.  Per plane it
+// solves the low x- and y-faces of its cells and each cell's high z-face,
+// and also the x-faces past the tile's last column and the y-faces past its
+// last row (solved again by the neighbouring tile unless they bound the box;
+// only the tile that owns a face counts it).  The x- and y-face states meet
+// in LDS, the z-face state stays in registers for the next plane, and each
+// cell is updated as soon as its six faces are known: the final face states
+// never reach HBM.  Every face and every cell runs the code of the staged
+// riem2 and update kernels, so the new state, the counters and dt_next are
+// those of the staged launches bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int kFinXs = kFinBlock + kFinBlock / 2;  // x-face slots: TY (TX + 1), TX >= 2
+constexpr int kFinYs = kFinBlock + 64;             // y-face slots: (TY + 1) TX, TX <= 64
+
+__device__ __forceinline__ void lds_put(real* L, int stride, int slot, const God& g) {
+  L[slot] = g.r;
+  L[stride + slot] = g.u;
+  L[2 * stride + slot] = g.v;
+  L[3 * stride + slot] = g.w;
+  L[4 * stride + slot] = g.p;
+}
+__device__ __forceinline__ God lds_get(const real* L, int stride, int slot) {
+  return God{L[slot], L[stride + slot], L[2 * stride + slot], L[3 * stride + slot],
+             L[4 * stride + slot]};
+}
+
+// The final face at E-index e in direction D when `on`, as the staged riem2
+// stores it (real); counted in T when `own`.
+template <int D>
+__device__ __forceinline__ God final_face(const StepArgs& A, const BoxDev& b, const StepC& C,
+                                          bool on, bool own, unsigned e, Tally& T) {
+  double ql[5], qr[5];
+  unsigned rv = 0;
+  if (on) final_states<D>(A, b, C, e, ql, qr, &rv);
+  const RiemannOut g = solve<false>(A, on, ql, qr, nullptr, &T.used, &T.fb);
+  God o{};
+  if (on) {
+    o = God{(real)g.r, (real)g.u, (real)g.v, (real)g.w, (real)g.p};
+    if (own) {
+      T.calls += 1;
+      T.iters += g.iters;
+      T.reverts += rv;
+    }
+  }
+  return o;
+}
+
+// Waves per SIMD k_final is compiled for: two workgroups per CU in the mixed
+// build (128 VGPRs, no spill); the FP64 build would spill at that count.
+#if defined(NYX_PREC_MIXED)
+constexpr int kFinWaves = 4;
+#else
+constexpr int kFinWaves = 2;
+#endif
+__global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
+  __shared__ real fx[5 * kFinXs];
+  __shared__ real fy[5 * kFinYs];
+  // box and tile of the workgroup (tiles numbered XCD-contiguously)
+  const int lin = (int)xcd_linear_block(true);
+  const int* pre = A.prefix[kSpaceT];
+  int lo = 0, hi = A.nb;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= lin) lo = mid;
+    else hi = mid;
+  }
+  const BoxDev& b = A.table[lo];
+  const StepC& C = step_consts(A, b);
+  const int TX = b.tx, TY = b.ty;
+  const int tile = lin - pre[lo];
+  const int tyi = tile / b.ntx;
+  const int i0 = (tile - tyi * b.ntx) * TX, j0 = tyi * TY;
+  const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
+  const int t = (int)threadIdx.x;
+  const int tj = t / TX, ti = t - tj * TX;
+  const bool lane = t < TX * TY;
+  const int i = i0 + ti, j = j0 + tj;
+  const bool cell = lane && i < nx && j < ny;
+  const bool xon = lane && i <= nx && j < ny;  // the x-face below column i (i = nx: the box's last)
+  const bool yon = lane && i < nx && j <= ny;
+  // faces past the tile: x-faces at i0 + TX of rows j0 + t (threads [0, TY)),
+  // y-faces at j0 + TY of columns i0 + t - yo (threads [yo, yo + TX)); yo is
+  // a multiple of 64, so each wavefront solves one direction
+  const int yo = (TY + 63) & ~63;
+  const bool xe = t < TY && i0 + TX <= nx && j0 + t < ny;
+  const bool ye = t >= yo && t < yo + TX && j0 + TY <= ny && i0 + (t - yo) < nx;
+  const bool xe_own = i0 + TX == nx, ye_own = j0 + TY == ny;
+  const unsigned ex = (unsigned)b.ex, exy = (unsigned)b.ex * (unsigned)b.ey;
+  const unsigned pxy = (unsigned)b.px * (unsigned)b.py;
+  // E-indices at plane k = 0 (cell (i, j, 0) is E-cell (i + 1, j + 1, 1));
+  // lanes without the face never use theirs
+  unsigned e = exy + (unsigned)(j + 1) * ex + (unsigned)(i + 1);
+  unsigned exe = exy + (unsigned)(j0 + t + 1) * ex + (unsigned)(i0 + TX + 1);
+  unsigned eye = exy + (unsigned)(j0 + TY + 1) * ex + (unsigned)(i0 + (t - yo) + 1);
+  unsigned id = (unsigned)b.ng * pxy + (unsigned)(j + b.ng) * (unsigned)b.px + (unsigned)(i + b.ng);
+  const real ah = (real)C.a_h;
+  Tally T;
+  CellCount n;
+  double smax = 0.0;
+  God zl = final_face<2>(A, b, C, cell, true, e, T);  // below the first plane
+  for (int k = 0; k < nz; ++k) {
+    {
+      const God g = final_face<0>(A, b, C, xon, true, e, T);
+      if (xon) lds_put(fx, kFinXs, tj * (TX + 1) + ti, g);
+    }
+    {
+      const God g = final_face<1>(A, b, C, yon, true, e, T);
+      if (yon) lds_put(fy, kFinYs, tj * TX + ti, g);
+    }
+    if (t < yo) {
+      const God g = final_face<0>(A, b, C, xe, xe_own, exe, T);
+      if (xe) lds_put(fx, kFinXs, t * (TX + 1) + TX, g);
+    } else if (t < yo + TX) {
+      const God g = final_face<1>(A, b, C, ye, ye_own, eye, T);
+      if (ye) lds_put(fy, kFinYs, TY * TX + (t - yo), g);
+    }
+    const God zh = final_face<2>(A, b, C, cell, true, e + exy, T);
+    CellIn x{};
+    if (cell) x = load_cell(A, b, id);
+    __syncthreads();
+    if (cell) {
+      const God gl[3] = {lds_get(fx, kFinXs, tj * (TX + 1) + ti), lds_get(fy, kFinYs, tj * TX + ti),
+                         zl};
+      const God gh[3] = {lds_get(fx, kFinXs, tj * (TX + 1) + ti + 1),
+                         lds_get(fy, kFinYs, (tj + 1) * TX + ti), zh};
+      double D[6], Pi;
+      flux_diff(A, ah, gl, gh, D, Pi);
+      smax = vmax(smax, update_apply(A, C, b, id, x, D, Pi, n));
+    }
+    zl = zh;
+    e += exy;
+    exe += exy;
+    eye += exy;
+    id += pxy;
+    // the face slots are free for the next plane (two LDS buffers with one
+    // barrier per plane measured slower: 14.3 against 13.7 ms on the stress
+    // patches)
+    __syncthreads();
+  }
+  if (A.stats) {
+    count<kFinBlock>(A, kRiemannCalls, T.calls);
+    count<kFinBlock>(A, kRiemannIters, T.iters);
+    count<kFinBlock>(A, kTransReverts, T.reverts);
+  }
+  count_cells<kFinBlock>(A, n);
+  if (A.dt_next) block_max_atomic<kFinBlock>(smax, A.smax + b.gidx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1571,6 +1773,13 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   if (learned(1)) hipLaunchKernelGGL(k_riem1<kHasLearned>, dim3(a.nblocks[kSpaceE], 6), blk, 0, s, a);
   else hipLaunchKernelGGL(k_riem1<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   mark(5);
+  if (a.fuse_final && !learned(2) && !a.harvest) {
+    // riem2 and update as one launch; its time is stage 6's, stage 7's is 0
+    hipLaunchKernelGGL(k_final, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
+    mark(6);
+    mark(7);
+    return hipGetLastError();
+  }
   if (learned(2)) hipLaunchKernelGGL(k_riem2<kHasLearned ? 1 : 0>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   else if (a.harvest) hipLaunchKernelGGL(k_riem2<2>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
   else hipLaunchKernelGGL(k_riem2<0>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);

@@ -99,7 +99,7 @@ __global__ void k_prologue(StepArgs A, int nbox, StepC* consts, BoxDev* single_d
   const BoxDev& b = single_dst ? A.single : A.table[i];
   if (single_dst && i == 0) {
     *single_dst = A.single;
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < kSpaces; ++s) {
       prefix_dst[2 * s] = 0;
       prefix_dst[2 * s + 1] = A.nblocks[s];
     }

@@ -127,9 +127,10 @@ def test_persistent_level4096_equals_staged(nyx):
     assert np.array_equal(s_dts[1], p_dts[1])
     assert s_st == p_st
     mode, ms = plan.autotune_mode(state, grav, dt, 0.25, 0.2505, p_state, reps=2)
-    print("level4096 mixed step: staged %.3f ms, persistent %.3f ms, kept mode %d"
-          % (ms[0], ms[1], mode))
-    assert mode in (nyx.NYX_LAUNCH_STAGED, nyx.NYX_LAUNCH_PERSISTENT) and ms[0] > 0 and ms[1] > 0
+    print("level4096 mixed step: staged %.3f ms, persistent %.3f ms, fused %.3f ms, kept mode %d"
+          % (ms[0], ms[1], ms[2], mode))
+    assert mode in (nyx.NYX_LAUNCH_STAGED, nyx.NYX_LAUNCH_PERSISTENT, nyx.NYX_LAUNCH_FUSED)
+    assert min(ms) > 0
     plan.close()
 
 
