@@ -684,6 +684,47 @@ __device__ __forceinline__ RiemannOut ts_finish(const TwoShock& t, const TwoShoc
                        ustar, p, qL, qR);
 }
 
+// The same star state and sample for the plain solver, with the reciprocal
+// and star density of the sampled (upwind) side only, both sides when u* = 0:
+// the same expressions as ts_finish and sample_upwind, so the same Godunov
+// state, two reciprocal estimates fewer per face.  The star density of the
+// side not sampled is returned as 0.
+__device__ __forceinline__ RiemannOut ts_finish_upwind(const TwoShock& t, const TwoShockEval& e,
+                                                       double p, const double* qL,
+                                                       const double* qR) {
+  const double ustar = (e.usL * e.zR + e.usR * e.zL) * rcp64(e.zL + e.zR);
+  const bool left = !(ustar < 0.0);  // u* > 0 samples the left wave, u* = 0 both
+  const double r = left ? t.rl : t.rr, pk = left ? t.pl : t.pr, w = left ? e.wL : e.wR;
+  const double ir = rcp_est(r);
+  const double D = ir - (p - pk) * (w * w);
+  const double rs = rcp_est(D);
+  double s1[3];
+  sample_side(t.gam, r, ir, left ? t.ul : -t.ur, pk, left ? e.XL : e.XR, w, D, rs,
+              left ? ustar : -ustar, p, s1);
+  RiemannOut o;
+  if (ustar != 0.0) {
+    o.r = s1[0]; o.u = left ? s1[1] : -s1[1]; o.p = s1[2];
+    o.v = left ? qL[2] : qR[2];
+    o.w = left ? qL[3] : qR[3];
+  } else {
+    const double irr = rcp_est(t.rr);
+    const double DR = irr - (p - t.pr) * (e.wR * e.wR);
+    double s2[3];
+    sample_side(t.gam, t.rr, irr, -t.ur, t.pr, e.XR, e.wR, DR, rcp_est(DR), -ustar, p, s2);
+    o.r = 0.5 * (s1[0] + s2[0]);
+    o.u = 0.5 * (s1[1] - s2[1]);
+    o.p = 0.5 * (s1[2] + s2[2]);
+    o.v = 0.5 * (qL[2] + qR[2]);
+    o.w = 0.5 * (qL[3] + qR[3]);
+  }
+  o.pstar = p;
+  o.ustar = ustar;
+  o.rsL = left ? rs : 0.0;
+  o.rsR = left ? 0.0 : rs;
+  o.iters = 0;
+  return o;
+}
+
 // Linearised solver of this build: the acoustic star state (refined
 // reciprocals), linearised star densities rho*_K = rho_K + (p* - p_K) rho_K^2
 // / C_K, and the same upwind sample as the two-shock solver.
@@ -705,6 +746,9 @@ __device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double*
   return o;
 }
 
+// BOTH: the star densities of both sides (training records); otherwise the
+// sampled side's only
+template <bool BOTH = false>
 __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
                                                 const double* qR) {
   const TwoShock t = ts_setup(A, qL, qR);
@@ -727,7 +771,8 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
     p = pn;
     if (conv) break;
   }
-  RiemannOut o = ts_finish(t, ts_eval_est(t, p), p, qL, qR);
+  const TwoShockEval e = ts_eval_est(t, p);
+  RiemannOut o = BOTH ? ts_finish(t, e, p, qL, qR) : ts_finish_upwind(t, e, p, qL, qR);
   o.iters = it;
   return o;
 }
@@ -771,6 +816,9 @@ __device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const dou
 }
 #else
 
+// BOTH is the mixed build's choice of star densities; this build always
+// computes both
+template <bool BOTH = true>
 __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
                                                 const double* qR) {
   const double gam = A.gamma;
@@ -977,7 +1025,7 @@ constexpr bool kHasLearned = false;
 // Riemann solve of one face of the wave.  LEARNED: every lane of the
 // wavefront must call it (the network runs wave-wide); `active` marks lanes
 // with a real face.  Returns the solution for active lanes.
-template <bool LEARNED>
+template <bool LEARNED, bool BOTH = false>
 __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, const double* qL,
                                             const double* qR, __bf16* lds, unsigned* used,
                                             unsigned* fallback) {
@@ -1006,7 +1054,7 @@ __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, cons
     return g;
   }
 #endif
-  if (active) g = A.linear_riemann ? lin_solve(A, qL, qR) : two_shock(A, qL, qR);
+  if (active) g = A.linear_riemann ? lin_solve(A, qL, qR) : two_shock<BOTH>(A, qL, qR);
   return g;
 }
 
@@ -1289,7 +1337,7 @@ __device__ __forceinline__ void riem2_dir(const StepArgs& A, const BoxDev& b, un
                       c[t2] <= b.n[t2];
   double ql[5], qr[5];
   if (active) final_states<D>(A, b, step_consts(A, b), e, ql, qr, &T.reverts);
-  RiemannOut g = solve<LEARNED>(A, active, ql, qr, lds, &T.used, &T.fb);
+  RiemannOut g = solve<LEARNED, MODE == 2>(A, active, ql, qr, lds, &T.used, &T.fb);
   if (active) {
     T.calls = 1;
     T.iters = g.iters;
