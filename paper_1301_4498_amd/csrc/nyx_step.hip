@@ -235,6 +235,24 @@ __global__ __launch_bounds__(kBlock) void k_flat(StepArgs A) { flat_body(A, laun
 // ---------------------------------------------------------------------------
 // stage 3: PPM (O3) and characteristic tracing (O4)
 // ---------------------------------------------------------------------------
+#if defined(NYX_PREC_MIXED)
+// The limited slope without the branch: with s the sign of d2 = q(j+1) -
+// q(j-1), min(|dc|, 2|dl|, 2|dr|) = 2 min(|d2|/4, s dl, s dr) when dl dr > 0
+// (then dl, dr and d2 share their sign), and that minimum is <= 0 otherwise,
+// so clamping it at 0 gives the limiter's zero slope.  Scaling by 2 and 1/4
+// is exact, so the value is the branchy form's (up to the sign of a zero
+// slope, and slopes below the FP32 normal range).
+__device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
+  const real d2 = qp1 - qm1;
+  const real dr = qp1 - q0;
+  const real dl = q0 - qm1;
+  const unsigned sg = __float_as_uint(d2) & 0x80000000u;
+  const real sdl = __uint_as_float(__float_as_uint(dl) ^ sg);
+  const real sdr = __uint_as_float(__float_as_uint(dr) ^ sg);
+  const real m = (real)2 * fmaxf(fminf(fminf((real)0.25 * fabsf(d2), sdl), sdr), (real)0);
+  return __uint_as_float(__float_as_uint(m) | sg);
+}
+#else
 // Under dr dl > 0 neither dl nor dr is NaN, so fmin (one instruction) takes
 // the same value as the compare-and-select minimum, infinite slopes included.
 __device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
@@ -247,6 +265,7 @@ __device__ __forceinline__ real lim_slope(real qm1, real q0, real qp1) {
   }
   return (real)0;
 }
+#endif
 // interface value between cells a and b from their limited slopes sa, sb
 __device__ __forceinline__ real ppm_face(real qa, real qb, real sa, real sb) {
 #if defined(NYX_PREC_MIXED)
