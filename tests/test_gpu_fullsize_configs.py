@@ -3,6 +3,9 @@ count, and the learned flux on a fresh 256^3 box, each in the launch
 configuration bench.py times (batched plans, device-resident dt, autotuned
 launch orders).
 
+Launch orders and (where bench.py chooses one) the launch mode come from the
+plan's autotuners, as in bench.py.
+
   * 4096-box level (edges from {16, 24, 32, 48, 64}): FP64 for 2 steps with
     per-box dt, then FP32-mixed with that dt sequence; 20 sampled boxes (4
     per x-edge length, every other edge random) against the oracle box by
@@ -85,8 +88,11 @@ def test_level4096_sampled_boxes_against_oracle(nyx):
         if prec == "fp64":
             plan.estimate_dt(bufs[0], a[0], 0.5, dt_seq[0])
         plan.autotune(bufs[0], G, dt_seq[0], a[0], a[1], bufs[1], reps=1)
-        print("level4096 %s: %d boxes in %d group(s), tuning %s"
-              % (prec, len(boxes), plan.num_groups, plan.tuning()), flush=True)
+        if prec == "mixed":
+            # the launch mode bench.py times (staged, persistent or fused)
+            plan.autotune_mode(bufs[0], G, dt_seq[0], a[0], a[1], bufs[1], reps=1)
+        print("level4096 %s: %d boxes in %d group(s), tuning %s, launch mode %d"
+              % (prec, len(boxes), plan.num_groups, plan.tuning(), plan.launch_mode), flush=True)
         for k in range(steps):
             plan.step(bufs[k % 2], G, dt_seq[k], a[k], a[k + 1], bufs[(k + 1) % 2],
                       dt_next=dt_seq[k + 1] if prec == "fp64" else None)
@@ -153,6 +159,9 @@ def test_box256_ten_steps_windows(nyx):
         if prec == "fp64":
             plan.estimate_dt(U[0], w.a0, 0.5, dts[0:1])
         plan.autotune(U[0], G, dts[0:1], a[0], a[1], U[1], reps=1)
+        plan.autotune_mode(U[0], G, dts[0:1], a[0], a[1], U[1], reps=1)
+        print("box256 %s: tuning %s, launch mode %d" % (prec, plan.tuning(), plan.launch_mode),
+              flush=True)
         for k in range(steps):
             plan.step(U[k % 2], G, dts[k:k + 1], a[k], a[k + 1], U[(k + 1) % 2],
                       dt_next=dts[k + 1:k + 2] if prec == "fp64" else None)
