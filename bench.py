@@ -381,9 +381,10 @@ def box256_leg(nyx, torch, synth, steps, warmup, log, n=256):
     for f, v in res.items():
         v["rho_l1_vs_fp64"] = float(np.abs(v["rho"] - res["fp64"]["rho"]).sum() /
                                     np.abs(res["fp64"]["rho"]).sum())
-        out["forms"][f] = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage",
-                                             "mean_riemann_iters", "finite", "rho_l1_vs_fp64",
-                                             "tuning", "roofline", "hbm_step")}
+        out["forms"][f] = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "launch_mode",
+                                             "mode_step_ms", "stage", "mean_riemann_iters",
+                                             "finite", "rho_l1_vs_fp64", "tuning", "roofline",
+                                             "hbm_step")}
     return out, w
 
 
@@ -408,8 +409,8 @@ def learned256_leg(nyx, torch, synth, learn, flux, steps, warmup, log, n=256):
         res[f] = run_box(nyx, torch, w, prm, steps, warmup, table)
         log("learned256 %s: %.3e zone-updates/s" % (f, res[f]["zone_updates_per_s"]))
     for f, v in res.items():
-        r = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "stage", "mean_riemann_iters",
-                               "finite")}
+        r = {k: v[k] for k in ("zone_updates_per_s", "ms_per_step", "launch_mode", "stage",
+                               "mean_riemann_iters", "finite")}
         for ref in ("fp64", "mixed"):
             r["rho_l1_vs_" + ref] = float(np.abs(v["rho"] - res[ref]["rho"]).sum() /
                                           np.abs(res[ref]["rho"]).sum())

@@ -12,8 +12,10 @@ namespace nyx {
 constexpr int kBlock = 256;  // threads per block: 4 wavefronts of 64
 // Threads per workgroup of the fused final-stage kernel (8 wavefronts): a
 // tile of TX x TY cell columns of a box, TX = min(n_x, 64), TY = min(n_y,
-// kFinBlock / TX).
+// kFinBlock / TX), over a chunk of at most kFinPlanes planes in z (tall
+// boxes are cut into several chunks so that the launch has enough tiles).
 constexpr int kFinBlock = 512;
+constexpr int kFinPlanes = 64;
 // Stored per face: the Godunov state (rho_g, u_g normal, v_g, w_g transverse,
 // p_g) in the face's rotated frame; every flux is recomputed from it.
 constexpr int kGod = 5;
@@ -51,7 +53,8 @@ struct BoxDev {
   FastDiv dz[3];           // per Space: number of planes
   unsigned sy[3];          // per Space: rows per plane
   unsigned sc[3];          // per Space: cell count (< 2^31)
-  int tx, ty, ntx, ntiles; // fused final stage: tile shape, tiles along x, tiles
+  int tx, ty, ntx, nty;    // fused final stage: tile shape, tiles along x and y,
+  int ntiles, pad2_;       // tiles in all (z chunks of kFinPlanes planes included)
 };
 
 // Stage-array element count for a box (before alignment padding).
@@ -103,7 +106,8 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   d.tx = b.n[0] < 64 ? b.n[0] : 64;
   d.ty = b.n[1] < kFinBlock / d.tx ? b.n[1] : kFinBlock / d.tx;
   d.ntx = (b.n[0] + d.tx - 1) / d.tx;
-  d.ntiles = d.ntx * ((b.n[1] + d.ty - 1) / d.ty);
+  d.nty = (b.n[1] + d.ty - 1) / d.ty;
+  d.ntiles = d.ntx * d.nty * ((b.n[2] + kFinPlanes - 1) / kFinPlanes);
   if (out) *out = d;
   return o;
 }

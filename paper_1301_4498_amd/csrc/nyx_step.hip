@@ -1626,7 +1626,9 @@ __global__ __launch_bounds__(kBlock) void k_update(StepArgs A) {
 
 // ---------------------------------------------------------------------------
 // stages 6 and 7 fused (plain solver, no harvest).  A workgroup takes a tile
-// of TX x TY cell columns of a box and marches up the box in z.  Per plane it
+// of TX x TY cell columns of a box and marches up one chunk of at most
+// kFinPlanes planes in z (a chunk above the first solves its bottom z-face
+// again: the chunk below owns it).  Per plane it
 // solves the low x- and y-faces of its cells and each cell's high z-face,
 // and also the x-faces past the tile's last column and the y-faces past its
 // last row (solved again by the neighbouring tile unless they bound the box;
@@ -1696,9 +1698,13 @@ __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
   const StepC& C = step_consts(A, b);
   const int TX = b.tx, TY = b.ty;
   const int tile = lin - pre[lo];
-  const int tyi = tile / b.ntx;
-  const int i0 = (tile - tyi * b.ntx) * TX, j0 = tyi * TY;
-  const int nx = b.n[0], ny = b.n[1], nz = b.n[2];
+  const int txy = b.ntx * b.nty;
+  const int tzi = tile / txy;
+  const int tyi = (tile - tzi * txy) / b.ntx;
+  const int i0 = (tile - tzi * txy - tyi * b.ntx) * TX, j0 = tyi * TY;
+  const int nx = b.n[0], ny = b.n[1];
+  const int k0 = tzi * kFinPlanes;
+  const int k1 = b.n[2] < k0 + kFinPlanes ? b.n[2] : k0 + kFinPlanes;
   const int t = (int)threadIdx.x;
   const int tj = t / TX, ti = t - tj * TX;
   const bool lane = t < TX * TY;
@@ -1715,18 +1721,20 @@ __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
   const bool xe_own = i0 + TX == nx, ye_own = j0 + TY == ny;
   const unsigned ex = (unsigned)b.ex, exy = (unsigned)b.ex * (unsigned)b.ey;
   const unsigned pxy = (unsigned)b.px * (unsigned)b.py;
-  // E-indices at plane k = 0 (cell (i, j, 0) is E-cell (i + 1, j + 1, 1));
+  // E-indices at plane k0 (cell (i, j, k) is E-cell (i + 1, j + 1, k + 1));
   // lanes without the face never use theirs
-  unsigned e = exy + (unsigned)(j + 1) * ex + (unsigned)(i + 1);
-  unsigned exe = exy + (unsigned)(j0 + t + 1) * ex + (unsigned)(i0 + TX + 1);
-  unsigned eye = exy + (unsigned)(j0 + TY + 1) * ex + (unsigned)(i0 + (t - yo) + 1);
-  unsigned id = (unsigned)b.ng * pxy + (unsigned)(j + b.ng) * (unsigned)b.px + (unsigned)(i + b.ng);
+  const unsigned ez0 = (unsigned)(k0 + 1) * exy;
+  unsigned e = ez0 + (unsigned)(j + 1) * ex + (unsigned)(i + 1);
+  unsigned exe = ez0 + (unsigned)(j0 + t + 1) * ex + (unsigned)(i0 + TX + 1);
+  unsigned eye = ez0 + (unsigned)(j0 + TY + 1) * ex + (unsigned)(i0 + (t - yo) + 1);
+  unsigned id = (unsigned)(k0 + b.ng) * pxy + (unsigned)(j + b.ng) * (unsigned)b.px +
+                (unsigned)(i + b.ng);
   const real ah = (real)C.a_h;
   Tally T;
   CellCount n;
   double smax = 0.0;
-  God zl = final_face<2>(A, b, C, cell, true, e, T);  // below the first plane
-  for (int k = 0; k < nz; ++k) {
+  God zl = final_face<2>(A, b, C, cell, k0 == 0, e, T);  // below the first plane
+  for (int k = k0; k < k1; ++k) {
     {
       const God g = final_face<0>(A, b, C, xon, true, e, T);
       if (xon) lds_put(fx, kFinXs, tj * (TX + 1) + ti, g);

@@ -4,9 +4,9 @@ marching in z, the final face states kept in LDS and registers) against the
 staged launches through the C ABI.  Every face and cell runs the staged
 kernels' code, so the new state, the next dt and the counters must be equal
 bit for bit: on boxes whose tiles are partial in x and in y, narrow boxes (2
-cells across), several groups, in FP64 (also against the oracle) and in
-FP32-mixed, replayed from a captured HIP graph, and on the 512^3 stress
-domain as 512 patches of 64^3."""
+cells across), boxes cut into several z chunks, several groups, in FP64
+(also against the oracle) and in FP32-mixed, replayed from a captured HIP
+graph, and on the 512^3 stress domain as 512 patches of 64^3."""
 import numpy as np
 import pytest
 
@@ -16,11 +16,12 @@ from paper_1301_4498_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-# tiles are TX = min(nx, 64) by TY = min(ny, 512 / TX) columns: partial in x
-# (80, 130), partial in y (20 rows of 8, 48 rows of 32, 24 rows of 21), and
-# boxes 2 cells across in x or y
+# tiles are TX = min(nx, 64) by TY = min(ny, 512 / TX) columns over chunks of
+# at most 64 planes: partial in x (80, 130), partial in y (20 rows of 8, 48
+# rows of 32, 24 rows of 21), boxes 2 cells across in x or y, and boxes
+# taller than one chunk (130 = 64 + 64 + 2 planes)
 SHAPES = [(16, 24, 32), (80, 20, 8), (130, 10, 6), (24, 24, 24), (16, 48, 8), (2, 6, 4),
-          (6, 2, 4), (64, 64, 16)]
+          (6, 2, 4), (64, 64, 16), (10, 8, 130)]
 
 
 @pytest.fixture(scope="module")
