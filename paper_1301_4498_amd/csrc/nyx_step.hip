@@ -1307,10 +1307,14 @@ __device__ __forceinline__ unsigned face_hash(unsigned long long seed, int box, 
 // e - e_d and e; c[d] >= 1 and the transverse coordinates in [1, n]): both
 // cells' edge states corrected by the t1- and t2-differences of the stage-1
 // states, rotated into the face's frame.  Adds the reverts to *reverts.
-template <int D>
+// A cell's differences are the same for both of its d-faces, so a caller
+// walking faces along d carries them: CARRY = 1 stores the upper cell's
+// differences (Dc, De) in carry[6]; CARRY = 2 also takes the lower cell's
+// from it instead of loading and differencing its stage-1 states.
+template <int D, int CARRY = 0>
 __device__ __forceinline__ void final_states(const StepArgs& A, const BoxDev& b, const StepC& C,
                                              unsigned e, double* ql, double* qr,
-                                             unsigned* reverts) {
+                                             unsigned* reverts, double* carry = nullptr) {
   constexpr int d = D;
   constexpr int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
   const long long sdd = e_stride(b, d), s1 = e_stride(b, t1), s2 = e_stride(b, t2);
@@ -1325,6 +1329,7 @@ __device__ __forceinline__ void final_states(const StepArgs& A, const BoxDev& b,
     const long long sh = s == 0 ? -sdd : 0;  // cell shift in the bases, offset e
     const int side = s == 0 ? 1 : 0;
     for (int v = 0; v < 5; ++v) qe[s][v] = ldu(W + ((d * 2 + side) * 5 + v) * b.E + sh, e);
+    if (CARRY == 2 && s == 0) continue;
     ga[s][0] = ld_god(G1a + sh, b.E, e);
     ga[s][1] = ld_god(G1a + sh + s1, b.E, e);
     gb[s][0] = ld_god(G1b + sh, b.E, e);
@@ -1335,8 +1340,17 @@ __device__ __forceinline__ void final_states(const StepArgs& A, const BoxDev& b,
     double q[5];
     for (int v = 0; v < 5; ++v) q[v] = (double)qe[s][v];
     double Dc[5], De;
-    tdiff<true>(A, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
-    tdiff<false>(A, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
+    if (CARRY == 2 && s == 0) {
+      for (int c = 0; c < 5; ++c) Dc[c] = carry[c];
+      De = carry[5];
+    } else {
+      tdiff<true>(A, t1, ga[s][0], ga[s][1], Dc, De);   // t1-flux corrected by t2
+      tdiff<false>(A, t2, gb[s][0], gb[s][1], Dc, De);  // t2-flux corrected by t1
+    }
+    if (CARRY != 0 && s == 1) {
+      for (int c = 0; c < 5; ++c) carry[c] = Dc[c];
+      carry[5] = De;
+    }
     *reverts += trans_correct(A, q, Dc, De, C.kap2, qs[s]) ? 1u : 0u;
   }
   rotate(d, qs[0], ql);
@@ -1656,12 +1670,13 @@ __device__ __forceinline__ God lds_get(const real* L, int stride, int slot) {
 
 // The final face at E-index e in direction D when `on`, as the staged riem2
 // stores it (real); counted in T when `own`.
-template <int D>
+template <int D, int CARRY = 0>
 __device__ __forceinline__ God final_face(const StepArgs& A, const BoxDev& b, const StepC& C,
-                                          bool on, bool own, unsigned e, Tally& T) {
+                                          bool on, bool own, unsigned e, Tally& T,
+                                          double* carry = nullptr) {
   double ql[5], qr[5];
   unsigned rv = 0;
-  if (on) final_states<D>(A, b, C, e, ql, qr, &rv);
+  if (on) final_states<D, CARRY>(A, b, C, e, ql, qr, &rv, carry);
   const RiemannOut g = solve<false>(A, on, ql, qr, nullptr, &T.used, &T.fb);
   God o{};
   if (on) {
@@ -1733,7 +1748,10 @@ __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
   Tally T;
   CellCount n;
   double smax = 0.0;
-  God zl = final_face<2>(A, b, C, cell, k0 == 0, e, T);  // below the first plane
+  // the z-faces carry each cell's differences from the face below it to
+  // the face above
+  double zc[6];
+  God zl = final_face<2, 1>(A, b, C, cell, k0 == 0, e, T, zc);  // below the first plane
   for (int k = k0; k < k1; ++k) {
     {
       const God g = final_face<0>(A, b, C, xon, true, e, T);
@@ -1750,7 +1768,7 @@ __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
       const God g = final_face<1>(A, b, C, ye, ye_own, eye, T);
       if (ye) lds_put(fy, kFinYs, TY * TX + (t - yo), g);
     }
-    const God zh = final_face<2>(A, b, C, cell, true, e + exy, T);
+    const God zh = final_face<2, 2>(A, b, C, cell, true, e + exy, T, zc);
     CellIn x{};
     if (cell) x = load_cell(A, b, id);
     __syncthreads();
