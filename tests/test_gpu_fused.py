@@ -187,3 +187,34 @@ def test_fused_stress_patches_equal_staged(nyx):
     assert torch.equal(s_dn, f_dn)
     assert s_st == f_st
     plan.close()
+
+
+VARIANTS = {"plm": dict(recon=1), "linear": dict(riemann=2), "gravity_form2": dict(grav_energy_form=2),
+            "all_three": dict(recon=1, riemann=2, grav_energy_form=2), "gamma14_expansion": dict(gamma=1.4)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_fused_equals_staged_variants(nyx, prec, variant):
+    """The scheme variants of Sec. 3.2 (PLM, the linearised solver, energy
+    gravity form 2, all three, gamma = 1.4 with the expansion term) through
+    the fused final stage: bitwise the staged launches."""
+    import torch
+    prm = nyx.default_params(precision=nyx.NYX_FP64 if prec == "fp64" else nyx.NYX_MIXED,
+                             **VARIANTS[variant])
+    shapes = SHAPES[:4]
+    boxes, states, gravs, flat, gflat = _pack(nyx, shapes)
+    _, one = nyx.Batch.workspace_bytes(prm, boxes)
+    plan = nyx.Batch(prm, boxes, aligned_ws(one))
+    Ui = to_dev(flat)
+    G = to_dev(gflat, torch.float64 if prec == "fp64" else torch.float32)
+    dt = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+    plan.estimate_dt(Ui, 0.25, 0.5, dt)
+    a_list = [0.25, 0.2505, 0.251]
+    s_state, s_dts, s_st = _steps(nyx, torch, plan, Ui, G, dt, a_list, nyx.NYX_LAUNCH_STAGED)
+    f_state, f_dts, f_st = _steps(nyx, torch, plan, Ui, G, dt, a_list, nyx.NYX_LAUNCH_FUSED)
+    assert torch.equal(s_state, f_state)
+    for a, b in zip(s_dts, f_dts):
+        assert np.array_equal(a, b)
+    assert s_st == f_st
+    plan.close()
