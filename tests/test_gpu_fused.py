@@ -218,3 +218,31 @@ def test_fused_equals_staged_variants(nyx, prec, variant):
         assert np.array_equal(a, b)
     assert s_st == f_st
     plan.close()
+
+
+@pytest.mark.parametrize("stages", [3, 7])
+def test_fused_with_learned_flux(nyx, stages):
+    """The learned flux on stages 0-1 (the fused kernel runs the plain final
+    stage) and on all three (the final stage stays staged): the fused mode
+    gives the staged launches' bits, counters included."""
+    import torch
+    from paper_1301_4498_amd import learn
+    f = learn.LearnedFlux(seed=9)
+    f.pack()
+    prm = learn.learned_params(f, tol=1e-3, stages=stages)
+    boxes, states, gravs, flat, gflat = _pack(nyx, SHAPES[:4])
+    _, one = nyx.Batch.workspace_bytes(prm, boxes)
+    plan = nyx.Batch(prm, boxes, aligned_ws(one))
+    Ui = to_dev(flat)
+    G = to_dev(gflat, torch.float32)
+    dt = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+    plan.estimate_dt(Ui, 0.25, 0.5, dt)
+    a_list = [0.25, 0.2505, 0.251]
+    s_state, s_dts, s_st = _steps(nyx, torch, plan, Ui, G, dt, a_list, nyx.NYX_LAUNCH_STAGED)
+    f_state, f_dts, f_st = _steps(nyx, torch, plan, Ui, G, dt, a_list, nyx.NYX_LAUNCH_FUSED)
+    assert torch.equal(s_state, f_state)
+    for a, b in zip(s_dts, f_dts):
+        assert np.array_equal(a, b)
+    assert s_st == f_st
+    assert s_st["mlp_used"] + s_st["mlp_fallback"] > 0
+    plan.close()
