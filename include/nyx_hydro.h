@@ -232,17 +232,18 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  * NYX_LAUNCH_STAGED (the default): every stage of a group is its own launch
  * over all boxes of the group.  NYX_LAUNCH_PERSISTENT: the seven stages of a
  * group run as one launch of as many workgroups as the device keeps
- * resident at once; per stage, the work items (the blocks of the staged
- * launch) are taken from atomic queues, one per eighth of the stage's walk,
- * which the workgroups of one XCD drain first, and a grid barrier separates
- * the stages.  Each item runs the staged kernel's code, so every box's result
+ * resident at once; per stage, each workgroup first runs a static,
+ * contiguous share of the work items (the blocks of the staged launch), then
+ * takes the rest in chunks from atomic queues, one per XCD's range, which the
+ * workgroups of that XCD drain first; a two-level grid barrier (per XCD, then
+ * across XCDs) separates the stages.  Each item runs the staged kernel's code, so every box's result
  * is bit for bit that of the staged launches.  The barrier gives up after 5 s
  * of wall clock if some workgroup never became resident (another kernel
  * holding the device); the launch then ends early, and
  * nyx_batch_persistent_aborted reports it.  Available for plain steps in
  * both precisions and for the learned flux on all three stages; a plan that
  * harvests training records runs staged.  Stage timing (nyx_profile_*) sees
- * only staged launches.
+ * only the staged and fused launches.
  * NYX_LAUNCH_FUSED: staged launches, except that the last two stages (the
  * final Riemann solves of Sec. 3.2 and the conservative update with the
  * gravity corrector and the dual-energy sync of Sec. 3.6, Steps 2 and 6)
