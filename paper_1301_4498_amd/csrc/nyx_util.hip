@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full,
   int gc[3];
   ghost_coords(b, (unsigned)id, gc);
   const int i = gc[0], j = gc[1], k = gc[2];
-  long long src;
+  long long src, ss = b.sstride;  // the source cell and its box's component stride
   if (mode == 0) {
     const int si = ((i % b.n[0]) + b.n[0]) % b.n[0];
     const int sj = ((j % b.n[1]) + b.n[1]) % b.n[1];
@@ -232,6 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full,
     const BoxDev& sb = full[(sbz * gy + sby) * gx + sbx];
     const int si = X - sbx * b.n[0], sj = Y - sby * b.n[1], sk = Z - sbz * b.n[2];
     src = sb.soff + ((long long)(sk + sb.ng) * sb.py + (sj + sb.ng)) * sb.px + (si + sb.ng);
+    ss = sb.sstride;
   }
   const long long dst = b.soff + ((long long)(k + b.ng) * b.py + (j + b.ng)) * b.px + (i + b.ng);
   const long long cs = b.sstride;
@@ -240,11 +241,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs A, const BoxDev* full,
     // are valid cells, destinations ghost cells, so no store feeds a load)
     double v[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = state[src + c * cs];
+    for (int c = 0; c < 6; ++c) v[c] = state[src + c * ss];
 #pragma unroll
     for (int c = 0; c < 6; ++c) state[dst + c * cs] = v[c];
   } else {
-    for (int c = 0; c < ncomp; ++c) state[dst + c * cs] = state[src + c * cs];
+    for (int c = 0; c < ncomp; ++c) state[dst + c * cs] = state[src + c * ss];
   }
 }
 

@@ -159,6 +159,49 @@ def test_ghost_fills(nyx):
     assert np.array_equal(T.cpu().numpy(), want)
 
 
+def test_ghost_fill_tiled_odd_layouts(nyx):
+    """Mode 1 on boxes that are not cubes, with ghost width 5, state offsets
+    that are multiples of nothing and a different component stride in every
+    box (a source box's stride is its own): every ghost cell equals the
+    periodic domain's, the valid cells and the padding between components
+    are untouched."""
+    import torch
+    prm = nyx.default_params()
+    gx, gy, gz, n, ng = 3, 2, 2, (10, 6, 8), 5
+    rng = np.random.default_rng(41)
+    dom = rng.normal(size=(6, gz * n[2], gy * n[1], gx * n[0]))
+    pad = synth.pad_periodic(dom, ng)
+    bl, want, start = [], [], []
+    off = 13
+    for bz in range(gz):
+        for by in range(gy):
+            for bx in range(gx):
+                part = pad[:, bz * n[2]: bz * n[2] + n[2] + 2 * ng, by * n[1]: by * n[1] + n[1] + 2 * ng,
+                           bx * n[0]: bx * n[0] + n[0] + 2 * ng]
+                P = part[0].size
+                cs = P + 7 * len(bl) + 3
+                bl.append(nyx.make_box(n, ng, 1 / 16, state_off=off, comp_stride=cs))
+                want.append(part)
+                start.append((off, cs))
+                off += 6 * cs + 11
+    flat = np.full(off, np.nan)
+    full = np.full(off, np.nan)
+    for (o, cs), part in zip(start, want):
+        for c in range(6):
+            z = np.zeros_like(part[c])
+            z[ng:-ng, ng:-ng, ng:-ng] = part[c][ng:-ng, ng:-ng, ng:-ng]
+            flat[o + c * cs: o + c * cs + z.size] = z.ravel()
+            full[o + c * cs: o + c * cs + z.size] = part[c].ravel()
+    T = to_dev(flat)
+    mn, _ = nyx.Batch.workspace_bytes(prm, bl)
+    plan = nyx.Batch(prm, bl, aligned_ws(mn))
+    plan.fill_ghosts(T, mode=1, grid=(gx, gy, gz))
+    torch.cuda.synchronize()
+    got = T.cpu().numpy()
+    assert np.array_equal(got, full, equal_nan=True)
+    plan.close()
+
+
 @pytest.mark.parametrize("tune", [0, 13])
 def test_graph_replay_matches_eager(nyx, tune):
     # capture [step with fused dt_next -> ghost fill] x 2 into a HIP graph and
