@@ -148,7 +148,8 @@ def roofline_of(stage_ms, table, shapes, iters, step_ms, grav_bytes, form, workl
     t = None
     if tune is not None and persistent_ms is None and dom in STAGES:
         t = measured_traffic(dom, form, tune[STAGES.index(dom)], workload)
-    roof = {"bound": "alu" if dom in RIEMANN + ("trace", "step_persistent", "final") else "hbm",
+    roof = {"bound": "alu" if dom in RIEMANN + ("trace", "step_persistent", "front", "final")
+            else "hbm",
             "kernel": dom, "ms_per_launch": round(ms, 4),
             "flops_per_launch": fl, "achieved": round(ach, 3), "peak": ALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 4), "traffic": t}
@@ -164,7 +165,10 @@ def roofline_of(stage_ms, table, shapes, iters, step_ms, grav_bytes, form, workl
     return roof, hbm
 
 
-FUSED_STAGES = STAGES[:5] + ("final",)  # riem2 + update as one launch (k_final)
+# the fused launch mode's kernels: "front" = trace + riem0 (k_front),
+# "final" = riem2 + update (k_final)
+FUSED_STAGES = ("prim", "flat", "front", "riem1", "final")
+FUSED_PARTS = {"front": ("trace", "riem0"), "final": ("riem2", "update")}
 
 
 def kernel_stages(fused):
@@ -172,16 +176,14 @@ def kernel_stages(fused):
 
 
 def kernel_ms(stage_ms, stage):
-    """ms of a stage kernel; "final" is the fused launch, which the library's
-    events report as stage riem2 (update's interval is empty)."""
-    return stage_ms["riem2"] + stage_ms["update"] if stage == "final" else stage_ms[stage]
+    """ms of a stage kernel; a fused kernel's time is what the library's
+    events report for its first stage (the second stage's interval is
+    empty), so the sum of both is the fused launch's."""
+    return sum(stage_ms[s] for s in FUSED_PARTS.get(stage, (stage,)))
 
 
 def kernel_flops(table, stage, shapes, iters):
-    if stage == "final":
-        return (stage_flops(table, "riem2", shapes, iters) +
-                stage_flops(table, "update", shapes, iters))
-    return stage_flops(table, stage, shapes, iters)
+    return sum(stage_flops(table, s, shapes, iters) for s in FUSED_PARTS.get(stage, (stage,)))
 
 
 def stage_rates(stage_ms, table, shapes, iters, fused=False):

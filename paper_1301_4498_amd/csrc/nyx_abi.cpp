@@ -85,6 +85,7 @@ void set_blocks(const BoxDev& b, int* nb) {
   nb[kSpaceE] = (int)blocks_for(b.E);
   nb[kSpaceV] = (int)blocks_for(b.V);
   nb[kSpaceT] = b.ntiles;
+  nb[kSpaceF] = b.fbx;
 }
 
 // [a0, a0 + alen) and [b0, b0 + blen) in bytes
@@ -462,6 +463,10 @@ int nyx_batch_create(const nyx_params* p, int nbox, const nyx_box* boxes, void* 
             acc += host[b].ntiles;
             continue;
           }
+          if (s == kSpaceF) {
+            acc += host[b].fbx;
+            continue;
+          }
           long long cnt = s == kSpaceP ? host[b].P : (s == kSpaceE ? host[b].E : host[b].V);
           acc += (int)blocks_for(cnt);
         }
@@ -609,10 +614,12 @@ int enqueue_batched(nyx_batch* plan, const double* state_in, const void* grav, c
     A.a_new = a_new;
     A.stats = stats;
     A.dt_next = dt_next;
-    // the fused final stage where the plan allows it (flux registers read
-    // the final face states the fused kernel does not store); the launch-
-    // order sweep times the staged kernels
+    // the fused kernels where the plan allows them (flux registers read the
+    // final face states the fused final stage does not store; the fused
+    // front stores everything the staged kernels do); the launch-order sweep
+    // times the staged kernels
     A.fuse_final = plan->mode == NYX_LAUNCH_FUSED && !plan->reg && !group_ev ? 1 : 0;
+    A.fuse_front = plan->mode == NYX_LAUNCH_FUSED && !group_ev ? 1 : 0;
     hipError_t e;
     if (group_ev) {
       A.ev = group_ev[&g - plan->groups.data()];

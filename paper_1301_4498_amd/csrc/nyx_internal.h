@@ -16,6 +16,10 @@ constexpr int kBlock = 256;  // threads per block: 4 wavefronts of 64
 // boxes are cut into several chunks so that the launch has enough tiles).
 constexpr int kFinBlock = 512;
 constexpr int kFinPlanes = 64;
+// Fused front (tracing and stage-0 solves of x in one kernel): a wavefront
+// holds 64 consecutive cells of the [-1, n]^3 range, the first of them the
+// last of the previous wavefront, so a block owns kFrontOwn cells.
+constexpr int kFrontOwn = kBlock / 64 * 63;
 // Stored per face: the Godunov state (rho_g, u_g normal, v_g, w_g transverse,
 // p_g) in the face's rotated frame; every flux is recomputed from it.
 constexpr int kGod = 5;
@@ -55,6 +59,7 @@ struct BoxDev {
   unsigned sc[3];          // per Space: cell count (< 2^31)
   int tx, ty, ntx, nty;    // fused final stage: tile shape, tiles along x and y,
   int ntiles, pad2_;       // tiles in all (z chunks of kFinPlanes planes included)
+  int fbx, pad3_;          // fused front: blocks of kFrontOwn cells
 };
 
 // Stage-array element count for a box (before alignment padding).
@@ -108,6 +113,7 @@ inline long long box_layout(const nyx_box& b, int gidx, long long base, BoxDev* 
   d.ntx = (b.n[0] + d.tx - 1) / d.tx;
   d.nty = (b.n[1] + d.ty - 1) / d.ty;
   d.ntiles = d.ntx * d.nty * ((b.n[2] + kFinPlanes - 1) / kFinPlanes);
+  d.fbx = (int)((d.E + kFrontOwn - 1) / kFrontOwn);
   if (out) *out = d;
   return o;
 }
@@ -121,10 +127,11 @@ struct StepC {
 };
 
 // Which cell range a launch walks: padded cells, the [-1, n]^3 range, valid
-// cells, and the column tiles of the fused final stage (counted in tiles,
-// not in blocks of cells; no cell coordinates of their own).
-enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2, kSpaceT = 3 };
-constexpr int kSpaces = 4;
+// cells, the column tiles of the fused final stage (counted in tiles, not in
+// blocks of cells; no cell coordinates of their own), and the fused front's
+// blocks of kFrontOwn cells of the [-1, n]^3 range.
+enum Space { kSpaceP = 0, kSpaceE = 1, kSpaceV = 2, kSpaceT = 3, kSpaceF = 4 };
+constexpr int kSpaces = 5;
 
 #ifdef __HIPCC__
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -292,6 +299,12 @@ struct StepArgs {
   unsigned long long barrier_ticks;
   // 1: stages riem2 and update run fused (k_final) where the step allows it
   int fuse_final;
+  // 1: stages trace and riem0 of x run fused (k_front) where the step
+  // allows it; their launches then take y and z only
+  int fuse_front;
+  // direction of row 0 of the trace and riem0 launches (1 when k_front has
+  // taken x)
+  int dir0;
 };
 
 

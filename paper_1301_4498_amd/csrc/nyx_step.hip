@@ -371,16 +371,16 @@ __device__ __forceinline__ void trace_side(const real* qc, real c, const real* q
 // The direction of a launch row is uniform per workgroup; each stage body is
 // instantiated per direction so that component and stride choices are
 // compile-time constants instead of selects.
+// The tracing of one cell of the [-1, n]^3 range in direction D (E-index e,
+// E-coordinates ie, je, ke): its low- and high-side edge states after the
+// half-step sources and the floors, in lo and hi; returns the floors applied.
 template <int D>
-__device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b, unsigned idx) {
+__device__ __forceinline__ unsigned trace_cell(const StepArgs& A, const BoxDev& b, const StepC& C,
+                                               unsigned e, int ie, int je, int ke, real* lo,
+                                               real* hi) {
   constexpr int d = D;
   unsigned floors = 0;
   {
-    const unsigned e = idx;
-    int ec[3];
-    space_coords(b, kSpaceE, idx, ec);
-    const int ie = ec[0], je = ec[1], ke = ec[2];
-    const StepC& C = step_consts(A, b);
     const real* prim = (const real*)A.work + b.w_prim;
     const unsigned c0 = pidx_e(b, ie, je, ke);
     const unsigned s = d == 0 ? 1u : (d == 1 ? (unsigned)b.px : (unsigned)b.px * (unsigned)b.py);
@@ -408,7 +408,6 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
     const real kh = (real)C.kh;
     real sig[3];
     for (int w = 0; w < 3; ++w) sig[w] = fabs(lam[w]) * kh;
-    real lo[5], hi[5];
     trace_side<+1>(qc, c, qp, dq, q6, lam, sig, nv, t1, t2, hi);
     trace_side<-1>(qc, c, qm, dq, q6, lam, sig, nv, t1, t2, lo);
     // half-step gravity and expansion sources, then floors
@@ -422,18 +421,32 @@ __device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b
       if (q[0] < sd_) { q[0] = sd_; floors++; }
       if (q[4] < sp_) { q[4] = sp_; floors++; }
     }
-    real* W = (real*)A.work + b.w_edge;
-    for (int v = 0; v < 5; ++v) {
-      stu(W + ((d * 2 + 0) * 5 + v) * b.E, e, lo[v]);
-      stu(W + ((d * 2 + 1) * 5 + v) * b.E, e, hi[v]);
-    }
   }
+  return floors;
+}
+template <int D>
+__device__ __forceinline__ void store_edges(const StepArgs& A, const BoxDev& b, unsigned e,
+                                            const real* lo, const real* hi) {
+  real* W = (real*)A.work + b.w_edge;
+  for (int v = 0; v < 5; ++v) {
+    stu(W + ((D * 2 + 0) * 5 + v) * b.E, e, lo[v]);
+    stu(W + ((D * 2 + 1) * 5 + v) * b.E, e, hi[v]);
+  }
+}
+template <int D>
+__device__ __forceinline__ unsigned trace_dir(const StepArgs& A, const BoxDev& b, unsigned idx) {
+  int ec[3];
+  space_coords(b, kSpaceE, idx, ec);
+  real lo[5], hi[5];
+  const unsigned floors = trace_cell<D>(A, b, step_consts(A, b), idx, ec[0], ec[1], ec[2], lo, hi);
+  store_edges<D>(A, b, idx, lo, hi);
   return floors;
 }
 
 __device__ __forceinline__ void trace_body(const StepArgs& A, const Item& it) {
   int d;
   Loc L = locate(A, kStTrace, kSpaceE, it, &d);
+  d += A.dir0;
   const BoxDev& b = *L.bd;
   unsigned floors = 0;
   if (L.idx < b.E) {
@@ -1130,6 +1143,7 @@ template <bool LEARNED>
 __device__ __forceinline__ void riem0_body(const StepArgs& A, const Item& it, __bf16* mlp_lds) {
   int d;
   Loc L = locate(A, kStRiem0, kSpaceE, it, &d);
+  d += A.dir0;
   const BoxDev& b = *L.bd;
   __bf16* lds = mlp_lds + (threadIdx.x >> 6) * kMlpWaveLds * LEARNED;
   Tally T;
@@ -1142,6 +1156,82 @@ template <bool LEARNED>
 __global__ __launch_bounds__(kBlock) void k_riem0(StepArgs A) {
   __shared__ __bf16 mlp_lds[LEARNED ? (kBlock / 64) * kMlpWaveLds : 1];
   riem0_body<LEARNED>(A, launch_item(A, kStRiem0), mlp_lds);
+}
+
+// ---------------------------------------------------------------------------
+// fused front (launch mode NYX_LAUNCH_FUSED): stages 3 and 4 of x in one
+// kernel.  Each cell is traced as k_trace traces it and its edge states are
+// stored, and each x-face is solved as k_riem0 solves it, from the high-side
+// state of the cell below and the low-side state of the cell above, which
+// the kernel still holds instead of reading them back.  (A thread walking a
+// column along y or z, carrying the high-side state in registers, was
+// slower than the staged kernels for those directions.)
+// ---------------------------------------------------------------------------
+// the stage-0 solve of the D-face at E-index e from the stage-array states L
+// (high side of the cell below) and R (low side of the cell above)
+template <int D>
+__device__ __forceinline__ void riem0_face(const StepArgs& A, const BoxDev& b, unsigned e,
+                                           bool active, const real* L, const real* R, Tally& T) {
+  double ql[5], qr[5];
+  if (active) {
+    double Ls[5], Rs[5];
+    for (int v = 0; v < 5; ++v) {
+      Ls[v] = (double)L[v];
+      Rs[v] = (double)R[v];
+    }
+    rotate(D, Ls, ql);
+    rotate(D, Rs, qr);
+  }
+  RiemannOut g = solve<false>(A, active, ql, qr, nullptr, &T.used, &T.fb);
+  if (active) {
+    T.calls += 1;
+    T.iters += g.iters;
+    store_god((real*)A.work + b.w_f0 + (long long)D * kGod * b.E, b.E, e, g);
+  }
+}
+
+// x: wavefront w of block bb holds E-cells bb kFrontOwn + 63 w - 1 + lane.
+// Lane 0's cell is the previous wavefront's last: lane 0 only traces it,
+// for the high-side state lane 1 takes.  Every other lane stores its
+// cell's edge states and solves the x-face below the cell (none at the
+// range's first column) with the state of lane - 1.
+__device__ __forceinline__ void front_x(const StepArgs& A, const BoxDev& b, const StepC& C,
+                                        unsigned bb, unsigned& floors, Tally& T) {
+  const int lane = (int)(threadIdx.x & 63);
+  const long long e = (long long)bb * kFrontOwn + (long long)(threadIdx.x >> 6) * 63 + lane - 1;
+  const bool on = e >= 0 && e < b.E;
+  const bool own = on && lane > 0;
+  int ec[3] = {0, 0, 0};
+  real lo[5] = {}, hi[5] = {};
+  unsigned fl = 0;
+  if (on) {
+    space_coords(b, kSpaceE, (unsigned)e, ec);
+    fl = trace_cell<0>(A, b, C, (unsigned)e, ec[0], ec[1], ec[2], lo, hi);
+  }
+  if (own) {
+    floors += fl;
+    store_edges<0>(A, b, (unsigned)e, lo, hi);
+  }
+  real left[5];
+  for (int v = 0; v < 5; ++v) left[v] = __shfl_up(hi[v], 1, 64);
+  riem0_face<0>(A, b, (unsigned)e, own && ec[0] >= 1, left, lo, T);
+}
+
+__global__ __launch_bounds__(kBlock) void k_front(StepArgs A) {
+  const unsigned x = xcd_linear_block(true);
+  const int* pre = A.prefix[kSpaceF];
+  int lo = 0, hi = A.nb;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= (int)x) lo = mid;
+    else hi = mid;
+  }
+  const BoxDev& b = A.table[lo];
+  unsigned floors = 0;
+  Tally T;
+  front_x(A, b, step_consts(A, b), x - (unsigned)pre[lo], floors, T);
+  if (A.stats) count(A, kFloorHits, floors);
+  count_tally<false>(A, T, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1858,10 +1948,22 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   mark(1);
   hipLaunchKernelGGL(k_flat, dim3(a.nblocks[kSpaceE]), blk, 0, s, a);
   mark(2);
-  hipLaunchKernelGGL(k_trace, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
-  mark(3);
-  if (learned(0)) hipLaunchKernelGGL(k_riem0<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
-  else hipLaunchKernelGGL(k_riem0<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  if (a.fuse_front && !learned(0)) {
+    // trace and riem0 of x fused, then the staged kernels for y and z
+    // (rows 0 and 1 of their grids); stage 3's time holds k_front and the
+    // y, z tracing, stage 4's the y, z solves
+    StepArgs yz = a;
+    yz.dir0 = 1;
+    hipLaunchKernelGGL(k_front, dim3(a.nblocks[kSpaceF]), blk, 0, s, a);
+    hipLaunchKernelGGL(k_trace, dim3(a.nblocks[kSpaceE], 2), blk, 0, s, yz);
+    mark(3);
+    hipLaunchKernelGGL(k_riem0<false>, dim3(a.nblocks[kSpaceE], 2), blk, 0, s, yz);
+  } else {
+    hipLaunchKernelGGL(k_trace, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+    mark(3);
+    if (learned(0)) hipLaunchKernelGGL(k_riem0<kHasLearned>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+    else hipLaunchKernelGGL(k_riem0<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);
+  }
   mark(4);
   if (learned(1)) hipLaunchKernelGGL(k_riem1<kHasLearned>, dim3(a.nblocks[kSpaceE], 6), blk, 0, s, a);
   else hipLaunchKernelGGL(k_riem1<false>, dim3(a.nblocks[kSpaceE], 3), blk, 0, s, a);

@@ -1,6 +1,6 @@
 """Host-side checks of the benchmark's contract (no GPU): more than one GPU
 is refused with a message; the roofline traffic record is keyed to the
-stage kernels' sources and holds one value per launch-order candidate; the per-launch byte table covers every stage; the fused final stage is booked as one kernel."""
+stage kernels' sources and holds one value per launch-order candidate; the per-launch byte table covers every stage; the fused kernels are booked as one kernel each."""
 import json
 import os
 import subprocess
@@ -54,17 +54,21 @@ def test_source_hash_ignores_comments_and_layout():
     assert bench._code_tokens("a - b") != bench._code_tokens("a + b")
 
 
-def test_fused_final_stage_accounting():
-    # the fused launch is reported as stage riem2 by the library's events
-    # (update's interval empty); the benchmark books it as one kernel,
-    # "final", with riem2's and update's algorithmic flops together
+def test_fused_stage_accounting():
+    # a fused launch is reported as its first stage by the library's events
+    # (the second stage's interval empty); the benchmark books it as one
+    # kernel, "front" (trace + riem0) or "final" (riem2 + update), with both
+    # stages' algorithmic flops together
     import bench
     table = bench.flop_table("box512_stress")
     shapes = [(64, 64, 64)] * 2
-    stage_ms = {"prim": 1.0, "flat": 1.0, "trace": 2.0, "riem0": 3.0, "riem1": 5.0,
+    stage_ms = {"prim": 1.0, "flat": 1.0, "trace": 2.0, "riem0": 3.0, "riem1": 6.0,
                 "riem2": 4.5, "update": 0.001}
-    assert bench.kernel_stages(True)[-1] == "final" and "riem2" not in bench.kernel_stages(True)
+    assert bench.kernel_stages(True) == ("prim", "flat", "front", "riem1", "final")
     assert bench.kernel_ms(stage_ms, "final") == 4.501
+    assert bench.kernel_ms(stage_ms, "front") == 5.0
+    assert bench.kernel_flops(table, "front", shapes, 3.4) == (
+        bench.stage_flops(table, "trace", shapes, 3.4) + bench.stage_flops(table, "riem0", shapes, 3.4))
     fl = bench.kernel_flops(table, "final", shapes, 3.4)
     assert fl == (bench.stage_flops(table, "riem2", shapes, 3.4) +
                   bench.stage_flops(table, "update", shapes, 3.4)) and fl > 0
@@ -78,3 +82,7 @@ def test_fused_final_stage_accounting():
                                 "box512_stress_patches", fused=True)
     assert roof["kernel"] == "final" and roof["traffic"] is None
     assert abs(roof["ms_per_launch"] - 9.001) < 1e-9
+    stage_ms["riem0"] = 8.0
+    roof, _ = bench.roofline_of(stage_ms, table, shapes, 3.4, 20.0, 4, "mixed",
+                                "box512_stress_patches", fused=True)
+    assert roof["kernel"] == "front" and roof["bound"] == "alu" and roof["traffic"] is None
