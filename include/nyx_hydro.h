@@ -244,17 +244,22 @@ int nyx_hydro_step_batched(nyx_batch* plan, const double* state_in, const void* 
  * both precisions and for the learned flux on all three stages; a plan that
  * harvests training records runs staged.  Stage timing (nyx_profile_*) sees
  * only the staged and fused launches.
- * NYX_LAUNCH_FUSED: staged launches, except that the last two stages (the
- * final Riemann solves of Sec. 3.2 and the conservative update with the
- * gravity corrector and the dual-energy sync of Sec. 3.6, Steps 2 and 6)
- * run as one launch: a workgroup takes a tile of cell columns of a box and
- * marches up the box in z, solving each final face once (plus the faces past
- * the tile's last column and row) and updating every cell as soon as its six
- * faces are known, so the final face states never reach HBM.  Bit for bit the
- * result of the staged launches.  A plan that uses the learned flux on the
- * final stage, harvests training records or feeds flux registers runs those
- * two stages staged; nyx_profile_* reports the fused launch as stage 6 and a
- * zero-length stage 7. */
+ * NYX_LAUNCH_FUSED: staged launches, except for two fusions.  The last two
+ * stages (the final Riemann solves of Sec. 3.2 and the conservative update
+ * with the gravity corrector and the dual-energy sync of Sec. 3.6, Steps 2
+ * and 6) run as one launch: a workgroup takes a tile of cell columns of a box
+ * and marches up the box in z, solving each final face once (plus the faces
+ * past the tile's last column and row) and updating every cell as soon as
+ * its six faces are known, so the final face states never reach HBM.  And
+ * the tracing and the first Riemann solves of x run as one launch: each lane
+ * traces one cell and solves the x-face below it with the edge state its
+ * neighbouring lane just traced (y and z keep their staged launches).  Bit
+ * for bit the result of the staged launches.  A plan that uses the learned
+ * flux on the final stage, harvests training records or feeds flux
+ * registers runs the last two stages staged, and one with the learned flux
+ * on the first solves runs those staged; nyx_profile_* reports each fused
+ * launch as its first stage (the x front with the y, z tracing as stage 3)
+ * and a shorter or zero-length second stage. */
 enum { NYX_LAUNCH_STAGED = 0, NYX_LAUNCH_PERSISTENT = 1, NYX_LAUNCH_FUSED = 2 };
 /* NYX_E_UNSUPPORTED when the persistent mode is not available for the
  * plan's parameters. */
