@@ -732,7 +732,7 @@ def level_leg(nyx, torch, synth, learn, flux, steps, warmup, log):
             r["per_box_ms_per_step"] = pms
             del wsb1
         res[form] = r
-        log("level %s: %s" % (form, {k: (round(v, 4) if isinstance(v, float) else v)
+        log("level %s: %s" % (form, {k: (float("%.4g" % v) if isinstance(v, float) else v)
                                      for k, v in r.items() if k not in ("stage", "tuning")}))
         plan.close()
         del plan, ws, state, grav, bufs, fin  # the plan object holds its workspace
