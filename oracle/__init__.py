@@ -141,6 +141,8 @@ def lib():
         L.nyxo_ppm_interface.restype = d
         L.nyxo_flatten_line.argtypes = [P, i, _D, _D, _D]
         L.nyxo_flatten_line.restype = None
+        L.nyxo_flattening.argtypes = [P, i, i, i, i, _D, d, _D]
+        L.nyxo_flattening.restype = i
         L.nyxo_trace_cell.argtypes = [P, i, _D, d, _D, _D, _D, d, d, d, d, _D, _D]
         L.nyxo_trace_cell.restype = i
         lg = ctypes.c_long
@@ -275,6 +277,20 @@ def flatten_line(p, u, params: Params | None = None):
     chi = np.full(p.shape[0], np.nan)
     lib().nyxo_flatten_line(ctypes.byref(params.c()), p.shape[0], _ptr(p), _ptr(u),
                             _ptr(chi))
+    return chi
+
+
+def flattening(state: np.ndarray, ng: int, a: float, params: Params | None = None):
+    """The step's flattening coefficient on the cells of [-1, n]^3 of a padded
+    state (6, nz+2ng, ny+2ng, nx+2ng): shape (nz+2, ny+2, nx+2)."""
+    params = params or Params()
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    nx, ny, nz = _dims(state, ng)
+    chi = np.full((nz + 2, ny + 2, nx + 2), np.nan)
+    rc = lib().nyxo_flattening(ctypes.byref(params.c()), nx, ny, nz, ng, _ptr(state),
+                               ctypes.c_double(a), _ptr(chi))
+    if rc != 0:
+        raise ValueError("nyxo_flattening: bad arguments")
     return chi
 
 

@@ -526,6 +526,80 @@ int nyxo_estimate_dt(const nyxo_params* prm, int nx, int ny, int nz, int ng,
 /* ------------------------------------------------------------------ */
 #define NF 8 /* values stored per face */
 
+/* O1 and O2 of the step: primitives (rho, u, p, c) on every padded cell of
+ * box b from the state at scale factor a_old, and the flattening coefficient
+ * chi (the minimum of the three directional coefficients) on the cells of
+ * [-1, n]^3.  prim: 6 P values, chi: E values (E-array layout). */
+static void prim_and_flattening(const nyxo_params* prm, const Box* bp, const double* Uin,
+                                double a_old, double* prim, double* chi, nyxo_stats* st) {
+  const Box b = *bp;
+  const long P = b.P;
+  const int* n = b.n;
+  const int ng = b.ng;
+  const double gam = prm->gamma, gm1 = gam - 1.0;
+#define PRIM(v, i, j, k) prim[(v) * P + pid(&b, i, j, k)]
+  /* ---- O1: primitives on every padded cell ---- */
+  NYXO_STAGE(1);
+  for (int kk = -ng; kk < n[2] + ng; ++kk)
+    for (int j = -ng; j < n[1] + ng; ++j)
+      for (int i = -ng; i < n[0] + ng; ++i) {
+        long id = pid(&b, i, j, kk);
+        double rho = Uin[id];
+        if (rho < prm->small_dens) { rho = prm->small_dens; st->floor_hits++; }
+        double u[3];
+        for (int d = 0; d < 3; ++d) u[d] = Uin[(1 + d) * P + id] / (a_old * rho);
+        double re = Uin[5 * P + id] / (a_old * a_old);
+        double p = gm1 * re;
+        if (p < prm->small_pres) { p = prm->small_pres; st->floor_hits++; }
+        double c = sqrt((gam * p) / rho);
+        prim[id] = rho;
+        for (int d = 0; d < 3; ++d) prim[(1 + d) * P + id] = u[d];
+        prim[4 * P + id] = p;
+        prim[5 * P + id] = c;
+      }
+
+  /* ---- O2: flattening, chi = min over directions, cells [-1, n]^3 ---- */
+  NYXO_STAGE(2);
+  for (int kk = -1; kk <= n[2]; ++kk)
+    for (int j = -1; j <= n[1]; ++j)
+      for (int i = -1; i <= n[0]; ++i) {
+        double cmin = 1.0;
+        for (int d = 0; d < 3; ++d) {
+          double p7[7], u5[5];
+          for (int s = -3; s <= 3; ++s) {
+            int c3[3] = {i, j, kk};
+            c3[d] += s;
+            p7[s + 3] = PRIM(4, c3[0], c3[1], c3[2]);
+            if (s >= -2 && s <= 2) u5[s + 2] = PRIM(1 + d, c3[0], c3[1], c3[2]);
+          }
+          double cd = flat_chi(prm->small_pres, p7, u5);
+          if (d == 0) cmin = cd;
+          else cmin = dmin(cmin, cd);
+        }
+        chi[eid(&b, i, j, kk)] = cmin;
+      }
+
+#undef PRIM
+}
+
+/* chi of the step (O2) on the cells of [-1, n]^3 of a box, for pins of the
+ * three-direction combination; chi_out: (nz + 2) (ny + 2) (nx + 2) values,
+ * x fastest.  Returns 0, or -1 on bad arguments / allocation failure. */
+int nyxo_flattening(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                    const double* state, double a, double* chi_out) {
+  if (!prm || !state || !chi_out || nx < 1 || ny < 1 || nz < 1 || ng < 4 || !(a > 0.0))
+    return -1;
+  Box b;
+  box_init(&b, nx, ny, nz, ng);
+  nyxo_stats st;
+  memset(&st, 0, sizeof st);
+  double* prim = (double*)malloc(sizeof(double) * 6 * b.P);
+  if (!prim) return -1;
+  prim_and_flattening(prm, &b, state, a, prim, chi_out, &st);
+  free(prim);
+  return 0;
+}
+
 int nyxo_hydro_step(const nyxo_params* prm, int nx, int ny, int nz, int ng,
                     const double* Uin, const double* grav, double dt,
                     double dx, double a_old, double a_new, double* Uout,
@@ -588,46 +662,7 @@ int nyxo_hydro_step_faces(const nyxo_params* prm, int nx, int ny, int nz, int ng
 #define FL1(d, t, v, id) F1[(((d) * 3 + (t)) * NF + (v)) * E + (id)]
 #define FL2(d, v, id) F2[((d) * NF + (v)) * E + (id)]
 
-  /* ---- O1: primitives on every padded cell ---- */
-  NYXO_STAGE(1);
-  for (int kk = -ng; kk < n[2] + ng; ++kk)
-    for (int j = -ng; j < n[1] + ng; ++j)
-      for (int i = -ng; i < n[0] + ng; ++i) {
-        long id = pid(&b, i, j, kk);
-        double rho = Uin[id];
-        if (rho < prm->small_dens) { rho = prm->small_dens; st->floor_hits++; }
-        double u[3];
-        for (int d = 0; d < 3; ++d) u[d] = Uin[(1 + d) * P + id] / (a_old * rho);
-        double re = Uin[5 * P + id] / (a_old * a_old);
-        double p = gm1 * re;
-        if (p < prm->small_pres) { p = prm->small_pres; st->floor_hits++; }
-        double c = sqrt((gam * p) / rho);
-        prim[id] = rho;
-        for (int d = 0; d < 3; ++d) prim[(1 + d) * P + id] = u[d];
-        prim[4 * P + id] = p;
-        prim[5 * P + id] = c;
-      }
-
-  /* ---- O2: flattening, chi = min over directions, cells [-1, n]^3 ---- */
-  NYXO_STAGE(2);
-  for (int kk = -1; kk <= n[2]; ++kk)
-    for (int j = -1; j <= n[1]; ++j)
-      for (int i = -1; i <= n[0]; ++i) {
-        double cmin = 1.0;
-        for (int d = 0; d < 3; ++d) {
-          double p7[7], u5[5];
-          for (int s = -3; s <= 3; ++s) {
-            int c3[3] = {i, j, kk};
-            c3[d] += s;
-            p7[s + 3] = PRIM(4, c3[0], c3[1], c3[2]);
-            if (s >= -2 && s <= 2) u5[s + 2] = PRIM(1 + d, c3[0], c3[1], c3[2]);
-          }
-          double cd = flat_chi(prm->small_pres, p7, u5);
-          if (d == 0) cmin = cd;
-          else cmin = dmin(cmin, cd);
-        }
-        chi[eid(&b, i, j, kk)] = cmin;
-      }
+  prim_and_flattening(prm, &b, Uin, a_old, prim, chi, st);
 
   /* ---- O3 + O4: PPM and tracing, all directions, cells [-1, n]^3 ---- */
   NYXO_STAGE(3);

@@ -134,6 +134,12 @@ double nyxo_ppm_interface(const double* q4);
 
 /* Directional flattening coefficient chi_d on a line of m cells for
  * j in [3, m-4]; others untouched. */
+/* The step's flattening coefficient chi (the minimum over the three
+ * directions of chi_d, from the primitives of the state at scale factor a)
+ * on the cells of [-1, n]^3: chi_out holds (nz+2)(ny+2)(nx+2) values, x
+ * fastest.  Returns 0, or -1 on bad arguments / allocation failure. */
+int nyxo_flattening(const nyxo_params* prm, int nx, int ny, int nz, int ng,
+                    const double* state, double a, double* chi_out);
 void nyxo_flatten_line(const nyxo_params* prm, int m, const double* p,
                        const double* u, double* chi);
 

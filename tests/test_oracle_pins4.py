@@ -1,0 +1,105 @@
+"""Pins of the step oracle's flattening and PPM limiting (Sec. 3.2: unsplit PPM
+with the CW84 flattening and monotonisation) that the earlier pins left open:
+the three-direction combination of the shock detector, the detector's
+threshold, the flattening blend of both edge values, and the monotonicity of
+every limited parabola (no GPU)."""
+import numpy as np
+
+import oracle
+from paper_1301_4498_amd import synth
+
+NG = 4
+
+
+def test_ppm_flattening_blends_both_edges():
+    # linear data: the limited slopes are the exact slope, both interface values
+    # are the exact midpoints, and a flattening coefficient chi pulls both edge
+    # values toward the cell average by the same factor (a linear profile needs
+    # no monotonisation)
+    h = 0.17
+    q = 0.3 + h * np.arange(16)
+    j = np.arange(2, 14)
+    for chi in (0.0, 0.25, 0.5, 0.8, 1.0):
+        qm, qp = oracle.ppm_line(q, np.full(16, chi))
+        assert np.allclose(qp[j], q[j] + chi * h / 2, rtol=0, atol=1e-14), chi
+        assert np.allclose(qm[j], q[j] - chi * h / 2, rtol=0, atol=1e-14), chi
+
+
+def test_ppm_limited_parabola_is_monotone_in_every_cell():
+    # the monotonised parabola through (q-, q_j, q+) has no extremum strictly
+    # inside the cell: |q6| <= |dq|, q6 = 6 q_j - 3 (q- + q+), dq = q+ - q-
+    # (equality where an edge was reset), or it is the constant q_j (a cell at
+    # a local extremum)
+    rng = np.random.default_rng(21)
+    reset = 0
+    for _ in range(200):
+        q = np.cumsum(rng.normal(0.0, 1.0, 40)) + rng.normal(0.0, 0.3, 40)
+        qm, qp = oracle.ppm_line(q)
+        j = np.arange(2, 38)
+        dq = qp[j] - qm[j]
+        q6 = 6.0 * q[j] - 3.0 * (qm[j] + qp[j])
+        flat = (qm[j] == q[j]) & (qp[j] == q[j])
+        tol = 1e-12 * np.maximum(1.0, np.abs(q[j]))
+        assert np.all(flat | (np.abs(q6) <= np.abs(dq) + tol))
+        reset += int(np.sum(~flat & (np.abs(np.abs(q6) - np.abs(dq)) <= tol) & (np.abs(dq) > 0)))
+    # the data exercise the edge reset, not only smooth cells
+    assert reset > 100
+
+
+def test_flatten_threshold_is_relative_to_the_lower_pressure():
+    # CW84 detector: a jump is a shock where |p_j+1 - p_j-1| > eps min(p_j+1,
+    # p_j-1), eps = 0.33.  A 40 % jump (0.40 > 0.33 of the lower pressure)
+    # flattens the two cells beside it completely (z = 1), a 30 % jump does not
+    u = np.array([1.0] * 6 + [0.0] * 6)  # compressive
+    for jump, expect in ((0.40, 0.0), (0.30, 1.0)):
+        p = np.array([1.0] * 6 + [1.0 + jump] * 6)
+        chi = oracle.flatten_line(p, u)
+        assert chi[5] == expect and chi[6] == expect, jump
+
+
+def _expected_chi(p, u):
+    """chi of every cell of [-1, n]^3: the minimum over the three axes of the
+    1-D detector along the axis through the cell (p and u_d on padded cells,
+    shape (nz+2NG, ny+2NG, nx+2NG); arrays indexed [k, j, i])."""
+    pz, py, px = p.shape
+    sl = slice(NG - 1, -(NG - 1))
+    out = np.ones((pz, py, px))
+    per_axis = []
+    for d in range(3):
+        ax = 2 - d
+        pl = np.moveaxis(p, ax, -1)
+        ul = np.moveaxis(u[d], ax, -1)
+        chi_d = np.full(pl.shape, np.nan)
+        for idx in np.ndindex(pl.shape[:-1]):
+            chi_d[idx] = oracle.flatten_line(pl[idx], ul[idx])
+        chi_d = np.moveaxis(chi_d, -1, ax)
+        per_axis.append(chi_d[sl, sl, sl])
+        out = np.minimum(out, chi_d)
+    return out[sl, sl, sl], per_axis
+
+
+def test_step_flattening_is_the_minimum_over_directions():
+    # a compressive jump along each axis (at different places) and a smooth
+    # background: where one jump is, the cells beside it take that axis'
+    # coefficient; the y and z detectors see no jump there and give 1
+    n = (12, 10, 8)
+    nx, ny, nz = n
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    p = 1.0 + 0.01 * np.sin(0.7 * x + 0.3 * y)
+    p = p * np.where(x >= 6, 3.0, 1.0) * np.where(y >= 4, 1.5, 1.0) * np.where(z >= 5, 2.0, 1.0)
+    u = np.stack([np.where(x >= 6, 0.0, 0.8), np.where(y >= 4, -0.2, 0.5),
+                  np.where(z >= 5, 0.0, 0.3)])
+    rho = 1.0 + 0.1 * np.cos(0.5 * z)
+    a = 0.4
+    U = synth.pad_periodic(synth.conserved(rho, u, p, a), NG)
+    chi = oracle.flattening(U, NG, a)
+    # the detector's inputs as the step derives them from the padded state
+    rp = U[0]
+    up = U[1:4] / (a * rp)
+    pp = (synth.GAMMA - 1.0) * (U[5] / (a * a))
+    want, per_axis = _expected_chi(pp, up)
+    assert np.isnan(chi).sum() == 0
+    assert np.array_equal(chi, want)
+    # each axis' jump is detected, and no single axis gives the step's chi
+    for chi_d in per_axis:
+        assert (chi_d < 1.0).any() and not np.array_equal(chi, chi_d)
