@@ -1,9 +1,12 @@
 """Pins of the step oracle's flattening and PPM limiting (Sec. 3.2: unsplit PPM
 with the CW84 flattening and monotonisation) that the earlier pins left open:
 the three-direction combination of the shock detector, the detector's
-threshold, the flattening blend of both edge values, and the monotonicity of
-every limited parabola (no GPU)."""
+threshold, the flattening blend of both edge values, the monotonicity of
+every limited parabola, and the half-step pressure source of the expansion
+(Sec. 2.2) against the update's own expansion of the internal energy (no
+GPU)."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_1301_4498_amd import synth
@@ -103,3 +106,52 @@ def test_step_flattening_is_the_minimum_over_directions():
     # each axis' jump is detected, and no single axis gives the step's chi
     for chi_d in per_axis:
         assert (chi_d < 1.0).any() and not np.array_equal(chi, chi_d)
+
+
+def _gas_box(p, a, gamma, n=(8, 4, 4)):
+    """Padded state of a gas at rest with uniform density 1 and the given
+    pressure on the padded x-axis (uniform in y and z)."""
+    nx, ny, nz = n
+    px = nx + 2 * NG
+    shape = (nz + 2 * NG, ny + 2 * NG, px)
+    P = np.broadcast_to(p, shape).copy()
+    U = np.zeros((6,) + shape)
+    U[0] = 1.0
+    U[5] = a * a * P / (gamma - 1.0)  # no kinetic energy: E = e
+    U[4] = U[5]
+    return U
+
+
+@pytest.mark.parametrize("gamma", [5.0 / 3.0, 1.4])
+def test_half_step_pressure_source_matches_the_expansion_of_the_update(gamma):
+    # Sec. 2.2 expansion terms, seen by two parts of the step: the update
+    # advances U_e = a^2 rho e of a uniform gas at rest over the step, so the
+    # primitive pressure p = (gamma - 1) U_e / a^2 changes at the log rate
+    # s = d ln p / d ln a; the tracing's half-step source must lower the edge
+    # pressures by the same rate over half the step, - s da / (2 a_h), to first
+    # order in da / a.  The edge pressure shows in the momentum update of a
+    # linear pressure profile: with u = 0 and a vanishing time step the x-face
+    # pressures differ by (1 - pexp) eps per cell, so m_new = -k eps (1 - pexp).
+    prm = oracle.Params(gamma=gamma)
+    a0, a1 = 0.5, 0.51
+    ah = 0.5 * (a0 + a1)
+    nx = 8
+    # the update alone: a uniform gas
+    U = _gas_box(np.ones(nx + 2 * NG), a0, gamma)
+    out, _ = oracle.hydro_step(U, np.zeros((3,) + U.shape[1:]), NG, 1e-3, 1.0, a0, a1, prm)
+    v = (slice(NG, -NG),) * 3
+    p_ratio = (out[5][v] / a1**2) / (U[5][v] / a0**2)
+    assert np.ptp(p_ratio) == 0.0
+    s = np.log(p_ratio.flat[0]) / np.log(a1 / a0)
+    # the tracing's source: a linear pressure profile, a tiny step
+    eps, k = 1e-3, 1e-7
+    xs = np.arange(nx + 2 * NG, dtype=float)
+    U = _gas_box(1.0 + eps * xs, a0, gamma)
+    out, _ = oracle.hydro_step(U, np.zeros((3,) + U.shape[1:]), NG, k, 1.0, a0, a1, prm)
+    m = out[1][v]
+    pexp = 1.0 + m / (k * eps)
+    assert np.ptp(pexp) <= 1e-6
+    want = -s * (a1 - a0) / (2.0 * ah)
+    # agreement to 2e-5 is observed at da / a = 2 %; a_old in place of a_h alone
+    # would differ by 1 %
+    assert abs(pexp.mean() / want - 1.0) <= 2e-3, (pexp.mean(), want)
