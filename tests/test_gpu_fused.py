@@ -220,11 +220,12 @@ def test_fused_equals_staged_variants(nyx, prec, variant):
     plan.close()
 
 
-@pytest.mark.parametrize("stages", [3, 7])
+@pytest.mark.parametrize("stages", [3, 4, 7])
 def test_fused_with_learned_flux(nyx, stages):
-    """The learned flux on stages 0-1 (the fused kernel runs the plain final
-    stage) and on all three (the final stage stays staged): the fused mode
-    gives the staged launches' bits, counters included."""
+    """The learned flux on stages 0-1 (the x front stays staged, the fused
+    final stage runs the plain solver), on the final stage only (the x front
+    is fused, the final stage stays staged) and on all three (both staged):
+    the fused mode gives the staged launches' bits, counters included."""
     import torch
     from paper_1301_4498_amd import learn
     f = learn.LearnedFlux(seed=9)

@@ -57,7 +57,7 @@ def _unpack(flat, arrays):
     return out
 
 
-def _gpu_two_levels(nyx, prm, setup, dt_c, groups, a0=0.5, a1=0.505):
+def _gpu_two_levels(nyx, prm, setup, dt_c, groups, a0=0.5, a1=0.505, mode=None):
     import torch
     cboxes, cdatas, fboxes, fdatas, cdom, dom = setup
     clo = [lo for _, lo in cboxes]
@@ -80,6 +80,9 @@ def _gpu_two_levels(nyx, prm, setup, dt_c, groups, a0=0.5, a1=0.505):
         return b
 
     cbat, fbat = batch(cb), batch(fb)
+    if mode is not None:
+        cbat.set_launch_mode(mode)
+        fbat.set_launch_mode(mode)
     cbat.set_flux_register(sync, 0, reg)
     fbat.set_flux_register(sync, 1, reg)
     dtc = torch.full((len(cb),), dt_c, dtype=torch.float64, device="cuda")
@@ -123,6 +126,25 @@ def test_fp64_sync_bitwise(nyx, reference, groups):
         assert np.array_equal(_valid(a), _valid(b))
     for a, b in zip(csync, reference["csync"]):
         assert np.array_equal(_valid(a), _valid(b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sync_in_the_fused_launch_mode(nyx, reference, prec):
+    # plans that feed flux registers keep the staged final stage but fuse the
+    # x tracing and stage-0 solves: the same bits as the staged launches, and
+    # (FP64) as the oracle
+    p = nyx.NYX_FP64 if prec == "fp64" else nyx.NYX_MIXED
+    prm = nyx.default_params(precision=p)
+    print("two-level sync, fused mode,", prec, flush=True)
+    runs = [_gpu_two_levels(nyx, prm, reference["setup"], reference["dt_c"], False, mode=m)
+            for m in (nyx.NYX_LAUNCH_STAGED, nyx.NYX_LAUNCH_FUSED)]
+    for a, b in zip(runs[0][0] + runs[0][1], runs[1][0] + runs[1][1]):
+        assert np.array_equal(_valid(a), _valid(b))
+    if prec == "fp64":
+        for a, b in zip(runs[1][1], reference["fnew"]):
+            assert np.array_equal(_valid(a), _valid(b))
+        for a, b in zip(runs[1][0], reference["csync"]):
+            assert np.array_equal(_valid(a), _valid(b))
 
 
 def test_mixed_sync_close_and_conservative(nyx, reference):
