@@ -577,10 +577,13 @@ __device__ __forceinline__ double rsq_est(double x) { return __builtin_amdgcn_rs
 //   p' = p - (u*_R - u*_L) / (1/Z_L + 1/Z_R),
 //   u* = (u*_L / Z_R + u*_R / Z_L) / (1/Z_L + 1/Z_R),
 //   1/rho*_K = 1/rho_K - (p* - p_K) w_K^2.
-// The converged pressure is the root of u*_R - u*_L, which takes the refined
-// w_K; the slope 1/Z_L + 1/Z_R only scales the step, so its reciprocal is the
-// raw estimate: a relative error of 2^-24 in a step that the stopping rule
-// bounds by 2^-12 p moves p' by less than 2^-36 p.
+// The converged pressure is the root of u*_R - u*_L: under the default
+// stopping rule it takes the raw w_K estimates, which shift that root by
+// about their own relative error (2^-24, the FP32 rounding of the stored
+// state); tighter rules take the refined w_K (ts_iterate).  The slope
+// 1/Z_L + 1/Z_R only scales the step, so its reciprocal is always the raw
+// estimate: a relative error of 2^-24 in a step that the stopping rule bounds
+// by 2^-12 p moves p' by less than 2^-36 p.
 struct TwoShock {
   double gam, sp, rl, ul, pl, rr, ur, pr, CL, CR, hCL, hCR, gl, gr;
 };
@@ -778,6 +781,26 @@ __device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double*
   return o;
 }
 
+// Newton iterations from p until a step falls below mixed_stop p (at most
+// maxiter in all).  RAW evaluates the two-shock relations with the raw
+// reciprocal square-root estimates: their relative error (below 2^-24) moves
+// the root of u*_R - u*_L by about that much, the size of the FP32 rounding of
+// the stored Godunov state, and lies far below a stopping step of 2^-20 or
+// more; tighter stopping rules take the refined w_K.
+template <bool RAW>
+__device__ __forceinline__ double ts_iterate(const StepArgs& A, const TwoShock& t, double p,
+                                             int& it) {
+  while (it < A.maxiter) {
+    const TwoShockEval e = RAW ? ts_eval_est(t, p) : ts_eval(t, p);
+    const double pn = ts_newton(t, e, p);
+    ++it;
+    const bool conv = fabs(pn - p) <= A.mixed_stop * pn;
+    p = pn;
+    if (conv) break;
+  }
+  return p;
+}
+
 // BOTH: the star densities of both sides (training records); otherwise the
 // sampled side's only
 template <bool BOTH = false>
@@ -795,14 +818,7 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
   // pressure is already resolved below FP32 rounding and the iteration stops
   // there.
   int it = 0;
-  while (it < A.maxiter) {
-    const TwoShockEval e = ts_eval(t, p);
-    const double pn = ts_newton(t, e, p);
-    ++it;
-    const bool conv = fabs(pn - p) <= A.mixed_stop * pn;
-    p = pn;
-    if (conv) break;
-  }
+  p = A.mixed_stop >= 0x1p-20 ? ts_iterate<true>(A, t, p, it) : ts_iterate<false>(A, t, p, it);
   const TwoShockEval e = ts_eval_est(t, p);
   RiemannOut o = BOTH ? ts_finish(t, e, p, qL, qR) : ts_finish_upwind(t, e, p, qL, qR);
   o.iters = it;
