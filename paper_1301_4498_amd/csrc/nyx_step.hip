@@ -186,7 +186,14 @@ __device__ __forceinline__ real flat_tilde(real sp, real pm2, real pm1, real pp1
                                            real um1, real up1) {
   real dp1 = pp1 - pm1;
   real dp2 = pp2 - pm2;
+#if defined(NYX_PREC_MIXED)
+  // the ratio only places the coefficient on its ramp: the hardware
+  // reciprocal (1 ulp) replaces the range-scaled division; a zero
+  // denominator still gives z = inf where the detector fires (dp1 != 0)
+  real z = fabs(dp1) * __builtin_amdgcn_rcpf(vmax(fabs(dp2), sp));
+#else
   real z = fabs(dp1) / vmax(fabs(dp2), sp);
+#endif
   bool w = (fabs(dp1) > (real)FLAT_EPS * vmin(pp1, pm1)) && ((up1 - um1) < (real)0);
   return w ? vmax((real)0, vmin((real)1, (real)FLAT_OMEGA2 * (z - (real)FLAT_OMEGA1))) : (real)0;
 }
@@ -218,13 +225,23 @@ __device__ __forceinline__ void flat_body(const StepArgs& A, const Item& it) {
   for (int d = 0; d < 3; ++d) {
     const real* p = pd[d];
     const real* u = ud[d];
-    real fm = flat_tilde(sp, p[0], p[1], p[3], p[4], u[0], u[2]);
     real f0 = flat_tilde(sp, p[1], p[2], p[4], p[5], u[1], u[3]);
-    real fp = flat_tilde(sp, p[2], p[3], p[5], p[6], u[2], u[4]);
     real dp1 = p[4] - p[2];
+#if defined(NYX_PREC_MIXED)
+    // the one neighbour the pressure jump selects (cell j-1 for dp1 > 0,
+    // j+1 for dp1 < 0) evaluated once on selected inputs: the same values
+    // as evaluating both, with one evaluation fewer
+    const bool lo = dp1 > (real)0;
+    const real fn = flat_tilde(sp, lo ? p[0] : p[2], lo ? p[1] : p[3], lo ? p[3] : p[5],
+                               lo ? p[4] : p[6], lo ? u[0] : u[2], lo ? u[2] : u[4]);
+    const real f = (lo || dp1 < (real)0) ? vmax(f0, fn) : f0;  // f0 alone for dp1 = 0 or NaN
+#else
+    real fm = flat_tilde(sp, p[0], p[1], p[3], p[4], u[0], u[2]);
+    real fp = flat_tilde(sp, p[2], p[3], p[5], p[6], u[2], u[4]);
     real f = f0;
     if (dp1 > (real)0) f = vmax(f0, fm);
     else if (dp1 < (real)0) f = vmax(f0, fp);
+#endif
     real cd = (real)1 - f;
     cmin = (d == 0) ? cd : vmin(cmin, cd);
   }
