@@ -804,6 +804,7 @@ __device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double*
 // the root of u*_R - u*_L by about that much, the size of the FP32 rounding of
 // the stored Godunov state, and lies far below a stopping step of 2^-20 or
 // more; tighter stopping rules take the refined w_K.
+__host__ __device__ __forceinline__ bool raw_stop(const StepArgs& A) { return A.mixed_stop >= 0x1p-20; }
 template <bool RAW>
 __device__ __forceinline__ double ts_iterate(const StepArgs& A, const TwoShock& t, double p,
                                              int& it) {
@@ -819,8 +820,10 @@ __device__ __forceinline__ double ts_iterate(const StepArgs& A, const TwoShock& 
 }
 
 // BOTH: the star densities of both sides (training records); otherwise the
-// sampled side's only
-template <bool BOTH = false>
+// sampled side's only.  RS selects the iteration's w_K: 0 by the stopping
+// rule at run time, 1 the raw estimates, 2 the refined ones (a kernel that
+// fixes RS holds one copy of the loop instead of two).
+template <bool BOTH = false, int RS = 0>
 __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
                                                 const double* qR) {
   const TwoShock t = ts_setup(A, qL, qR);
@@ -835,7 +838,9 @@ __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double*
   // pressure is already resolved below FP32 rounding and the iteration stops
   // there.
   int it = 0;
-  p = A.mixed_stop >= 0x1p-20 ? ts_iterate<true>(A, t, p, it) : ts_iterate<false>(A, t, p, it);
+  if constexpr (RS == 1) p = ts_iterate<true>(A, t, p, it);
+  else if constexpr (RS == 2) p = ts_iterate<false>(A, t, p, it);
+  else p = raw_stop(A) ? ts_iterate<true>(A, t, p, it) : ts_iterate<false>(A, t, p, it);
   const TwoShockEval e = ts_eval_est(t, p);
   RiemannOut o = BOTH ? ts_finish(t, e, p, qL, qR) : ts_finish_upwind(t, e, p, qL, qR);
   o.iters = it;
@@ -881,9 +886,10 @@ __device__ __forceinline__ RiemannOut learned_solve(const StepArgs& A, const dou
 }
 #else
 
-// BOTH is the mixed build's choice of star densities; this build always
-// computes both
-template <bool BOTH = true>
+// BOTH and RS are the mixed build's choices of star densities and of the
+// iteration's reciprocal square roots; this build always computes both
+// densities with correctly rounded arithmetic
+template <bool BOTH = true, int RS = 0>
 __device__ __forceinline__ RiemannOut two_shock(const StepArgs& A, const double* qL,
                                                 const double* qR) {
   const double gam = A.gamma;
@@ -1090,7 +1096,7 @@ constexpr bool kHasLearned = false;
 // Riemann solve of one face of the wave.  LEARNED: every lane of the
 // wavefront must call it (the network runs wave-wide); `active` marks lanes
 // with a real face.  Returns the solution for active lanes.
-template <bool LEARNED, bool BOTH = false>
+template <bool LEARNED, bool BOTH = false, int RS = 0>
 __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, const double* qL,
                                             const double* qR, __bf16* lds, unsigned* used,
                                             unsigned* fallback) {
@@ -1119,7 +1125,7 @@ __device__ __forceinline__ RiemannOut solve(const StepArgs& A, bool active, cons
     return g;
   }
 #endif
-  if (active) g = A.linear_riemann ? lin_solve(A, qL, qR) : two_shock<BOTH>(A, qL, qR);
+  if (active) g = A.linear_riemann ? lin_solve(A, qL, qR) : two_shock<BOTH, RS>(A, qL, qR);
   return g;
 }
 
@@ -1793,14 +1799,14 @@ __device__ __forceinline__ God lds_get(const real* L, int stride, int slot) {
 
 // The final face at E-index e in direction D when `on`, as the staged riem2
 // stores it (real); counted in T when `own`.
-template <int D, int CARRY = 0>
+template <int D, int CARRY = 0, int RS = 0>
 __device__ __forceinline__ God final_face(const StepArgs& A, const BoxDev& b, const StepC& C,
                                           bool on, bool own, unsigned e, Tally& T,
                                           double* carry = nullptr) {
   double ql[5], qr[5];
   unsigned rv = 0;
   if (on) final_states<D, CARRY>(A, b, C, e, ql, qr, &rv, carry);
-  const RiemannOut g = solve<false>(A, on, ql, qr, nullptr, &T.used, &T.fb);
+  const RiemannOut g = solve<false, false, RS>(A, on, ql, qr, nullptr, &T.used, &T.fb);
   God o{};
   if (on) {
     o = God{(real)g.r, (real)g.u, (real)g.v, (real)g.w, (real)g.p};
@@ -1820,6 +1826,7 @@ constexpr int kFinWaves = 4;
 #else
 constexpr int kFinWaves = 2;
 #endif
+template <int RS>
 __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
   __shared__ real fx[5 * kFinXs];
   __shared__ real fy[5 * kFinYs];
@@ -1874,24 +1881,24 @@ __global__ __launch_bounds__(kFinBlock, kFinWaves) void k_final(StepArgs A) {
   // the z-faces carry each cell's differences from the face below it to
   // the face above
   double zc[6];
-  God zl = final_face<2, 1>(A, b, C, cell, k0 == 0, e, T, zc);  // below the first plane
+  God zl = final_face<2, 1, RS>(A, b, C, cell, k0 == 0, e, T, zc);  // below the first plane
   for (int k = k0; k < k1; ++k) {
     {
-      const God g = final_face<0>(A, b, C, xon, true, e, T);
+      const God g = final_face<0, 0, RS>(A, b, C, xon, true, e, T);
       if (xon) lds_put(fx, kFinXs, tj * (TX + 1) + ti, g);
     }
     {
-      const God g = final_face<1>(A, b, C, yon, true, e, T);
+      const God g = final_face<1, 0, RS>(A, b, C, yon, true, e, T);
       if (yon) lds_put(fy, kFinYs, tj * TX + ti, g);
     }
     if (t < yo) {
-      const God g = final_face<0>(A, b, C, xe, xe_own, exe, T);
+      const God g = final_face<0, 0, RS>(A, b, C, xe, xe_own, exe, T);
       if (xe) lds_put(fx, kFinXs, t * (TX + 1) + TX, g);
     } else if (t < yo + TX) {
-      const God g = final_face<1>(A, b, C, ye, ye_own, eye, T);
+      const God g = final_face<1, 0, RS>(A, b, C, ye, ye_own, eye, T);
       if (ye) lds_put(fy, kFinYs, TY * TX + (t - yo), g);
     }
-    const God zh = final_face<2, 2>(A, b, C, cell, true, e + exy, T, zc);
+    const God zh = final_face<2, 2, RS>(A, b, C, cell, true, e + exy, T, zc);
     CellIn x{};
     if (cell) x = load_cell(A, b, id);
     __syncthreads();
@@ -2003,7 +2010,12 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   mark(5);
   if (a.fuse_final && !learned(2) && !a.harvest) {
     // riem2 and update as one launch; its time is stage 6's, stage 7's is 0
-    hipLaunchKernelGGL(k_final, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
+#if defined(NYX_PREC_MIXED)
+    if (raw_stop(a)) hipLaunchKernelGGL(k_final<1>, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_final<2>, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
+#else
+    hipLaunchKernelGGL(k_final<0>, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
+#endif
     mark(6);
     mark(7);
     return hipGetLastError();
