@@ -332,6 +332,22 @@ int nyx_fill_ghosts_periodic(const nyx_box* box, double* state, int ncomp, void*
 int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
                           void* stream);
 
+/* Where later steps of a plan take the input state's ghost cells (Sec. 4.1:
+ * a level's ghost cells hold copies of the cells they stand for):
+ *   mode -1: from the input's own ghost cells (the default; the caller fills
+ *            them, e.g. with nyx_batch_fill_ghosts);
+ *   mode 0:  from each box's own valid cells, the box being its own periodic
+ *            domain;
+ *   mode 1:  from the neighbouring boxes' valid cells, the boxes tiling a
+ *            periodic domain as a gx*gy*gz grid as in nyx_batch_fill_ghosts
+ *            mode 1 (grid checked here: NYX_E_SHAPE).
+ * Modes 0 and 1 give the step the same result as filling the input's ghosts
+ * with nyx_batch_fill_ghosts in that mode first, bit for bit, without reading
+ * or writing the input's ghost cells; the output's ghost cells are then left
+ * as they were.  Only the primitive stage reads ghost cells of the state.
+ * Other modes: NYX_E_PARAM. */
+int nyx_batch_set_ghost_source(nyx_batch* plan, int mode, int gx, int gy, int gz);
+
 /* ---------------- ghost fill of an AMR level (Sec. 4.1) ----------------
  * A level is nbox boxes of one cell size in a periodic domain of dom[3]
  * cells (host, 3 ints, each even and at least the ghost width).  lo (host,

@@ -268,6 +268,13 @@ class Batch:
         check("nyx_batch_fill_ghosts", lib().nyx_batch_fill_ghosts(
             self.handle, mode, grid[0], grid[1], grid[2], _ptr(state), _stream(stream)))
 
+    def set_ghost_source(self, mode=-1, grid=(1, 1, 1)):
+        """Later steps take the input's ghost cells from their source cells
+        (mode 0: each box periodic; 1: the boxes tile a periodic domain as
+        `grid`) instead of reading them; -1 reads them again."""
+        check("nyx_batch_set_ghost_source", lib().nyx_batch_set_ghost_source(
+            self.handle, int(mode), int(grid[0]), int(grid[1]), int(grid[2])))
+
     def close(self):
         if self.handle is not None and self.handle.value:
             lib().nyx_batch_destroy(self.handle)

@@ -102,6 +102,7 @@ def lib():
             "nyx_hydro_step_batched": (i, [vp, vp, vp, vp, d, d, vp, vp, vp, vp]),
             "nyx_fill_ghosts_periodic": (i, [B, vp, i, vp]),
             "nyx_batch_fill_ghosts": (i, [vp, i, i, i, i, vp, vp]),
+            "nyx_batch_set_ghost_source": (i, [vp, i, i, i, i]),
             "nyx_profile_enable": (i, [i]),
             "nyx_batch_set_harvest": (i, [vp, vp, vp, ctypes.c_longlong, d, ctypes.c_ulonglong]),
             "nyx_mlp_init": (i, [vp, ctypes.c_ulonglong, vp]),
@@ -165,7 +166,8 @@ def exported_symbols():
             "nyx_hydro_step", "nyx_batch_workspace_bytes", "nyx_batch_create",
             "nyx_batch_destroy", "nyx_batch_num_groups", "nyx_batch_estimate_dt",
             "nyx_batch_min_dt", "nyx_hydro_step_batched", "nyx_fill_ghosts_periodic",
-            "nyx_batch_fill_ghosts", "nyx_profile_enable", "nyx_profile_read",
+            "nyx_batch_fill_ghosts", "nyx_batch_set_ghost_source", "nyx_profile_enable",
+            "nyx_profile_read",
             "nyx_batch_set_harvest", "nyx_mlp_init", "nyx_mlp_loss_grad", "nyx_mlp_adam",
             "nyx_mlp_pack", "nyx_mlp_predict", "nyx_batch_autotune", "nyx_batch_set_tuning",
             "nyx_batch_get_tuning", "nyx_fill_plan_bytes", "nyx_fill_plan_create",

@@ -374,6 +374,9 @@ struct nyx_batch {
   unsigned long long* ctl = nullptr;
   unsigned long long barrier_ticks = 0;
   int mode = NYX_LAUNCH_STAGED;
+  // ghost source of stage 1 (StepArgs::gsrc) and the tiling grid
+  int gsrc = 0;
+  int gg[3] = {1, 1, 1};
 };
 
 namespace {
@@ -547,6 +550,9 @@ StepArgs group_args(const nyx_batch* plan, const nyx_batch::Group& g) {
   for (int i = 0; i < kStages; ++i) A.tune[i] = plan->tune[i];
   A.ctl = plan->ctl;
   A.barrier_ticks = plan->barrier_ticks;
+  A.gsrc = plan->gsrc;
+  for (int d = 0; d < 3; ++d) A.gg[d] = plan->gg[d];
+  A.gfull = plan->table;
   return A;
 }
 
@@ -955,17 +961,47 @@ int nyx_profile_read(double* ms, long long* sequences, int reset) {
   return NYX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The plan's boxes tile a periodic domain as a gx x gy x gz grid of equal
+// boxes, in box order, each at least ng cells across (NYX_OK or NYX_E_SHAPE).
+int check_tiling(const nyx_batch* plan, int gx, int gy, int gz) {
+  if (gx < 1 || gy < 1 || gz < 1 || (long long)gx * gy * gz != plan->nbox) return NYX_E_SHAPE;
+  const nyx_box& b0 = plan->boxes[0];
+  for (const auto& b : plan->boxes)
+    if (b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.n[2] != b0.n[2] || b.ng != b0.ng ||
+        b.ng > b.n[0] || b.ng > b.n[1] || b.ng > b.n[2])
+      return NYX_E_SHAPE;
+  return NYX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nyx_batch_set_ghost_source(nyx_batch* plan, int mode, int gx, int gy, int gz) {
+  if (!plan) return NYX_E_NULL;
+  if (mode < -1 || mode > 1) return NYX_E_PARAM;
+  if (mode == 1) {
+    const int rc = check_tiling(plan, gx, gy, gz);
+    if (rc) return rc;
+  }
+  plan->gsrc = mode + 1;
+  plan->gg[0] = mode == 1 ? gx : 1;
+  plan->gg[1] = mode == 1 ? gy : 1;
+  plan->gg[2] = mode == 1 ? gz : 1;
+  return NYX_OK;
+}
+
 int nyx_batch_fill_ghosts(nyx_batch* plan, int mode, int gx, int gy, int gz, double* state,
                           void* stream) {
   if (!plan || !state) return NYX_E_NULL;
   if (mode != 0 && mode != 1) return NYX_E_PARAM;
   if (mode == 1) {
-    if (gx < 1 || gy < 1 || gz < 1 || (long long)gx * gy * gz != plan->nbox) return NYX_E_SHAPE;
-    const nyx_box& b0 = plan->boxes[0];
-    for (const auto& b : plan->boxes)
-      if (b.n[0] != b0.n[0] || b.n[1] != b0.n[1] || b.n[2] != b0.n[2] || b.ng != b0.ng ||
-          b.ng > b.n[0] || b.ng > b.n[1] || b.ng > b.n[2])
-        return NYX_E_SHAPE;
+    const int rc = check_tiling(plan, gx, gy, gz);
+    if (rc) return rc;
   }
   hipStream_t s = (hipStream_t)stream;
   for (const auto& g : plan->groups) {

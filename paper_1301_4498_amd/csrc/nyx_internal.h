@@ -305,6 +305,13 @@ struct StepArgs {
   // direction of row 0 of the trace and riem0 launches (1 when k_front has
   // taken x)
   int dir0;
+  // where stage 1 reads a ghost cell of the input state: 0 the input's own
+  // ghost cell; 1 its periodic image in the same box; 2 its source cell in
+  // the neighbouring box of boxes that tile a periodic domain as a
+  // gg[0] x gg[1] x gg[2] grid (gfull: every box of the plan in box order)
+  int gsrc;
+  int gg[3];
+  const BoxDev* gfull;
 };
 
 

@@ -144,6 +144,40 @@ __device__ __forceinline__ void count(const StepArgs& A, int field, unsigned v) 
 // ---------------------------------------------------------------------------
 // stage 1: primitives on every padded cell
 // ---------------------------------------------------------------------------
+// Where stage 1 reads padded cell id of box b when the input's ghost cells
+// are not read (StepArgs::gsrc): a valid cell is itself; a ghost cell is its
+// periodic image in the box (gsrc 1) or the cell of the neighbouring box of
+// the tiling grid that a same-level ghost fill would copy into it (gsrc 2).
+// Returns the source box's state, component stride and cell index.
+__device__ __forceinline__ void ghost_source(const StepArgs& A, const BoxDev& b, unsigned id,
+                                             const double*& U, long long& ss, unsigned& sid) {
+  const unsigned px = (unsigned)b.px, pxy = px * (unsigned)b.py;
+  const unsigned pk = id / pxy, r = id - pk * pxy, pj = r / px;
+  int c[3] = {(int)(r - pj * px) - b.ng, (int)pj - b.ng, (int)pk - b.ng};
+  if ((unsigned)c[0] < (unsigned)b.n[0] && (unsigned)c[1] < (unsigned)b.n[1] &&
+      (unsigned)c[2] < (unsigned)b.n[2])
+    return;
+  const BoxDev* sb = &b;
+  if (A.gsrc == 1) {
+    for (int d = 0; d < 3; ++d) c[d] = ((c[d] % b.n[d]) + b.n[d]) % b.n[d];
+  } else {
+    const int gx = A.gg[0], gy = A.gg[1];
+    const int bq[3] = {b.gidx % gx, (b.gidx / gx) % gy, b.gidx / (gx * gy)};
+    int t[3];
+    for (int d = 0; d < 3; ++d) {
+      const int N = A.gg[d] * b.n[d];
+      const int X = ((bq[d] * b.n[d] + c[d]) % N + N) % N;
+      t[d] = X / b.n[d];
+      c[d] = X - t[d] * b.n[d];
+    }
+    sb = &A.gfull[(t[2] * gy + t[1]) * gx + t[0]];
+  }
+  U = A.Uin + sb->soff;
+  ss = sb->sstride;
+  sid = ((unsigned)(c[2] + sb->ng) * (unsigned)sb->py + (unsigned)(c[1] + sb->ng)) * (unsigned)sb->px +
+        (unsigned)(c[0] + sb->ng);
+}
+
 __device__ __forceinline__ void prim_body(const StepArgs& A, const Item& it) {
   Loc L = locate(A, kStPrim, kSpaceP, it);
   const BoxDev& b = *L.bd;
@@ -151,13 +185,16 @@ __device__ __forceinline__ void prim_body(const StepArgs& A, const Item& it) {
   if (L.idx < b.P) {
     const unsigned id = L.idx;
     const double* U = A.Uin + b.soff;
+    long long ss = b.sstride;
+    unsigned sid = id;  // the cell read for padded cell id
+    if (A.gsrc) ghost_source(A, b, id, U, ss, sid);
     const double ao = A.a_old;
-    double rho = ldu(U, id);
+    double rho = ldu(U, sid);
     if (rho < A.small_dens) { rho = A.small_dens; floors++; }
-    double u = ldu(U + b.sstride, id) / (ao * rho);
-    double v = ldu(U + 2 * b.sstride, id) / (ao * rho);
-    double w = ldu(U + 3 * b.sstride, id) / (ao * rho);
-    double re = ldu(U + 5 * b.sstride, id) / (ao * ao);
+    double u = ldu(U + ss, sid) / (ao * rho);
+    double v = ldu(U + 2 * ss, sid) / (ao * rho);
+    double w = ldu(U + 3 * ss, sid) / (ao * rho);
+    double re = ldu(U + 5 * ss, sid) / (ao * ao);
     double p = (A.gamma - 1.0) * re;
     if (p < A.small_pres) { p = A.small_pres; floors++; }
     double c = sqrt((A.gamma * p) / rho);

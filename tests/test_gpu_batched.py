@@ -296,3 +296,126 @@ def test_every_launch_order_gives_the_same_bits(nyx, prec, tmp_path):
     assert ms2 is None and tune2 == tune and plan2.tuning() == tune
     plan.close()
     plan2.close()
+
+
+def _periodic_parts(grid, n, ng, seed, a):
+    """A periodic domain of gx*gy*gz boxes of n cells (box order x fastest):
+    each box's padded state and gravity with its ghosts taken from the domain.
+    Smooth flow plus per-cell noise, so a ghost read from a wrong cell shows."""
+    gx, gy, gz = grid
+    NX, NY, NZ = gx * n[0], gy * n[1], gz * n[2]
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(NZ) / NZ, np.arange(NY) / NY, np.arange(NX) / NX, indexing="ij")
+    tw = 2 * np.pi
+    rho = 1.0 + 0.3 * np.sin(tw * (x + 2 * y)) * np.cos(tw * z) + 0.05 * rng.random(x.shape)
+    u = np.stack([0.4 * np.sin(tw * (y + z)), 0.3 * np.cos(tw * (x + z)), -0.2 * np.sin(tw * (x - y))])
+    u = u + 0.02 * rng.normal(size=u.shape)
+    p = 0.6 + 0.2 * np.cos(tw * (x + y + z)) + 0.05 * rng.random(x.shape)
+    pad = synth.pad_periodic(synth.conserved(rho, u, p, a), ng)
+    gpad = synth.pad_periodic(0.01 * rng.normal(size=(3, NZ, NY, NX)), ng)
+    parts = []
+    for bz in range(gz):
+        for by in range(gy):
+            for bx in range(gx):
+                sl = (slice(None), slice(bz * n[2], bz * n[2] + n[2] + 2 * ng),
+                      slice(by * n[1], by * n[1] + n[1] + 2 * ng), slice(bx * n[0], bx * n[0] + n[0] + 2 * ng))
+                parts.append((n, pad[sl].copy(), gpad[sl].copy()))
+    return parts
+
+
+def _lay_out(nyx, parts, ng, dx):
+    """Boxes at odd offsets with a different component stride each; the state
+    with every ghost cell NaN, the same with the ghosts filled, the gravity."""
+    boxes, spans = [], []
+    off = goff = 0
+    for b, (n, U, g) in enumerate(parts):
+        P = U[0].size
+        cs = P + 7 * b + 3
+        boxes.append(nyx.make_box(n, ng, dx, state_off=off + 5, grav_off=goff, comp_stride=cs))
+        spans.append((off + 5, cs))
+        off += 6 * cs + 11
+        goff += 3 * P
+    bare = np.zeros(off)
+    full = np.zeros(off)
+    for (o, cs), (n, U, g) in zip(spans, parts):
+        for c in range(6):
+            v = np.full(U[c].shape, np.nan)
+            v[ng:-ng, ng:-ng, ng:-ng] = U[c][ng:-ng, ng:-ng, ng:-ng]
+            bare[o + c * cs: o + c * cs + U[c].size] = v.ravel()
+            full[o + c * cs: o + c * cs + U[c].size] = U[c].ravel()
+    gflat = np.concatenate([g.ravel() for _, _, g in parts])
+    return boxes, spans, bare, full, gflat
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["tiled", "tiled_ng_eq_n", "own_periodic"])
+def test_step_takes_ghosts_from_their_sources(nyx, prec, case):
+    """A plan told where the input's ghost cells come from (each box periodic,
+    or the neighbouring box of a tiling grid) never reads them: stepping an
+    input whose ghosts are NaN gives, in every launch mode, the bits of
+    stepping it after the same-level ghost fill, leaves the input as it was,
+    and in FP64 equals the oracle box by box."""
+    import torch
+    a0, a1, dx = 0.25, 0.2505, 1 / 64
+    if case == "tiled":
+        grid, mode, parts = (3, 2, 2), 1, _periodic_parts((3, 2, 2), (10, 6, 8), NG, 71, a0)
+    elif case == "tiled_ng_eq_n":
+        grid, mode, parts = (2, 2, 2), 1, _periodic_parts((2, 2, 2), (4, 4, 4), NG, 72, a0)
+    else:
+        grid, mode = (1, 1, 1), 0
+        parts = [p for s, n in enumerate(SHAPES[:4]) for p in _periodic_parts((1, 1, 1), n, NG, 80 + s, a0)]
+    prm = nyx.default_params(precision=nyx.NYX_FP64 if prec == "fp64" else nyx.NYX_MIXED)
+    boxes, spans, bare, full, gflat = _lay_out(nyx, parts, NG, dx)
+    _, one = nyx.Batch.workspace_bytes(prm, boxes)
+    plan = nyx.Batch(prm, boxes, aligned_ws(one))
+    G = to_dev(gflat, torch.float64 if prec == "fp64" else torch.float32)
+    filled = to_dev(bare)
+    plan.fill_ghosts(filled, mode=mode, grid=grid)
+    torch.cuda.synchronize()
+    assert np.array_equal(filled.cpu().numpy(), full)
+    dt = torch.zeros(len(boxes), dtype=torch.float64, device="cuda")
+    plan.estimate_dt(filled, a0, 0.5, dt)
+    Ui = to_dev(bare)
+    outs = {}
+    for lm in (nyx.NYX_LAUNCH_STAGED, nyx.NYX_LAUNCH_FUSED, nyx.NYX_LAUNCH_PERSISTENT):
+        plan.set_launch_mode(lm)
+        ref = torch.zeros_like(Ui)
+        got = torch.zeros_like(Ui)
+        plan.set_ghost_source(-1)
+        plan.step(filled, G, dt, a0, a1, ref)
+        plan.set_ghost_source(mode, grid)
+        plan.step(Ui, G, dt, a0, a1, got)
+        plan.set_ghost_source(-1)
+        torch.cuda.synchronize()
+        r, g = ref.cpu().numpy(), got.cpu().numpy()
+        assert np.isfinite(r).all()
+        assert np.array_equal(r, g), lm
+        outs[lm] = g
+    assert np.array_equal(Ui.cpu().numpy(), bare, equal_nan=True)
+    if prec == "fp64":
+        dts = dt.cpu().numpy()
+        got = outs[nyx.NYX_LAUNCH_STAGED]
+        for b, ((o, cs), (n, U, gr)) in enumerate(zip(spans, parts)):
+            want, _ = oracle.hydro_step(U, gr, NG, float(dts[b]), dx, a0, a1)
+            v = np.stack([got[o + c * cs: o + c * cs + U[c].size].reshape(U[c].shape) for c in range(6)])
+            assert np.array_equal(v[:, NG:-NG, NG:-NG, NG:-NG], want[:, NG:-NG, NG:-NG, NG:-NG]), b
+    plan.close()
+
+
+def test_set_ghost_source_rejects_bad_shapes(nyx):
+    prm = nyx.default_params()
+    boxes = [nyx.make_box((8, 8, 8), NG, 1 / 16, state_off=6 * 16 ** 3 * b, grav_off=3 * 16 ** 3 * b)
+             for b in range(4)]
+    _, one = nyx.Batch.workspace_bytes(prm, boxes)
+    plan = nyx.Batch(prm, boxes, aligned_ws(one))
+    for mode, grid in ((1, (2, 2, 2)), (1, (4, 1, 0)), (1, (3, 1, 1))):
+        with pytest.raises(nyx.NyxError):
+            plan.set_ghost_source(mode, grid)
+    for mode in (-2, 2):
+        with pytest.raises(nyx.NyxError):
+            plan.set_ghost_source(mode, (1, 1, 1))
+    plan.set_ghost_source(1, (4, 1, 1))
+    plan.set_ghost_source(1, (1, 2, 2))
+    plan.set_ghost_source(0)
+    plan.set_ghost_source(-1)
+    plan.close()
