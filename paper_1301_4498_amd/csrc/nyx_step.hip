@@ -841,6 +841,8 @@ __device__ __forceinline__ RiemannOut lin_solve(const StepArgs& A, const double*
 // the root of u*_R - u*_L by about that much, the size of the FP32 rounding of
 // the stored Godunov state, and lies far below a stopping step of 2^-20 or
 // more; tighter stopping rules take the refined w_K.
+// true where the stopping step lies far enough above the raw estimates'
+// error for the iteration to use them (see ts_iterate)
 __host__ __device__ __forceinline__ bool raw_stop(const StepArgs& A) { return A.mixed_stop >= 0x1p-20; }
 template <bool RAW>
 __device__ __forceinline__ double ts_iterate(const StepArgs& A, const TwoShock& t, double p,
@@ -2048,6 +2050,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
   if (a.fuse_final && !learned(2) && !a.harvest) {
     // riem2 and update as one launch; its time is stage 6's, stage 7's is 0
 #if defined(NYX_PREC_MIXED)
+    // the instantiation whose Newton loop matches the stopping rule
     if (raw_stop(a)) hipLaunchKernelGGL(k_final<1>, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
     else hipLaunchKernelGGL(k_final<2>, dim3(a.nblocks[kSpaceT]), dim3(kFinBlock), 0, s, a);
 #else
