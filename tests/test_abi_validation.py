@@ -145,6 +145,10 @@ def test_batch_argument_errors(nyx):
     # a workspace smaller than the largest box is rejected before any upload
     assert L.nyx_batch_create(ctypes.byref(p), 2, good, 0x40000000, 4096, None, ctypes.byref(h)) == -7
     assert L.nyx_hydro_step_batched(None, 1, 1, 1, 0.5, 0.5, 2, None, None, None) == -1
+    # a plan is required before any ghost-source mode is looked at
+    for mode in (-1, 0, 1, 5):
+        assert L.nyx_batch_set_ghost_source(None, mode, 1, 1, 1) == -1
+    assert L.nyx_batch_fill_ghosts(None, 0, 1, 1, 1, 0x10000000, None) == -1
 
 
 def test_level_fill_planning_errors(nyx):
