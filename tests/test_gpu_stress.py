@@ -12,7 +12,9 @@ patches stay within 1e-5 relative L1.  At full size (512^3, in the benchmark's
 launch configurations: FP64 as one box, FP32-mixed as an 8^3 grid of 64^3
 patches, each in the staged and in the fused-final launch mode, which must
 agree bit for bit) sampled 8^3 windows are checked against the oracle, which
-computes each window as a box of its own.  Single faces of the FP32-mixed Riemann
+computes each window as a box of its own; with the ghost exchange inside the
+step (the benchmark's configuration: input ghost cells NaN, read from their
+sources) both forms give the bits of the filled input.  Single faces of the FP32-mixed Riemann
 solver on these fields match the oracle's two-shock solution of the same
 states to 2e-6 plus the spread that storing those states in FP32 causes."""
 import numpy as np
@@ -122,6 +124,17 @@ CORNERS = [(0, 0, 0), (NF - WIN, NF - WIN, NF - WIN), (60, 0, 250), (64 - 4, 128
            (301, 77, NF - WIN), (447, 511 - WIN, 3)]
 
 
+def _poison_ghosts(t):
+    """NaN into every ghost cell of boxes viewed as (nbox, ncomp, pz, py, px)."""
+    nan = float("nan")
+    t[:, :, :NG] = nan
+    t[:, :, -NG:] = nan
+    t[:, :, :, :NG] = nan
+    t[:, :, :, -NG:] = nan
+    t[:, :, :, :, :NG] = nan
+    t[:, :, :, :, -NG:] = nan
+
+
 def _window(f, x0, y0, z0):
     s = f[:, z0:z0 + WIN + 2 * NG, y0:y0 + WIN + 2 * NG, x0:x0 + WIN + 2 * NG]
     return np.ascontiguousarray(s.cpu().numpy())
@@ -148,6 +161,15 @@ def test_full_size_stress_sampled_windows(nyx):
     plan.set_launch_mode(nyx.NYX_LAUNCH_STAGED)
     plan.step(state, grav, dt, a0, a1, out)
     assert bool((out.view(torch.int64).sum() == fused_sum).item())
+    # the box's ghost cells read from their periodic images inside the step
+    nan_in = state.clone()
+    _poison_ghosts(nan_in.view(1, 6, NF + 2 * NG, NF + 2 * NG, NF + 2 * NG))
+    out2 = torch.empty_like(state)
+    plan.set_ghost_source(0)
+    plan.step(nan_in, grav, dt, a0, a1, out2)
+    V = (slice(None), slice(NG, -NG), slice(NG, -NG), slice(NG, -NG))
+    assert torch.equal(out2[V], out[V])
+    del nan_in, out2
     torch.cuda.synchronize()
     dtv = float(dt.item())
     plan.close()
@@ -181,6 +203,16 @@ def test_full_size_stress_sampled_windows(nyx):
     assert torch.equal(staged, B)
     del staged
     mixed = synth.join_valid(B, g8, (m, m, m))
+    # the patches' ghost cells read from the neighbouring patches inside the
+    # step (fused mode, as the benchmark times it)
+    An = A.clone()
+    _poison_ghosts(An.view(512, 6, m + 2 * NG, m + 2 * NG, m + 2 * NG))
+    C = torch.empty_like(A)
+    plan.set_ghost_source(1, g8)
+    plan.step(An, G, dts, a0, a1, C)
+    torch.cuda.synchronize()
+    assert torch.equal(synth.join_valid(C, g8, (m, m, m)), mixed)
+    del An, C
     gotm = {c: mixed[:, c[2]:c[2] + WIN, c[1]:c[1] + WIN, c[0]:c[0] + WIN].cpu().numpy()
             for c in CORNERS}
     plan.close()
