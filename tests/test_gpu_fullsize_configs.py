@@ -4,7 +4,10 @@ configuration bench.py times (batched plans, device-resident dt, autotuned
 launch orders).
 
 Launch orders and (where bench.py chooses one) the launch mode come from the
-plan's autotuners, as in bench.py.
+plan's autotuners, as in bench.py, and every plan reads the ghost cells from
+their periodic images inside the step, as bench.py does: the inputs' ghost
+cells are NaN here, and after the steps exactly those values are still NaN
+(no ghost cell read into a valid one, none written).
 
   * 4096-box level (edges from {16, 24, 32, 48, 64}): FP64 for 2 steps with
     per-box dt, then FP32-mixed with that dt sequence; 20 sampled boxes (4
@@ -49,6 +52,22 @@ def _threads():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
+def _poison_ghosts(buf, shapes, soffs):
+    """NaN into every ghost cell of the boxes (shapes n, state offsets) of a
+    flat state buffer; returns how many values were set."""
+    nan, count = float("nan"), 0
+    for n, so in zip(shapes, soffs):
+        px, py, pz = (n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG)
+        v = buf[so:so + 6 * px * py * pz].view(6, pz, py, px)
+        for sl in ((slice(None), slice(None, NG)), (slice(None), slice(-NG, None)),
+                   (slice(None), slice(None), slice(None, NG)), (slice(None), slice(None), slice(-NG, None)),
+                   (slice(None), slice(None), slice(None), slice(None, NG)),
+                   (slice(None), slice(None), slice(None), slice(-NG, None))):
+            v[sl] = nan
+        count += 6 * (px * py * pz - n[0] * n[1] * n[2])
+    return count
+
+
 def test_level4096_sampled_boxes_against_oracle(nyx):
     import torch
     shapes = synth.config3_shapes()
@@ -84,7 +103,13 @@ def test_level4096_sampled_boxes_against_oracle(nyx):
         plan = nyx.Batch(prm, boxes, aligned_ws(wsb))
         if prec == "mixed":
             assert plan.num_groups == 1
-        bufs = [state.clone(), torch.empty_like(state)]
+        # as bench.py steps it: every box its own periodic domain, the ghost
+        # cells read from their images inside the step (here NaN in both
+        # buffers, and never written)
+        plan.set_ghost_source(0)
+        bufs = [state.clone(), state.clone()]
+        nghost = _poison_ghosts(bufs[0], shapes, [o[0] for o in offs])
+        _poison_ghosts(bufs[1], shapes, [o[0] for o in offs])
         if prec == "fp64":
             plan.estimate_dt(bufs[0], a[0], 0.5, dt_seq[0])
         plan.autotune(bufs[0], G, dt_seq[0], a[0], a[1], bufs[1], reps=1)
@@ -96,10 +121,10 @@ def test_level4096_sampled_boxes_against_oracle(nyx):
         for k in range(steps):
             plan.step(bufs[k % 2], G, dt_seq[k], a[k], a[k + 1], bufs[(k + 1) % 2],
                       dt_next=dt_seq[k + 1] if prec == "fp64" else None)
-            plan.fill_ghosts(bufs[(k + 1) % 2])
         torch.cuda.synchronize()
         fin = bufs[steps % 2]
-        assert bool(torch.isfinite(fin).all())
+        assert int(torch.isnan(fin).sum().item()) == nghost
+        assert int((~torch.isfinite(fin)).sum().item()) == nghost
         results[prec] = {b: host_box(fin, b, 6) for b in pick}
         plan.close()
         del plan, bufs, G, fin  # the plan object holds its workspace
@@ -153,8 +178,13 @@ def test_box256_ten_steps_windows(nyx):
         p = nyx.default_params(precision=nyx.NYX_FP64 if prec == "fp64" else nyx.NYX_MIXED)
         _, one = nyx.Batch.workspace_bytes(p, [box])
         plan = nyx.Batch(p, [box], aligned_ws(one))
+        # as bench.py steps it: ghost cells read from their periodic images
+        # inside the step (here NaN, and never written)
+        plan.set_ghost_source(0)
         U = [to_dev(w.state), None]
-        U[1] = torch.empty_like(U[0])
+        U[1] = U[0].clone()
+        nghost = _poison_ghosts(U[0].view(-1), [w.n], [0])
+        _poison_ghosts(U[1].view(-1), [w.n], [0])
         G = to_dev(w.grav, torch.float64 if prec == "fp64" else torch.float32)
         if prec == "fp64":
             plan.estimate_dt(U[0], w.a0, 0.5, dts[0:1])
@@ -165,9 +195,9 @@ def test_box256_ten_steps_windows(nyx):
         for k in range(steps):
             plan.step(U[k % 2], G, dts[k:k + 1], a[k], a[k + 1], U[(k + 1) % 2],
                       dt_next=dts[k + 1:k + 2] if prec == "fp64" else None)
-            plan.fill_ghosts(U[(k + 1) % 2])
         torch.cuda.synchronize()
         out[prec] = U[steps % 2].cpu().numpy()
+        assert int(np.isnan(out[prec]).sum()) == nghost
         plan.close()
         del U, G
     dtl = dts.cpu().tolist()
@@ -219,8 +249,11 @@ def test_learned_flux_fresh_256_box_twenty_steps(nyx):
                       ("learned", learn.learned_params(f, tol=1e-3, stages=7))):
         _, one = nyx.Batch.workspace_bytes(prm, [box])
         plan = nyx.Batch(prm, [box], aligned_ws(one))
+        plan.set_ghost_source(0)  # as bench.py steps it
         U = [to_dev(w.state), None]
-        U[1] = torch.empty_like(U[0])
+        U[1] = U[0].clone()
+        _poison_ghosts(U[0].view(-1), [w.n], [0])
+        _poison_ghosts(U[1].view(-1), [w.n], [0])
         G = to_dev(w.grav, torch.float32)
         dts = torch.zeros(2, dtype=torch.float64, device="cuda")
         st = torch.zeros(10, dtype=torch.int64, device="cuda")
@@ -228,7 +261,6 @@ def test_learned_flux_fresh_256_box_twenty_steps(nyx):
         for k in range(w.steps):
             plan.step(U[k % 2], G, dts[k % 2:k % 2 + 1], w.a_at(k), w.a_at(k + 1),
                       U[(k + 1) % 2], dt_next=dts[(k + 1) % 2:(k + 1) % 2 + 1], stats=st)
-            plan.fill_ghosts(U[(k + 1) % 2])
         torch.cuda.synchronize()
         res[name] = (U[w.steps % 2][0, NG:-NG, NG:-NG, NG:-NG].cpu().numpy(), nyx.stats_dict(st))
         plan.close()
